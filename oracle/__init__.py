@@ -1,0 +1,167 @@
+"""CPU oracle for the per-stream generators and the checkerboard Ising update.
+
+TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the CPU-baseline
+leg of the benchmark import this package; the product package
+(`paper_1204_6193_amd`) never does, and this package imports nothing from it.
+The arithmetic lives in plain C (`rng_oracle.c`, built to `liborc.so` with gcc)
+and in `exact_ising.py` (high-precision exact finite-lattice values); this
+module only marshals numpy buffers.
+
+Kinds are named by string so that the oracle does not depend on the product's
+enum values: "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborc.so")
+SOURCES = [os.path.join(HERE, "rng_oracle.c")]
+
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w"]
+_CODE = {k: i + 1 for i, k in enumerate(KINDS)}
+OUT_U32, OUT_F32, OUT_XOR = 0, 1, 2
+
+
+def build() -> str:
+    """Compile the C oracle with gcc (always recompiles)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", *SOURCES, "-o", LIB_PATH, "-lm"]
+    subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    """Load liborc.so, building it first only if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        u64, i32, vp = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
+        L.orc_mix64.restype = u64
+        L.orc_mix64.argtypes = [u64]
+        L.orc_splitmix.restype = u64
+        L.orc_splitmix.argtypes = [u64, u64]
+        L.orc_state_bytes.restype = ctypes.c_size_t
+        L.orc_state_bytes.argtypes = [i32, u64]
+        L.orc_seed.restype = i32
+        L.orc_seed.argtypes = [i32, u64, u64, vp]
+        L.orc_generate.restype = i32
+        L.orc_generate.argtypes = [i32, u64, vp, u64, u64, u64, i32, vp]
+        L.orc_step_n.restype = i32
+        L.orc_step_n.argtypes = [i32, u64, vp, u64, u64, u64]
+        L.orc_jump.restype = i32
+        L.orc_jump.argtypes = [i32, u64, vp, u64, u64, vp, i32]
+        L.orc_ising_threshold.restype = u64
+        L.orc_ising_threshold.argtypes = [ctypes.c_double, i32]
+        L.orc_ising_hot_start.restype = i32
+        L.orc_ising_hot_start.argtypes = [ctypes.c_uint32, u64, vp]
+        L.orc_ising_energy.restype = ctypes.c_int32
+        L.orc_ising_energy.argtypes = [ctypes.c_uint32, vp]
+        L.orc_ising_sweeps.restype = i32
+        L.orc_ising_sweeps.argtypes = [ctypes.c_uint32, i32, ctypes.c_double, vp, vp, u64, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def code(kind: str) -> int:
+    return _CODE[kind]
+
+
+def mix64(z: int) -> int:
+    return int(lib().orc_mix64(z))
+
+
+def splitmix(seed: int, k: int) -> int:
+    """SM(k) = mix64(seed + k * gamma)."""
+    return int(lib().orc_splitmix(seed, k))
+
+
+def state_bytes(kind: str, S: int) -> int:
+    return int(lib().orc_state_bytes(_CODE[kind], S))
+
+
+def seed(kind: str, S: int, seed_: int) -> np.ndarray:
+    """Canonical state image (uint8) of S freshly seeded streams."""
+    st = np.zeros(state_bytes(kind, S), dtype=np.uint8)
+    _check(lib().orc_seed(_CODE[kind], S, seed_, _ptr(st)), "seed")
+    return st
+
+
+def generate(kind: str, S: int, st: np.ndarray, count: int, lo: int = 0, hi: int | None = None,
+             mode: int = OUT_U32) -> np.ndarray:
+    """`count` outputs of streams [lo, hi); advances `st` in place.
+
+    U32/F32: array [count, hi-lo] (out[k, s-lo] is output k of stream s).
+    XOR: array [hi-lo] with the XOR of each stream's outputs.
+    """
+    hi = S if hi is None else hi
+    w = hi - lo
+    if mode == OUT_XOR:
+        out = np.zeros(w, dtype=np.uint32)
+    else:
+        out = np.zeros((count, w), dtype=np.float32 if mode == OUT_F32 else np.uint32)
+    _check(lib().orc_generate(_CODE[kind], S, _ptr(st), lo, hi, count, mode, _ptr(out)), "generate")
+    return out
+
+
+def step_n(kind: str, S: int, st: np.ndarray, n: int, lo: int = 0, hi: int | None = None):
+    hi = S if hi is None else hi
+    _check(lib().orc_step_n(_CODE[kind], S, _ptr(st), lo, hi, n), "step_n")
+
+
+def _words(n: int) -> np.ndarray:
+    nw = max(1, (n.bit_length() + 63) // 64)
+    return np.array([(n >> (64 * i)) & ((1 << 64) - 1) for i in range(nw)], dtype=np.uint64)
+
+
+def jump(kind: str, S: int, st: np.ndarray, n: int, lo: int = 0, hi: int | None = None):
+    """Advance streams [lo, hi) by n outputs (n may exceed 2^64)."""
+    hi = S if hi is None else hi
+    w = _words(n)
+    _check(lib().orc_jump(_CODE[kind], S, _ptr(st), lo, hi, _ptr(w), len(w)), "jump")
+
+
+def ising_threshold(beta: float, dE: int) -> int:
+    return int(lib().orc_ising_threshold(beta, dE))
+
+
+def ising_hot_start(L: int, seed_: int) -> np.ndarray:
+    sp = np.zeros(L * L, dtype=np.int8)
+    _check(lib().orc_ising_hot_start(L, seed_, _ptr(sp)), "hot start")
+    return sp
+
+
+def ising_energy(L: int, spins: np.ndarray) -> int:
+    return int(lib().orc_ising_energy(L, _ptr(np.ascontiguousarray(spins, dtype=np.int8))))
+
+
+def ising_sweeps(L: int, kind: str, beta: float, st: np.ndarray, spins: np.ndarray, n_sweeps: int,
+                 trace: bool = True):
+    """Run n_sweeps checkerboard sweeps in place; returns the energy trace (int32) or None."""
+    tr = np.zeros(max(n_sweeps, 1), dtype=np.int32) if trace else None
+    _check(lib().orc_ising_sweeps(L, _CODE[kind], beta, _ptr(st), _ptr(spins), n_sweeps,
+                                  _ptr(tr) if trace else None), "ising sweeps")
+    return tr[:n_sweeps] if trace else None
+
+
+def ising_create(L: int, kind: str, seed_: int):
+    """Hot-started lattice and its S = L*L/4 freshly seeded streams."""
+    return ising_hot_start(L, seed_), seed(kind, L * L // 4, seed_)
