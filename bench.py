@@ -1,0 +1,221 @@
+"""Benchmark of the per-stream generator hot path on one MI355X.
+
+Headline (one JSON line): bulk fill with the paper's XORShift-1024/Weyl
+generator, 2^20 streams x 4096 uint32 outputs per step (16 GiB written per
+step), inputs (generator state) resident in HBM, in Gsamples/s.  One step is
+one rng_fill_u32 call = one kernel launch; it is timed with HIP events on the
+stream the kernel runs on.
+
+The same line carries, under "parts", every generator's u32 fill, FP32 fill,
+consume-only rate and jump-ahead time at the same size, a plain write
+kernel's ceiling, and checkerboard-Ising throughput at L = 4096 in flips/ns;
+"roofline" for the dominant kernel and "cpu_baseline" for the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+S_FULL, COUNT_FULL = 1 << 20, 4096
+KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10"]
+# state bytes read + written once per launch, per stream
+STATE_BYTES = {"lcg32": 4, "lcg64": 8, "mwc": 8, "xorwow": 24, "philox4x32_10": 16, "xs1024w": 4 + 8 / 32}
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "xs1024w_fill_u32_2p20x4096_traffic.json")
+KERNEL_SOURCES = ["paper_1204_6193_amd/csrc/gen.hip", "paper_1204_6193_amd/csrc/rngx_internal.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def time_launches(fn, steps, warmup):
+    """Per-launch durations (ms) from HIP events on torch's current stream,
+    which is the stream every call below launches on."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in evs], wall
+
+
+def bench_fill(rx, kind, mode, out, steps, warmup):
+    import torch
+    g = rx.rng_create(kind, S_FULL, 1)
+    if mode == "u32":
+        fn = lambda: rx.rng_fill_u32(g, out, COUNT_FULL)
+    elif mode == "f32":
+        fo = out.view(torch.float32)
+        fn = lambda: rx.rng_fill_f32(g, fo, COUNT_FULL)
+    else:
+        acc = torch.empty(S_FULL, dtype=torch.int32, device="cuda")
+        fn = lambda: rx.rng_consume(g, acc, COUNT_FULL)
+    durs, _ = time_launches(fn, steps, warmup)
+    ms = sum(durs) / len(durs)
+    samples = S_FULL * COUNT_FULL
+    out_bytes = samples * 4 if mode != "consume" else S_FULL * 4
+    alg_bytes = out_bytes + 2 * STATE_BYTES[kind] * S_FULL
+    return {"ms": round(ms, 4), "gsamples_s": round(samples / ms / 1e6, 2),
+            "gbs": round(alg_bytes / ms / 1e6, 1), "hbm_frac": round(alg_bytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "ms_min": round(min(durs), 4)}
+
+
+def bench_write_ceiling(out, steps, warmup):
+    durs, _ = time_launches(lambda: out.fill_(7), steps, warmup)
+    ms = sum(durs) / len(durs)
+    return {"ms": round(ms, 4), "gbs": round(out.numel() * 4 / ms / 1e6, 1)}
+
+
+def bench_skip(rx, kind, reps=5):
+    g = rx.rng_create(kind, S_FULL, 1)
+    durs, _ = time_launches(lambda: rx.rng_skip(g, (1 << 40) + 12345), reps, 1)
+    return round(sum(durs) / len(durs), 4)
+
+
+def bench_ising(rx, kind, L, sweeps, beta=0.4):
+    import torch
+    lat = rx.ising_create(L, kind, 1)
+    rx.ising_sweep(lat, beta, 5)
+    tr = torch.zeros(sweeps, dtype=torch.int32, device="cuda")
+    durs, _ = time_launches(lambda: rx.ising_sweep(lat, beta, sweeps, tr), 1, 0)
+    ms = durs[0]
+    return {"sweeps": sweeps, "ms": round(ms, 3), "flips_per_ns": round(L * L * sweeps / (ms * 1e6), 2)}
+
+
+def traffic_from_profile():
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    only while the kernel sources are the ones it was taken from."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(target_s: float = 10.0):
+    """The CPU oracle (never tuned) on a bounded sample of the same workload:
+    XS1024W u32 fill of all 2^20 streams, the first n outputs of each (n sized
+    for about target_s seconds of wall time), streams split over host
+    threads, each thread producing its block 64 outputs per oracle call."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    S = S_FULL
+    st = oracle.seed("xs1024w", S, 1)
+    t = time.perf_counter()
+    oracle.generate("xs1024w", S, st.copy(), 64, lo=0, hi=32 * 256)
+    rate1 = 32 * 256 * 64 / (time.perf_counter() - t)  # values/s on one thread
+    n = max(64, int(rate1 * threads * target_s / S) // 64 * 64)
+    chunk = S // threads
+
+    def work(i):
+        lo, hi = i * chunk, (i + 1) * chunk
+        for _ in range(n // 64):
+            oracle.generate("xs1024w", S, st, 64, lo=lo, hi=hi)
+
+    t = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(work, range(threads)))
+    dt = time.perf_counter() - t
+    return {"value": round(S * n / dt / 1e9, 4), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
+            "sample": f"xs1024w u32 fill of {S} streams x first {n} outputs ({S * n} values, {dt:.1f} s wall, "
+                      f"{threads} threads over stream blocks)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--parts", default="all", help="all | none: per-kind parts and Ising")
+    ap.add_argument("--ising-sweeps", type=int, default=10000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent streams shard by index range with no communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1204_6193_amd as rx
+    rx.load()
+    torch.cuda.set_device(0)
+    out = torch.empty(S_FULL * COUNT_FULL, dtype=torch.int32, device="cuda")
+
+    head = bench_fill(rx, "xs1024w", "u32", out, args.steps, args.warmup)
+    print(f"# headline xs1024w u32 fill: {head}", file=sys.stderr, flush=True)
+    parts = {}
+    if not args.only_headline and args.parts == "all":
+        parts["write_ceiling"] = bench_write_ceiling(out, max(5, args.steps // 2), 2)
+        print(f"# write ceiling {parts['write_ceiling']}", file=sys.stderr, flush=True)
+        for kind in KINDS:
+            rec = {}
+            for mode in ("u32", "f32", "consume"):
+                rec[mode] = bench_fill(rx, kind, mode, out, max(5, args.steps // 2), 2)
+            rec["skip_2p40_ms"] = bench_skip(rx, kind)
+            parts[kind] = rec
+            print(f"# {kind}: {rec}", file=sys.stderr, flush=True)
+        del out
+        torch.cuda.empty_cache()
+        ising = {}
+        for kind in KINDS:
+            sweeps = args.ising_sweeps if kind == "xs1024w" else max(100, args.ising_sweeps // 10)
+            ising[kind] = bench_ising(rx, kind, 4096, sweeps)
+            print(f"# ising L=4096 {kind}: {ising[kind]}", file=sys.stderr, flush=True)
+        parts["ising_L4096_beta0.4"] = ising
+
+    samples = S_FULL * COUNT_FULL
+    alg_bytes = samples * 4 + 2 * STATE_BYTES["xs1024w"] * S_FULL
+    achieved = alg_bytes / head["ms"] / 1e6
+    line = {
+        "metric": "RNG Gsamples/s (% HBM peak) per generator; Ising Metropolis flips/ns at L=4096",
+        "value": head["gsamples_s"],
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "xs1024w bulk fill, uint32, interleaved out[k*S+s]", "n_streams": S_FULL,
+                   "outputs_per_stream": COUNT_FULL, "seed": 1, "generator": "XORShift-1024 + Weyl (paper's)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile()},
+        "kernel_hash": kernel_hash(),
+    }
+    if parts:
+        line["parts"] = parts
+    if not args.no_cpu and not args.only_headline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * rngx -- many independent per-thread random-number streams and their use in
+ * a checkerboard Metropolis update of the 2D Ising ferromagnet, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Manssen, Weigel & Hartmann, "Random number
+ * generators for massively parallel simulations on GPU" (arXiv:1204.6193):
+ * thousands to millions of generator instances, one per updating unit, each
+ * delivering its own stream (Introduction), with generator state kept in
+ * fast on-chip storage during a launch and moved to and from device memory
+ * once (Introduction; LCG section on state loads per Ising tile visit).
+ *
+ * General conventions
+ *   - Plain C ABI.  Device pointers ("d_" prefix) are addresses in the
+ *     memory of the device the handle was created on; host pointers are
+ *     ordinary process memory.  `stream` is a hipStream_t passed as void*
+ *     (NULL = the default stream).
+ *   - Every call validates all arguments before it touches the device.  On
+ *     any error nothing is modified and the call returns a negative status;
+ *     rngx_last_error() gives a description (per calling thread).
+ *   - Calls that take a stream only enqueue work on it and return; results
+ *     are ready when the stream reaches that point.  Calls without a stream
+ *     argument are synchronous.  A handle must not be used from two host
+ *     threads at once, nor by two streams whose work overlaps.
+ *   - Output buffers belong to the caller, must be 16-byte aligned and hold
+ *     the stated number of elements; the library owns generator state and
+ *     lattices (allocated by *_create, released by *_destroy).
+ *
+ * Streams and outputs
+ *   - Stream s of a generator created with (kind, n_streams = S, seed)
+ *     produces outputs u_0, u_1, ... (32-bit).  Every recursive generator
+ *     steps first and then outputs.
+ *   - Uniform fills write output k of stream s to out[k*S + s] (the paper's
+ *     "warp order" for one XORShift-1024 instance; the interleaved sub-stream
+ *     order for LCGs), k < count_per_stream.
+ *   - FP32 uniforms are f = (u >> 8) * 2^-24, exact, in [0, 1).
+ *   - XS1024W: a stream is one 32-bit lane of a 1024-bit instance; stream s
+ *     is lane s % 32 of instance s / 32, so S must be a multiple of 32.
+ *
+ * Seeding (the paper seeds instances "with another RNG"; the exact indices
+ * are this library's definition), with SM(k) = splitmix64 output k of
+ * `seed`, i.e. mix64(seed + k * 0x9E3779B97F4A7C15):
+ *   LCG32    x = low32(SM(1+s))            LCG64  x = SM(1+s)
+ *   MWC      x = low32(SM(1+s)), carry = high32(SM(1+s)) mod (a-1), x = 1 if both 0
+ *   XORWOW   (x,y) (z,w) (v,d) = low/high words of SM(1+3s), SM(2+3s), SM(3+3s);
+ *            x = 1 if x..v are all 0
+ *   PHILOX   key = (low32, high32) of SM(1+s), position 0
+ *   XS1024W  word i of instance g = low32 (i even) / high32 (i odd) of
+ *            SM(1 + 16 g + i/2); Weyl seed y0 = high32(SM(0)) shared by all
+ *            instances; step counter 0
+ *
+ * Checkpoint image (rng_get_state / rng_set_state), little-endian,
+ * structure of arrays:
+ *   LCG32    u32 x[S]                    LCG64   u64 x[S]
+ *   MWC      u64 y[S], y = carry << 32 | x
+ *   XORWOW   u32 x[S] y[S] z[S] w[S] v[S] d[S]
+ *   PHILOX   u32 k0[S] k1[S] u64 pos[S]  (pos = outputs consumed)
+ *   XS1024W  u32 W[S] (W[32g+i] = word i of instance g, word 0 most
+ *            significant) u64 n[S/32] (steps taken) u32 y0
+ */
+#ifndef RNGX_H
+#define RNGX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RNGX_LCG32 = 1,         /* x <- 1664525 x + 1013904223 mod 2^32; out x          (LCG section)  */
+    RNGX_LCG64 = 2,         /* x <- a x + c mod 2^64 (a, c of the LCG section); out x >> 32        */
+    RNGX_MWC = 3,           /* lag-1 multiply-with-carry, base 2^32, a = 4294967118; out x (MWC sec.) */
+    RNGX_XORWOW = 4,        /* 160-bit xorshift (2,1,4) + Weyl d += 362437; out d + v (XORShift sec.) */
+    RNGX_PHILOX4X32_10 = 5, /* counter-based Philox4x32, 10 rounds (counter-based section)         */
+    RNGX_XS1024W = 6        /* the paper's XORShift-1024 (329,347,344) + Weyl (XORShift section)    */
+} rngx_kind;
+
+typedef enum {
+    RNGX_OK = 0,
+    RNGX_E_INVALID = -1,  /* bad kind, null pointer, zero size, bad beta, unknown handle        */
+    RNGX_E_ALIGN = -2,    /* S % 32 != 0 for XS1024W; L % 16 != 0 or L < 16; unaligned buffer  */
+    RNGX_E_NOMEM = -3,    /* device allocation failed                                          */
+    RNGX_E_HIP = -4,      /* a HIP runtime call failed                                         */
+    RNGX_E_OVERFLOW = -5, /* element or byte counts overflow 64 bits                           */
+    RNGX_E_STATE = -6,    /* a state image holds a fixed point of the generator or bad size    */
+    RNGX_E_BUSY = -7      /* resource temporarily unavailable                                  */
+} rngx_status;
+
+typedef struct rngx_gen_s *rngx_gen;     /* opaque; owns the device state of S streams      */
+typedef struct rngx_ising_s *rngx_ising; /* opaque; owns L*L int8 spins and L*L/4 streams    */
+
+/* Create S = n_streams streams of `kind` seeded from `seed` as above, on the
+ * current device.  Seeding runs on the device; the call returns when it is
+ * done.  *out receives the handle.  Errors: RNGX_E_INVALID (kind, S = 0,
+ * out NULL), RNGX_E_ALIGN (XS1024W with S % 32 != 0), RNGX_E_OVERFLOW
+ * (S > 2^36), RNGX_E_NOMEM.  (No XS1024W instance can be seeded all-zero:
+ * at most one of its 16 distinct splitmix64 words is 0.) */
+rngx_status rng_create(rngx_kind kind, uint64_t n_streams, uint64_t seed, rngx_gen *out);
+
+/* Release the handle and its device memory (waits for the device first). */
+rngx_status rng_destroy(rngx_gen g);
+
+/* Kind and stream count of a handle; either output pointer may be NULL. */
+rngx_status rng_info(rngx_gen g, rngx_kind *kind, uint64_t *n_streams);
+
+/* Write the next count_per_stream outputs of every stream to the device
+ * buffer d_out (S * count_per_stream u32 elements, out[k*S + s]) and advance
+ * every stream by count_per_stream.  count 0 is a no-op.  Errors:
+ * RNGX_E_INVALID, RNGX_E_ALIGN (d_out not 16-byte aligned),
+ * RNGX_E_OVERFLOW (S * count * 4 bytes overflows). */
+rngx_status rng_fill_u32(rngx_gen g, uint32_t *d_out, uint64_t count_per_stream, void *stream);
+
+/* As rng_fill_u32, writing f = (u >> 8) * 2^-24 as float. */
+rngx_status rng_fill_f32(rngx_gen g, float *d_out, uint64_t count_per_stream, void *stream);
+
+/* Generate count_per_stream outputs of every stream without storing them:
+ * d_xor[s] (S u32 elements) receives the XOR of stream s's outputs.  The
+ * numbers are produced exactly as by rng_fill_u32 and the streams advance
+ * the same way; this isolates generation from output bandwidth (the paper's
+ * Table 3 peak rates are measured without storing the numbers). */
+rngx_status rng_consume(rngx_gen g, uint32_t *d_xor, uint64_t count_per_stream, void *stream);
+
+/* Advance every stream by n outputs without producing them (jump-ahead):
+ * LCGs by the n-step affine map (eq. lcg_skipping), MWC by y <- a^n y mod
+ * (a 2^32 - 1), XORWOW and XS1024W by the n-th power of the GF(2)
+ * transition matrix of their xorshift part (the XORShift section's
+ * sub-stream seeding multiplies by such a power) plus n steps of the Weyl
+ * term, Philox by its counter.  The result equals producing and discarding
+ * n outputs. */
+rngx_status rng_skip(rngx_gen g, uint64_t n, void *stream);
+
+/* Copy the handle's state image (layout above) to host memory.  If host_buf
+ * is NULL only *bytes is set to the image size.  Otherwise *bytes must be at
+ * least that size; the call waits for `stream` and then copies. */
+rngx_status rng_get_state(rngx_gen g, void *host_buf, size_t *bytes, void *stream);
+
+/* Replace the handle's state by an image (layout above) of exactly the
+ * image size.  Images holding a fixed point (XS1024W all-zero instance,
+ * XORWOW all-zero xorshift words, MWC y = 0 or y >= a 2^32 - 1) are refused
+ * with RNGX_E_STATE.  The copy is ordered on `stream` and the host buffer
+ * may be reused when the call returns. */
+rngx_status rng_set_state(rngx_gen g, const void *host_buf, size_t bytes, void *stream);
+
+/* Create an L x L periodic Ising lattice (J = 1, h = 0; Sec. 2 application
+ * test) with int8 spins +-1 at y*L + x, hot-started: spin i = +1 iff bit 63
+ * of splitmix64 output i+1 of (seed ^ 0xD1B54A32D192ED03) is set.  It owns
+ * S = L*L/4 streams of `kind` seeded from `seed` as rng_create would; stream
+ * s = y*(L/4) + x/4 drives the four sites x0..x0+3 (x0 = 4*(x/4)) of row y.
+ * Synchronous.  Errors: RNGX_E_ALIGN unless L % 16 == 0 and L >= 16. */
+rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *out);
+
+/* Run n_sweeps checkerboard Metropolis sweeps at inverse temperature beta
+ * (finite, >= 0).  A sweep updates colour 0 (x+y even), then colour 1; in
+ * pass c stream s updates site x0 + ((c+y)&1) with its next output r and
+ * then site x0 + 2 + ((c+y)&1) with the following one.  A flip with energy
+ * change dE is accepted iff dE <= 0 or r < floor(exp(-beta dE) 2^32), the
+ * two thresholds (dE = 4, 8) being computed on the host in IEEE double.
+ * If d_energy_trace is not NULL, entry t (n_sweeps int32 elements) receives
+ * E = -sum s(x,y)[s(x+1,y) + s(x,y+1)] after sweep t. */
+rngx_status ising_sweep(rngx_ising lat, double beta, uint64_t n_sweeps, int32_t *d_energy_trace,
+                        void *stream);
+
+/* Borrow the device pointer of the spins (L*L int8, row-major).  The
+ * pointer stays valid until ising_destroy; writes through it are allowed
+ * (values must stay +-1) and are ordered by the caller's streams. */
+rngx_status ising_spins(rngx_ising lat, int8_t **d_spins);
+
+/* Copy the L*L spins to host memory (waits for `stream`), or replace them
+ * from host memory (every value must be +1 or -1, else RNGX_E_STATE; the
+ * copy is ordered on `stream` and done when the call returns).  With the
+ * generator image these form the lattice checkpoint. */
+rngx_status ising_get_spins(rngx_ising lat, int8_t *host_spins, void *stream);
+rngx_status ising_set_spins(rngx_ising lat, const int8_t *host_spins, void *stream);
+
+/* Borrow the generator handle that drives the lattice (for checkpoints via
+ * rng_get_state / rng_set_state).  It must not be destroyed by the caller. */
+rngx_status ising_rng(rngx_ising lat, rngx_gen *g);
+
+/* Release the lattice, its spins and its streams. */
+rngx_status ising_destroy(rngx_ising lat);
+
+/* Description of the calling thread's most recent error ("" if none). */
+const char *rngx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RNGX_H */

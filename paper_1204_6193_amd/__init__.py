@@ -1,0 +1,246 @@
+"""Thin Python binding of the rngx C-ABI (include/rngx.h).
+
+Per-thread random-number streams (LCG32, LCG64, MWC, XORWOW, Philox4x32-10
+and the XORShift-1024/Weyl generator of Manssen, Weigel & Hartmann) and their
+checkerboard Metropolis Ising consumer, as HIP kernels for gfx950 in
+librngx.so.  This module only marshals arguments: device buffers are torch
+tensors (or raw device addresses as ints), streams default to torch's current
+stream, and every non-OK status raises RngxError.  There is no fallback: if
+librngx.so is absent the import of the library fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first so that librngx.so binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librngx.so")
+
+KINDS = {"lcg32": 1, "lcg64": 2, "mwc": 3, "xorwow": 4, "philox4x32_10": 5, "xs1024w": 6}
+KIND_NAMES = {v: k for k, v in KINDS.items()}
+STATUS = {0: "RNGX_OK", -1: "RNGX_E_INVALID", -2: "RNGX_E_ALIGN", -3: "RNGX_E_NOMEM", -4: "RNGX_E_HIP",
+          -5: "RNGX_E_OVERFLOW", -6: "RNGX_E_STATE", -7: "RNGX_E_BUSY"}
+
+# Names exported by the C-ABI and their ctypes signatures.
+_u64, _i32, _vp, _sz = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+SIGNATURES = {
+    "rng_create": (_i32, [_i32, _u64, _u64, ctypes.POINTER(_vp)]),
+    "rng_destroy": (_i32, [_vp]),
+    "rng_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_u64)]),
+    "rng_fill_u32": (_i32, [_vp, _vp, _u64, _vp]),
+    "rng_fill_f32": (_i32, [_vp, _vp, _u64, _vp]),
+    "rng_consume": (_i32, [_vp, _vp, _u64, _vp]),
+    "rng_skip": (_i32, [_vp, _u64, _vp]),
+    "rng_get_state": (_i32, [_vp, _vp, ctypes.POINTER(_sz), _vp]),
+    "rng_set_state": (_i32, [_vp, _vp, _sz, _vp]),
+    "ising_create": (_i32, [ctypes.c_uint32, _i32, _u64, ctypes.POINTER(_vp)]),
+    "ising_sweep": (_i32, [_vp, ctypes.c_double, _u64, _vp, _vp]),
+    "ising_spins": (_i32, [_vp, ctypes.POINTER(_vp)]),
+    "ising_get_spins": (_i32, [_vp, _vp, _vp]),
+    "ising_set_spins": (_i32, [_vp, _vp, _vp]),
+    "ising_rng": (_i32, [_vp, ctypes.POINTER(_vp)]),
+    "ising_destroy": (_i32, [_vp]),
+    "rngx_last_error": (ctypes.c_char_p, []),
+}
+
+
+class RngxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load librngx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        raise RngxError(st, load().rngx_last_error().decode())
+
+
+def _kind(kind) -> int:
+    return KINDS[kind] if isinstance(kind, str) else int(kind)
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dptr(buf, min_elems: int, elem_size: int):
+    """Device address of `buf` (a CUDA tensor, or an int address)."""
+    if isinstance(buf, int) or buf is None:
+        return buf
+    if not buf.is_cuda:
+        raise ValueError("buffer must be a device tensor")
+    if not buf.is_contiguous():
+        raise ValueError("buffer must be contiguous")
+    if buf.element_size() != elem_size:
+        raise ValueError(f"buffer elements must be {elem_size} bytes")
+    if buf.numel() < min_elems:
+        raise ValueError(f"buffer holds {buf.numel()} elements, needs {min_elems}")
+    return buf.data_ptr()
+
+
+class Gen:
+    """A handle of S streams (owns the device state unless borrowed)."""
+
+    def __init__(self, handle, owned=True):
+        self.handle = handle
+        self.owned = owned
+        k = ctypes.c_int()
+        s = ctypes.c_uint64()
+        _check(load().rng_info(handle, ctypes.byref(k), ctypes.byref(s)))
+        self.kind = KIND_NAMES[k.value]
+        self.n_streams = s.value
+
+    def __del__(self):
+        if getattr(self, "owned", False) and self.handle and _lib is not None:
+            _lib.rng_destroy(self.handle)
+            self.handle = None
+
+    def destroy(self):
+        if self.owned and self.handle:
+            _check(load().rng_destroy(self.handle))
+        self.handle = None
+
+
+def rng_create(kind, n_streams: int, seed: int) -> Gen:
+    h = _vp()
+    _check(load().rng_create(_kind(kind), n_streams, seed, ctypes.byref(h)))
+    return Gen(h.value)
+
+
+def rng_destroy(g: Gen):
+    g.destroy()
+
+
+def rng_fill_u32(g: Gen, out, count_per_stream: int, stream=None):
+    _check(load().rng_fill_u32(g.handle, _dptr(out, g.n_streams * count_per_stream, 4), count_per_stream,
+                               _stream(stream)))
+
+
+def rng_fill_f32(g: Gen, out, count_per_stream: int, stream=None):
+    _check(load().rng_fill_f32(g.handle, _dptr(out, g.n_streams * count_per_stream, 4), count_per_stream,
+                               _stream(stream)))
+
+
+def rng_consume(g: Gen, out_xor, count_per_stream: int, stream=None):
+    _check(load().rng_consume(g.handle, _dptr(out_xor, g.n_streams, 4), count_per_stream, _stream(stream)))
+
+
+def rng_skip(g: Gen, n: int, stream=None):
+    _check(load().rng_skip(g.handle, n, _stream(stream)))
+
+
+def rng_get_state(g: Gen, stream=None):
+    """State image as a numpy uint8 array (layout in include/rngx.h)."""
+    import numpy as np
+    n = ctypes.c_size_t()
+    _check(load().rng_get_state(g.handle, None, ctypes.byref(n), _stream(stream)))
+    buf = np.zeros(n.value, dtype=np.uint8)
+    _check(load().rng_get_state(g.handle, buf.ctypes.data, ctypes.byref(n), _stream(stream)))
+    return buf
+
+
+def rng_set_state(g: Gen, image, stream=None):
+    import numpy as np
+    buf = np.ascontiguousarray(image, dtype=np.uint8)
+    _check(load().rng_set_state(g.handle, buf.ctypes.data, buf.nbytes, _stream(stream)))
+
+
+class Ising:
+    """An L x L lattice with its L*L/4 streams."""
+
+    def __init__(self, handle, L, kind):
+        self.handle = handle
+        self.L = L
+        self.kind = kind
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ising_destroy(self.handle)
+            self.handle = None
+
+    def destroy(self):
+        if self.handle:
+            _check(load().ising_destroy(self.handle))
+        self.handle = None
+
+
+def ising_create(L: int, kind, seed: int) -> Ising:
+    h = _vp()
+    _check(load().ising_create(L, _kind(kind), seed, ctypes.byref(h)))
+    return Ising(h.value, L, kind)
+
+
+def ising_sweep(lat: Ising, beta: float, n_sweeps: int, energy_trace=None, stream=None):
+    _check(load().ising_sweep(lat.handle, beta, n_sweeps, _dptr(energy_trace, n_sweeps, 4), _stream(stream)))
+
+
+def ising_spins(lat: Ising) -> int:
+    """Device address of the L*L int8 spins (borrowed)."""
+    p = _vp()
+    _check(load().ising_spins(lat.handle, ctypes.byref(p)))
+    return p.value
+
+
+class _DeviceArray:
+    """Exposes a borrowed device allocation through __cuda_array_interface__."""
+
+    def __init__(self, ptr: int, n: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False),
+                                         "version": 2, "strides": None}
+
+
+def ising_spins_view(lat: Ising) -> torch.Tensor:
+    """Zero-copy int8 device tensor [L, L] over the lattice's spins (borrowed:
+    valid until the lattice is destroyed)."""
+    L = lat.L
+    return torch.as_tensor(_DeviceArray(ising_spins(lat), L * L, "|i1"), device="cuda").view(L, L)
+
+
+def ising_get_spins(lat: Ising, stream=None):
+    """Spins as a numpy int8 array [L, L] (host copy)."""
+    import numpy as np
+    out = np.zeros(lat.L * lat.L, dtype=np.int8)
+    _check(load().ising_get_spins(lat.handle, out.ctypes.data, _stream(stream)))
+    return out.reshape(lat.L, lat.L)
+
+
+def ising_set_spins(lat: Ising, spins, stream=None):
+    import numpy as np
+    buf = np.ascontiguousarray(spins, dtype=np.int8).ravel()
+    if buf.size != lat.L * lat.L:
+        raise ValueError(f"need {lat.L * lat.L} spins, got {buf.size}")
+    _check(load().ising_set_spins(lat.handle, buf.ctypes.data, _stream(stream)))
+
+
+def ising_rng(lat: Ising) -> Gen:
+    h = _vp()
+    _check(load().ising_rng(lat.handle, ctypes.byref(h)))
+    return Gen(h.value, owned=False)
+
+
+def ising_destroy(lat: Ising):
+    lat.destroy()

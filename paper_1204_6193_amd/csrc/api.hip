@@ -1,0 +1,360 @@
+// C-ABI entry points of rngx (declared and documented in include/rngx.h).
+//
+// Every entry point validates its arguments completely before touching the
+// device; on error it returns a negative status with a thread-local message
+// and modifies nothing.  Live handles are kept in a registry so that a
+// stale or foreign handle is reported instead of dereferenced.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <unordered_set>
+
+#include "rngx_internal.h"
+
+namespace rngx {
+
+namespace {
+
+constexpr uint64_t kGenMagic = 0x52474E5847454E31ull;    // "RGNXGEN1"
+constexpr uint64_t kIsingMagic = 0x52474E584953474Eull;  // "RGNXISGN"
+constexpr uint64_t kMaxStreams = 1ull << 36;
+constexpr uint32_t kMaxL = 16384;  // |E| <= 2 L^2 must fit int32
+
+thread_local std::string g_error;
+std::mutex g_mu;
+std::unordered_set<const void *> g_live;
+
+void reg(const void *p) { std::lock_guard<std::mutex> l(g_mu); g_live.insert(p); }
+void unreg(const void *p) { std::lock_guard<std::mutex> l(g_mu); g_live.erase(p); }
+bool live(const void *p) { std::lock_guard<std::mutex> l(g_mu); return p && g_live.count(p); }
+
+// Makes the handle's device current for the scope of a call.
+struct DeviceScope {
+    int prev = -1, want;
+    explicit DeviceScope(int dev) : want(dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != want) (void)hipSetDevice(want);
+    }
+    ~DeviceScope() { if (prev >= 0 && prev != want) (void)hipSetDevice(prev); }
+};
+
+bool mul_overflows(uint64_t a, uint64_t b, uint64_t *out) { return __builtin_mul_overflow(a, b, out); }
+
+rngx_status check_gen(rngx_gen h, Gen **g) {
+    if (!live(h)) return fail(RNGX_E_INVALID, "unknown or destroyed generator handle");
+    *g = reinterpret_cast<Gen *>(h);
+    if ((*g)->magic != kGenMagic) return fail(RNGX_E_INVALID, "corrupt generator handle");
+    return RNGX_OK;
+}
+
+rngx_status check_ising(rngx_ising h, Ising **lat) {
+    if (!live(h)) return fail(RNGX_E_INVALID, "unknown or destroyed lattice handle");
+    *lat = reinterpret_cast<Ising *>(h);
+    if ((*lat)->magic != kIsingMagic) return fail(RNGX_E_INVALID, "corrupt lattice handle");
+    return RNGX_OK;
+}
+
+rngx_status alloc_gen(rngx_kind kind, uint64_t S, Gen **out) {
+    if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind " + std::to_string(kind));
+    if (S == 0) return fail(RNGX_E_INVALID, "n_streams must be positive");
+    if (S > kMaxStreams) return fail(RNGX_E_OVERFLOW, "n_streams exceeds 2^36");
+    if (kind == RNGX_XS1024W && S % 32 != 0)
+        return fail(RNGX_E_ALIGN, "XS1024W needs n_streams % 32 == 0 (32 lanes per 1024-bit instance)");
+    Gen *g = new Gen{};
+    g->magic = kGenMagic;
+    g->kind = kind;
+    g->S = S;
+    g->state_bytes = state_bytes(kind, S);
+    if (hipGetDevice(&g->device) != hipSuccess) { delete g; return fail(RNGX_E_HIP, "hipGetDevice failed"); }
+    hipError_t e = hipMalloc(&g->d_state, g->state_bytes);
+    if (e != hipSuccess) {
+        delete g;
+        (void)hipGetLastError();
+        return fail(RNGX_E_NOMEM, std::string("hipMalloc of generator state failed: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return RNGX_OK;
+}
+
+void free_gen(Gen *g) {
+    if (!g) return;
+    (void)hipFree(g->d_state);
+    g->magic = 0;
+    delete g;
+}
+
+rngx_status validate_image(rngx_kind kind, uint64_t S, const uint8_t *img) {
+    if (kind == RNGX_XS1024W) {
+        const uint32_t *W = reinterpret_cast<const uint32_t *>(img);
+        for (uint64_t g = 0; g < S / 32; ++g) {
+            uint32_t acc = 0;
+            for (int i = 0; i < 32; ++i) acc |= W[32 * g + i];
+            if (!acc) return fail(RNGX_E_STATE, "XS1024W instance " + std::to_string(g) + " is all-zero");
+        }
+    } else if (kind == RNGX_XORWOW) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(img);
+        for (uint64_t s = 0; s < S; ++s)
+            if (!(p[s] | p[S + s] | p[2 * S + s] | p[3 * S + s] | p[4 * S + s]))
+                return fail(RNGX_E_STATE, "XORWOW stream " + std::to_string(s) + " has all-zero xorshift words");
+    } else if (kind == RNGX_MWC) {
+        const uint64_t *y = reinterpret_cast<const uint64_t *>(img);
+        for (uint64_t s = 0; s < S; ++s)
+            if (y[s] == 0 || y[s] >= kMwcP)
+                return fail(RNGX_E_STATE, "MWC stream " + std::to_string(s) + " is a fixed point (y = 0 or y >= p)");
+    }
+    return RNGX_OK;
+}
+
+rngx_status fill_common(rngx_gen h, void *d_out, uint64_t count, int mode, void *stream) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (!d_out) return fail(RNGX_E_INVALID, "output pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16) return fail(RNGX_E_ALIGN, "output pointer must be 16-byte aligned");
+    uint64_t n, bytes;
+    if (mode != kOutXor && (mul_overflows(g->S, count, &n) || mul_overflows(n, 4, &bytes)))
+        return fail(RNGX_E_OVERFLOW, "n_streams * count * 4 overflows 64 bits");
+    if (count == 0 && mode != kOutXor) { clear_error(); return RNGX_OK; }
+    DeviceScope ds(g->device);
+    hipError_t e = launch_fill(g, d_out, count, mode, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "fill kernel launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+}  // namespace
+
+size_t state_bytes(rngx_kind kind, uint64_t S) {
+    switch (kind) {
+    case RNGX_LCG32: return 4 * S;
+    case RNGX_LCG64: return 8 * S;
+    case RNGX_MWC: return 8 * S;
+    case RNGX_XORWOW: return 24 * S;
+    case RNGX_PHILOX4X32_10: return 16 * S;
+    case RNGX_XS1024W: return 4 * S + 8 * (S / 32) + 4;
+    }
+    return 0;
+}
+
+bool kind_valid(int kind) { return kind >= RNGX_LCG32 && kind <= RNGX_XS1024W; }
+
+rngx_status fail(rngx_status st, const std::string &msg) { g_error = msg; return st; }
+rngx_status hip_fail(hipError_t e, const char *what) {
+    (void)hipGetLastError();
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return RNGX_E_HIP;
+}
+void clear_error() { g_error.clear(); }
+
+}  // namespace rngx
+
+using namespace rngx;
+
+extern "C" {
+
+const char *rngx_last_error(void) { return g_error.c_str(); }
+
+rngx_status rng_create(rngx_kind kind, uint64_t n_streams, uint64_t seed, rngx_gen *out) {
+    if (!out) return fail(RNGX_E_INVALID, "out is NULL");
+    Gen *g;
+    if (rngx_status s = alloc_gen(kind, n_streams, &g)) return s;
+    hipError_t e = launch_seed(g, seed, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) { free_gen(g); return hip_fail(e, "seeding"); }
+    reg(g);
+    *out = reinterpret_cast<rngx_gen>(g);
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_destroy(rngx_gen h) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (g->owner) return fail(RNGX_E_INVALID, "this generator belongs to a lattice; destroy the lattice instead");
+    DeviceScope ds(g->device);
+    (void)hipDeviceSynchronize();
+    unreg(g);
+    free_gen(g);
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_info(rngx_gen h, rngx_kind *kind, uint64_t *n_streams) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (kind) *kind = g->kind;
+    if (n_streams) *n_streams = g->S;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_fill_u32(rngx_gen g, uint32_t *d_out, uint64_t count, void *stream) {
+    return fill_common(g, d_out, count, kOutU32, stream);
+}
+
+rngx_status rng_fill_f32(rngx_gen g, float *d_out, uint64_t count, void *stream) {
+    return fill_common(g, d_out, count, kOutF32, stream);
+}
+
+rngx_status rng_consume(rngx_gen g, uint32_t *d_xor, uint64_t count, void *stream) {
+    return fill_common(g, d_xor, count, kOutXor, stream);
+}
+
+rngx_status rng_skip(rngx_gen h, uint64_t n, void *stream) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (n == 0) { clear_error(); return RNGX_OK; }
+    DeviceScope ds(g->device);
+    hipError_t e = launch_skip(g, n, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "skip kernel launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_get_state(rngx_gen h, void *host_buf, size_t *bytes, void *stream) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (!bytes) return fail(RNGX_E_INVALID, "bytes is NULL");
+    if (!host_buf) { *bytes = g->state_bytes; clear_error(); return RNGX_OK; }
+    if (*bytes < g->state_bytes) return fail(RNGX_E_INVALID, "host buffer smaller than the state image");
+    DeviceScope ds(g->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(host_buf, g->d_state, g->state_bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "state copy to host");
+    *bytes = g->state_bytes;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_set_state(rngx_gen h, const void *host_buf, size_t bytes, void *stream) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (!host_buf) return fail(RNGX_E_INVALID, "host buffer is NULL");
+    if (bytes != g->state_bytes)
+        return fail(RNGX_E_STATE, "state image has " + std::to_string(bytes) + " bytes, expected " +
+                                      std::to_string(g->state_bytes));
+    if (rngx_status s = validate_image(g->kind, g->S, static_cast<const uint8_t *>(host_buf))) return s;
+    DeviceScope ds(g->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(g->d_state, host_buf, bytes, hipMemcpyHostToDevice, st);
+    // The caller may reuse host_buf on return: wait for the (pageable) copy.
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "state copy to device");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *out) {
+    if (!out) return fail(RNGX_E_INVALID, "out is NULL");
+    if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind " + std::to_string(kind));
+    if (L < 16 || L % 16) return fail(RNGX_E_ALIGN, "L must be a multiple of 16 and at least 16");
+    if (L > kMaxL) return fail(RNGX_E_OVERFLOW, "L must not exceed 16384 (int32 energies)");
+    const uint64_t S = static_cast<uint64_t>(L) * L / 4;
+    Gen *g;
+    if (rngx_status s = alloc_gen(kind, S, &g)) return s;
+    Ising *lat = new Ising{};
+    lat->magic = kIsingMagic;
+    lat->L = L;
+    lat->device = g->device;
+    lat->gen = g;
+    g->owner = lat;
+    hipError_t e = hipMalloc(&lat->d_spins, static_cast<size_t>(L) * L);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_gen(g);
+        delete lat;
+        return fail(RNGX_E_NOMEM, "hipMalloc of the lattice failed");
+    }
+    e = launch_seed(g, seed, nullptr);
+    if (e == hipSuccess) e = launch_hot_start(lat, seed, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        (void)hipFree(lat->d_spins);
+        free_gen(g);
+        delete lat;
+        return hip_fail(e, "lattice initialisation");
+    }
+    reg(g);
+    reg(lat);
+    *out = reinterpret_cast<rngx_ising>(lat);
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_sweep(rngx_ising h, double beta, uint64_t n_sweeps, int32_t *d_trace, void *stream) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (!std::isfinite(beta) || beta < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");
+    if (d_trace && reinterpret_cast<uintptr_t>(d_trace) % 4) return fail(RNGX_E_ALIGN, "trace must be 4-byte aligned");
+    if (n_sweeps == 0) { clear_error(); return RNGX_OK; }
+    DeviceScope ds(lat->device);
+    hipError_t e = launch_ising(lat, beta, n_sweeps, d_trace, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "Ising kernel launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_spins(rngx_ising h, int8_t **d_spins) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (!d_spins) return fail(RNGX_E_INVALID, "d_spins is NULL");
+    *d_spins = lat->d_spins;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_get_spins(rngx_ising h, int8_t *host_spins, void *stream) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (!host_spins) return fail(RNGX_E_INVALID, "host_spins is NULL");
+    DeviceScope ds(lat->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t n = static_cast<size_t>(lat->L) * lat->L;
+    hipError_t e = hipMemcpyAsync(host_spins, lat->d_spins, n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "spin copy to host");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_set_spins(rngx_ising h, const int8_t *host_spins, void *stream) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (!host_spins) return fail(RNGX_E_INVALID, "host_spins is NULL");
+    const size_t n = static_cast<size_t>(lat->L) * lat->L;
+    for (size_t i = 0; i < n; ++i)
+        if (host_spins[i] != 1 && host_spins[i] != -1)
+            return fail(RNGX_E_STATE, "spin " + std::to_string(i) + " is neither +1 nor -1");
+    DeviceScope ds(lat->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(lat->d_spins, host_spins, n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "spin copy to device");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_rng(rngx_ising h, rngx_gen *g) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (!g) return fail(RNGX_E_INVALID, "g is NULL");
+    *g = reinterpret_cast<rngx_gen>(lat->gen);
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_destroy(rngx_ising h) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    DeviceScope ds(lat->device);
+    (void)hipDeviceSynchronize();
+    unreg(lat);
+    unreg(lat->gen);
+    (void)hipFree(lat->d_spins);
+    free_gen(lat->gen);
+    lat->magic = 0;
+    delete lat;
+    clear_error();
+    return RNGX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+// Seeding, bulk fill and consume kernels for all generator kinds.
+//
+// Fills are HBM-write-bound: each thread keeps its streams' state in VGPRs
+// for the whole launch (loaded once, stored once) and writes output k of
+// stream s to out[k*S + s], so a wavefront's stores cover one contiguous
+// span per step.  Small-state kinds run V consecutive streams per thread
+// (V = 4: one 16-byte store per step); XS1024W runs one instance per
+// 16-lane DPP row with two words per lane (one 8-byte store per step).
+#include "rngx_internal.h"
+
+namespace rngx {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// --------------------------------------------------------------------------
+// Seeding (definitions in rngx.h).
+__global__ __launch_bounds__(kBlock) void k_seed_small(rngx_kind kind, uint8_t *st, uint64_t S, uint64_t seed) {
+    const uint64_t s = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    uint32_t *u32 = reinterpret_cast<uint32_t *>(st);
+    uint64_t *u64 = reinterpret_cast<uint64_t *>(st);
+    switch (kind) {
+    case RNGX_LCG32: u32[s] = static_cast<uint32_t>(splitmix(seed, 1 + s)); break;
+    case RNGX_LCG64: u64[s] = splitmix(seed, 1 + s); break;
+    case RNGX_MWC: {
+        const uint64_t z = splitmix(seed, 1 + s);
+        uint64_t x = z & 0xFFFFFFFFull, c = (z >> 32) % (kMwcA - 1);
+        if (x == 0 && c == 0) x = 1;
+        u64[s] = (c << 32) | x;
+        break;
+    }
+    case RNGX_XORWOW: {
+        const uint64_t p = splitmix(seed, 1 + 3 * s), q = splitmix(seed, 2 + 3 * s), r = splitmix(seed, 3 + 3 * s);
+        uint32_t w[6] = {static_cast<uint32_t>(p), static_cast<uint32_t>(p >> 32), static_cast<uint32_t>(q),
+                         static_cast<uint32_t>(q >> 32), static_cast<uint32_t>(r), static_cast<uint32_t>(r >> 32)};
+        if ((w[0] | w[1] | w[2] | w[3] | w[4]) == 0) w[0] = 1;
+        for (int i = 0; i < 6; ++i) u32[i * S + s] = w[i];
+        break;
+    }
+    case RNGX_PHILOX4X32_10: {
+        const uint64_t z = splitmix(seed, 1 + s);
+        u32[s] = static_cast<uint32_t>(z);
+        u32[S + s] = static_cast<uint32_t>(z >> 32);
+        reinterpret_cast<uint64_t *>(st + 8 * S)[s] = 0;
+        break;
+    }
+    default: break;
+    }
+}
+
+// XS1024W: one thread per 64-bit seed word (two state words).  Among the 16
+// words SM(1+16g .. 16+16g) of an instance at most one can be zero (mix64 is
+// a bijection with mix64(0) = 0), so no instance is seeded all-zero.
+__global__ __launch_bounds__(kBlock) void k_seed_xs(uint8_t *st, uint64_t S, uint64_t seed) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;  // pair index
+    const uint64_t G = S / 32;
+    if (t >= 16 * G) return;
+    const uint64_t z = splitmix(seed, 1 + t);  // t = 16 g + i/2
+    reinterpret_cast<uint2 *>(st)[t] = make_uint2(static_cast<uint32_t>(z), static_cast<uint32_t>(z >> 32));
+    if ((t & 15) == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[t >> 4] = 0;
+    if (t == 0) *reinterpret_cast<uint32_t *>(st + 4 * S + 8 * G) = static_cast<uint32_t>(splitmix(seed, 0) >> 32);
+}
+
+// --------------------------------------------------------------------------
+// Output stores.
+__device__ __forceinline__ float to_unit(uint32_t u) { return static_cast<float>(u >> 8) * 0x1.0p-24f; }
+
+template <int MODE, int V>
+__device__ __forceinline__ void store_out(void *out, uint64_t idx, const uint32_t (&u)[V]) {
+    if constexpr (MODE == kOutU32) {
+        uint32_t *o = static_cast<uint32_t *>(out) + idx;
+        if constexpr (V == 4) *reinterpret_cast<uint4 *>(o) = make_uint4(u[0], u[1], u[2], u[3]);
+        else if constexpr (V == 2) *reinterpret_cast<uint2 *>(o) = make_uint2(u[0], u[1]);
+        else *o = u[0];
+    } else {
+        float *o = static_cast<float *>(out) + idx;
+        if constexpr (V == 4) *reinterpret_cast<float4 *>(o) = make_float4(to_unit(u[0]), to_unit(u[1]), to_unit(u[2]), to_unit(u[3]));
+        else if constexpr (V == 2) *reinterpret_cast<float2 *>(o) = make_float2(to_unit(u[0]), to_unit(u[1]));
+        else *o = to_unit(u[0]);
+    }
+}
+
+// Small-state kinds: V consecutive streams per thread.
+template <class G, int MODE, int V>
+__global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, uint64_t count, void *out) {
+    const uint64_t s0 = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * V;
+    if (s0 >= S) return;
+    G g[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) g[v].load(st, S, s0 + v);
+    uint32_t acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0;
+    for (uint64_t k = 0; k < count; ++k) {
+        uint32_t u[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) u[v] = g[v].next();
+        if constexpr (MODE == kOutXor) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] ^= u[v];
+        } else {
+            store_out<MODE, V>(out, k * S + s0, u);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) g[v].store(st, S, s0 + v);
+    if constexpr (MODE == kOutXor) {
+        uint32_t *o = static_cast<uint32_t *>(out);
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[s0 + v] = acc[v];
+    }
+}
+
+// XS1024W: thread t runs lane j = t % 16 of instance g = t / 16.  Rows past
+// the last instance exit as a whole, so every active row is complete.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_fill_xs(uint8_t *st, uint64_t S, uint64_t count, void *out) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t G = S / 32, g = t >> 4;
+    if (g >= G) return;
+    uint2 *W = reinterpret_cast<uint2 *>(st);
+    uint64_t *N = reinterpret_cast<uint64_t *>(st + 4 * S);
+    const uint32_t y0 = *reinterpret_cast<const uint32_t *>(st + 4 * S + 8 * G);
+    const uint2 w = W[t];
+    uint32_t a = w.x, b = w.y;
+    const uint64_t n = N[g];
+    uint32_t y = y0 + static_cast<uint32_t>(n) * kWeylC;
+    uint32_t acc0 = 0, acc1 = 0;
+    for (uint64_t k = 0; k < count; ++k) {
+        xs1024_step(a, b);
+        y += kWeylC;
+        const uint32_t m = weyl_mix(y);
+        const uint32_t u[2] = {a + m, b + m};
+        if constexpr (MODE == kOutXor) {
+            acc0 ^= u[0];
+            acc1 ^= u[1];
+        } else {
+            store_out<MODE, 2>(out, k * S + 2 * t, u);
+        }
+    }
+    W[t] = make_uint2(a, b);
+    if ((t & 15) == 0) N[g] = n + count;
+    if constexpr (MODE == kOutXor) reinterpret_cast<uint2 *>(out)[t] = make_uint2(acc0, acc1);
+}
+
+template <class G, int MODE>
+hipError_t fill_small(Gen *g, void *out, uint64_t count, hipStream_t st) {
+    const uint64_t S = g->S;
+    const bool vec4 = (S % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    if (vec4) {
+        const uint64_t threads = S / 4;
+        const unsigned blocks = static_cast<unsigned>((threads + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_fill_small<G, MODE, 4>), dim3(blocks), dim3(kBlock), 0, st, g->d_state, S, count, out);
+    } else {
+        const unsigned blocks = static_cast<unsigned>((S + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_fill_small<G, MODE, 1>), dim3(blocks), dim3(kBlock), 0, st, g->d_state, S, count, out);
+    }
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
+    switch (g->kind) {
+    case RNGX_LCG32: return fill_small<Lcg32, MODE>(g, out, count, st);
+    case RNGX_LCG64: return fill_small<Lcg64, MODE>(g, out, count, st);
+    case RNGX_MWC: return fill_small<Mwc, MODE>(g, out, count, st);
+    case RNGX_XORWOW: return fill_small<Xorwow, MODE>(g, out, count, st);
+    case RNGX_PHILOX4X32_10: return fill_small<Philox, MODE>(g, out, count, st);
+    case RNGX_XS1024W: {
+        const uint64_t threads = g->S / 2;
+        const unsigned blocks = static_cast<unsigned>((threads + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_fill_xs<MODE>), dim3(blocks), dim3(kBlock), 0, st, g->d_state, g->S, count, out);
+        return hipGetLastError();
+    }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st) {
+    if (g->kind == RNGX_XS1024W) {
+        const uint64_t pairs = g->S / 2;
+        const unsigned blocks = static_cast<unsigned>((pairs + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_seed_xs, dim3(blocks), dim3(kBlock), 0, st, g->d_state, g->S, seed);
+    } else {
+        const unsigned blocks = static_cast<unsigned>((g->S + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_seed_small, dim3(blocks), dim3(kBlock), 0, st, g->kind, g->d_state, g->S, seed);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st) {
+    if (mode == kOutU32) return fill_mode<kOutU32>(g, d_out, count, st);
+    if (mode == kOutF32) return fill_mode<kOutF32>(g, d_out, count, st);
+    return fill_mode<kOutXor>(g, d_out, count, st);
+}
+
+}  // namespace rngx

@@ -1,0 +1,198 @@
+// Internal declarations of the rngx library: handles, status helpers and the
+// device-side generator definitions shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "rngx.h"
+
+namespace rngx {
+
+// ---------------------------------------------------------------------------
+// Constants of the generators (paper sections cited in rngx.h).
+constexpr uint32_t kLcg32A = 1664525u;
+constexpr uint32_t kLcg32C = 1013904223u;
+constexpr uint64_t kLcg64A = 2862933555777941757ull;
+constexpr uint64_t kLcg64C = 1442695040888963407ull;
+constexpr uint64_t kMwcA = 4294967118ull;
+constexpr uint64_t kMwcP = (kMwcA << 32) - 1;  // safe prime a*2^32 - 1
+constexpr uint32_t kWeylC = 362437u;
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u, kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u, kPhiloxW1 = 0xBB67AE85u;
+constexpr uint64_t kSmGamma = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kSpinSeedXor = 0xD1B54A32D192ED03ull;
+
+// ---------------------------------------------------------------------------
+// Handles.  The device state is one allocation laid out exactly as the
+// checkpoint image documented in rngx.h (structure of arrays).
+struct Gen {
+    uint64_t magic;
+    rngx_kind kind;
+    uint64_t S;
+    int device;
+    uint8_t *d_state;
+    size_t state_bytes;
+    const void *owner;  // the lattice that owns this generator, if any
+};
+
+struct Ising {
+    uint64_t magic;
+    uint32_t L;
+    int device;
+    int8_t *d_spins;
+    Gen *gen;
+};
+
+size_t state_bytes(rngx_kind kind, uint64_t S);
+bool kind_valid(int kind);
+
+// Thread-local error text; returns `st` for `return fail(...)`.
+rngx_status fail(rngx_status st, const std::string &msg);
+rngx_status hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+// Launchers (stream-ordered, no host synchronisation).
+hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st);
+hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st);
+hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
+hipError_t launch_hot_start(Ising *lat, uint64_t seed, hipStream_t st);
+hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st);
+
+enum { kOutU32 = 0, kOutF32 = 1, kOutXor = 2 };
+
+// ---------------------------------------------------------------------------
+// Device-side helpers.
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t splitmix(uint64_t seed, uint64_t k) { return mix64(seed + k * kSmGamma); }
+
+// One generator per stream, held in registers between load() and store().
+// Each reads and writes its own arrays of the structure-of-arrays image.
+struct Lcg32 {
+    uint32_t x;
+    __device__ void load(const uint8_t *st, uint64_t, uint64_t s) { x = reinterpret_cast<const uint32_t *>(st)[s]; }
+    __device__ void store(uint8_t *st, uint64_t, uint64_t s) const { reinterpret_cast<uint32_t *>(st)[s] = x; }
+    __device__ uint32_t next() { x = kLcg32A * x + kLcg32C; return x; }
+};
+
+struct Lcg64 {
+    uint64_t x;
+    __device__ void load(const uint8_t *st, uint64_t, uint64_t s) { x = reinterpret_cast<const uint64_t *>(st)[s]; }
+    __device__ void store(uint8_t *st, uint64_t, uint64_t s) const { reinterpret_cast<uint64_t *>(st)[s] = x; }
+    __device__ uint32_t next() { x = kLcg64A * x + kLcg64C; return static_cast<uint32_t>(x >> 32); }
+};
+
+struct Mwc {
+    uint64_t y;  // carry << 32 | x
+    __device__ void load(const uint8_t *st, uint64_t, uint64_t s) { y = reinterpret_cast<const uint64_t *>(st)[s]; }
+    __device__ void store(uint8_t *st, uint64_t, uint64_t s) const { reinterpret_cast<uint64_t *>(st)[s] = y; }
+    __device__ uint32_t next() {
+        y = kMwcA * static_cast<uint32_t>(y) + (y >> 32);  // one 32x32+32 -> 64 multiply-add
+        return static_cast<uint32_t>(y);
+    }
+};
+
+struct Xorwow {
+    uint32_t x, y, z, w, v, d;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t s) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
+        x = p[s]; y = p[S + s]; z = p[2 * S + s]; w = p[3 * S + s]; v = p[4 * S + s]; d = p[5 * S + s];
+    }
+    __device__ void store(uint8_t *st, uint64_t S, uint64_t s) const {
+        uint32_t *p = reinterpret_cast<uint32_t *>(st);
+        p[s] = x; p[S + s] = y; p[2 * S + s] = z; p[3 * S + s] = w; p[4 * S + s] = v; p[5 * S + s] = d;
+    }
+    __device__ uint32_t next() {
+        uint32_t t = x ^ (x >> 2);
+        x = y; y = z; z = w; w = v;
+        v = (v ^ (v << 4)) ^ (t ^ (t << 1));
+        d += kWeylC;
+        return d + v;
+    }
+};
+
+// Philox4x32-10 block function on counter (lo, hi, 0, 0) with key (k0, k1).
+__device__ inline void philox_block(uint32_t k0, uint32_t k1, uint64_t blk, uint32_t &o0, uint32_t &o1,
+                                    uint32_t &o2, uint32_t &o3) {
+    uint32_t x0 = static_cast<uint32_t>(blk), x1 = static_cast<uint32_t>(blk >> 32), x2 = 0, x3 = 0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * x0;
+        const uint64_t p1 = static_cast<uint64_t>(kPhiloxM1) * x2;
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ x1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ x3 ^ k1;
+        x1 = static_cast<uint32_t>(p1);
+        x3 = static_cast<uint32_t>(p0);
+        x0 = n0; x2 = n2;
+        k0 += kPhiloxW0; k1 += kPhiloxW1;
+    }
+    o0 = x0; o1 = x1; o2 = x2; o3 = x3;
+}
+
+struct Philox {
+    uint32_t k0, k1, b0, b1, b2, b3;
+    uint64_t pos;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t s) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
+        k0 = p[s]; k1 = p[S + s];
+        pos = reinterpret_cast<const uint64_t *>(st + 8 * S)[s];
+        if (pos & 3) philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);  // resume mid-block
+    }
+    __device__ void store(uint8_t *st, uint64_t S, uint64_t s) const {
+        reinterpret_cast<uint64_t *>(st + 8 * S)[s] = pos;
+    }
+    __device__ uint32_t next() {
+        const uint32_t j = static_cast<uint32_t>(pos) & 3;
+        if (j == 0) philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);
+        ++pos;
+        return j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// XORShift-1024 on wave64: one 1024-bit instance per 16-lane DPP row, two
+// 32-bit words per lane (lane j holds words 2j and 2j+1, word 0 most
+// significant).  A word shift by 10 is then a lane shift by 5 inside the row,
+// and DPP row shifts read zero from outside the row, which is exactly the
+// zero fill of a shift of a 1024-bit number (bound_ctrl set: a source lane
+// outside the row reads as 0).
+template <int N>
+__device__ __forceinline__ uint32_t from_lane_plus(uint32_t v) {  // lane j <- lane j+N of its row
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x100 + N, 0xF, 0xF, true));
+}
+template <int N>
+__device__ __forceinline__ uint32_t from_lane_minus(uint32_t v) {  // lane j <- lane j-N of its row
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x110 + N, 0xF, 0xF, true));
+}
+// (hi << (32 - s)) | (lo >> s)
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s) {
+    return __builtin_amdgcn_alignbit(hi, lo, s);
+}
+
+// X ^= X << 329; X ^= X >> 347; X ^= X << 344  on the row-distributed state.
+__device__ __forceinline__ void xs1024_step(uint32_t &a, uint32_t &b) {
+    // << 329 = 10 words + 9 bits: W[i] ^= W[i+10] << 9 | W[i+11] >> 23
+    uint32_t p5a = from_lane_plus<5>(a), p5b = from_lane_plus<5>(b), p6a = from_lane_plus<6>(a);
+    a ^= funnel(p5a, p5b, 23);
+    b ^= funnel(p5b, p6a, 23);
+    // >> 347 = 10 words + 27 bits: W[i] ^= W[i-11] << 5 | W[i-10] >> 27
+    uint32_t m6b = from_lane_minus<6>(b), m5a = from_lane_minus<5>(a), m5b = from_lane_minus<5>(b);
+    a ^= funnel(m6b, m5a, 27);
+    b ^= funnel(m5a, m5b, 27);
+    // << 344 = 10 words + 24 bits: W[i] ^= W[i+10] << 24 | W[i+11] >> 8
+    p5a = from_lane_plus<5>(a); p5b = from_lane_plus<5>(b); p6a = from_lane_plus<6>(a);
+    a ^= funnel(p5a, p5b, 8);
+    b ^= funnel(p5b, p6a, 8);
+}
+
+// Weyl output term y (I + R^16) with y = y0 + n c.
+__device__ __forceinline__ uint32_t weyl_mix(uint32_t y) { return y ^ (y >> 16); }
+
+}  // namespace rngx

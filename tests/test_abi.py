@@ -1,0 +1,88 @@
+"""The C-ABI library loads, exports every function include/rngx.h declares,
+and rejects bad arguments before touching a device (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rngx.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:rngx_status|const char \*)\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_hot_path_calls():
+    names = _declared()
+    for n in ("rng_create", "rng_fill_u32", "rng_fill_f32", "rng_consume", "rng_skip", "ising_create",
+              "ising_sweep", "rngx_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(rngx):
+    lib = rngx.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(rngx.SIGNATURES)
+
+
+def test_library_links_no_oracle_code(rngx):
+    # the product library must not carry the oracle's symbols
+    lib = rngx.load()
+    for name in ("orc_generate", "orc_seed", "orc_ising_sweeps"):
+        assert not hasattr(lib, name)
+
+
+def _err(lib):
+    return lib.rngx_last_error().decode()
+
+
+def test_create_validation(rngx):
+    lib = rngx.load()
+    h = ctypes.c_void_p()
+    assert lib.rng_create(0, 16, 1, ctypes.byref(h)) == -1
+    assert lib.rng_create(7, 16, 1, ctypes.byref(h)) == -1
+    assert lib.rng_create(1, 0, 1, ctypes.byref(h)) == -1
+    assert lib.rng_create(6, 48, 1, ctypes.byref(h)) == -2 and "% 32" in _err(lib)
+    assert lib.rng_create(1, (1 << 36) + 1, 1, ctypes.byref(h)) == -5
+    assert lib.rng_create(1, 16, 1, None) == -1
+    assert h.value is None  # nothing was written
+
+
+@pytest.mark.parametrize("L", [0, 8, 17, 24, 100])
+def test_ising_create_rejects_bad_L(rngx, L):
+    lib = rngx.load()
+    h = ctypes.c_void_p()
+    assert lib.ising_create(L, 1, 1, ctypes.byref(h)) == -2
+    assert lib.ising_create(32768, 1, 1, ctypes.byref(h)) == -5
+
+
+def test_unknown_handles_are_rejected(rngx):
+    lib = rngx.load()
+    bogus = ctypes.c_void_p(0x1234560)
+    assert lib.rng_fill_u32(bogus, ctypes.c_void_p(0x1000), 4, None) == -1
+    assert lib.rng_skip(None, 4, None) == -1
+    assert lib.rng_destroy(bogus) == -1
+    assert lib.ising_sweep(bogus, 0.4, 1, None, None) == -1
+    assert lib.ising_destroy(None) == -1
+    assert "unknown" in _err(lib)
+
+
+def test_last_error_is_per_thread(rngx):
+    import threading
+    lib = rngx.load()
+    h = ctypes.c_void_p()
+    lib.rng_create(99, 1, 1, ctypes.byref(h))
+    seen = {}
+
+    def other():
+        seen["msg"] = lib.rngx_last_error().decode()
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen["msg"] == "" and "kind" in _err(lib)

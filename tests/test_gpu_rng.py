@@ -1,0 +1,192 @@
+"""GPU <-> oracle parity of the generator calls, element by element, bit-exact.
+
+Sizes span several tiles and ragged tails at small scale; the full-size case
+(2^20 streams x 4096 outputs, the bulk-fill workload) compares sampled
+stream ranges against the oracle and checks properties of the whole output.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w"]
+
+
+def _sizes(kind):
+    # XS1024W: whole instances (1 instance, 3 = less than a block, 33 = a
+    # block plus one); small kinds: ragged S (scalar path) and S % 4 == 0.
+    return [32, 96, 1056] if kind == "xs1024w" else [1, 7, 1000, 4096, 5003]
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _fill(rx, g, count, f32=False):
+    out = torch.empty(g.n_streams * count + 4, dtype=torch.float32 if f32 else torch.int32, device="cuda")
+    (rx.rng_fill_f32 if f32 else rx.rng_fill_u32)(g, out, count)
+    host = out[: g.n_streams * count].cpu().numpy()
+    return host.reshape(count, g.n_streams) if f32 else host.view(np.uint32).reshape(count, g.n_streams)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_seed_image_matches_oracle(rngx, orc, kind):
+    for S in _sizes(kind):
+        g = rngx.rng_create(kind, S, 0xC0FFEE)
+        assert np.array_equal(rngx.rng_get_state(g), orc.seed(kind, S, 0xC0FFEE)), (kind, S)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_fill_u32_parity_and_continuation(rngx, orc, kind):
+    for S in _sizes(kind):
+        print(f"case fill_u32 {kind} S={S}", flush=True)
+        g = rngx.rng_create(kind, S, 1)
+        st = orc.seed(kind, S, 1)
+        for count in (37, 1, 29):  # odd counts: Philox resumes mid-block
+            got = _fill(rngx, g, count)
+            want = orc.generate(kind, S, st, count)
+            assert np.array_equal(got, want), (kind, S, count)
+        assert np.array_equal(rngx.rng_get_state(g), st)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_fill_f32_parity(rngx, orc, kind):
+    S = 96 if kind == "xs1024w" else 1000
+    g = rngx.rng_create(kind, S, 5)
+    st = orc.seed(kind, S, 5)
+    got = _fill(rngx, g, 19, f32=True)
+    want = orc.generate(kind, S, st, 19, mode=orc.OUT_F32)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    assert np.array_equal(rngx.rng_get_state(g), st)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_consume_parity(rngx, orc, kind):
+    for S in _sizes(kind):
+        g = rngx.rng_create(kind, S, 9)
+        st = orc.seed(kind, S, 9)
+        out = torch.zeros(S, dtype=torch.int32, device="cuda")
+        rngx.rng_consume(g, out, 301)
+        want = orc.generate(kind, S, st, 301, mode=orc.OUT_XOR)
+        assert np.array_equal(_u32(out), want), (kind, S)
+        assert np.array_equal(rngx.rng_get_state(g), st)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_skip_parity(rngx, orc, kind):
+    S = 64 if kind == "xs1024w" else 100
+    g = rngx.rng_create(kind, S, 3)
+    st = orc.seed(kind, S, 3)
+    for n in (1, 2, 5, 1000, 4097, (1 << 40) + 7, (1 << 64) - 1):
+        print(f"case skip {kind} n={n}", flush=True)
+        rngx.rng_skip(g, n)
+        orc.jump(kind, S, st, n)
+        assert np.array_equal(rngx.rng_get_state(g), st), (kind, n)
+        assert np.array_equal(_fill(rngx, g, 3), orc.generate(kind, S, st, 3)), (kind, n)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_set_state_roundtrip(rngx, orc, kind):
+    S = 64 if kind == "xs1024w" else 64
+    g = rngx.rng_create(kind, S, 1)
+    st = orc.seed(kind, S, 77)  # a different seed's image
+    orc.generate(kind, S, st, 11)
+    rngx.rng_set_state(g, st)
+    assert np.array_equal(rngx.rng_get_state(g), st)
+    assert np.array_equal(_fill(rngx, g, 13), orc.generate(kind, S, st, 13))
+
+
+def test_set_state_rejects_fixed_points(rngx, orc):
+    g = rngx.rng_create("xs1024w", 64, 1)
+    img = rngx.rng_get_state(g)
+    bad = img.copy()
+    bad[128:256] = 0  # instance 1 all-zero
+    with pytest.raises(rngx.RngxError) as e:
+        rngx.rng_set_state(g, bad)
+    assert e.value.status == -6
+    assert np.array_equal(rngx.rng_get_state(g), img)  # unchanged
+    m = rngx.rng_create("mwc", 4, 1)
+    mi = rngx.rng_get_state(m)
+    mb = mi.copy()
+    mb[8:16] = 0
+    with pytest.raises(rngx.RngxError):
+        rngx.rng_set_state(m, mb)
+    with pytest.raises(rngx.RngxError):
+        rngx.rng_set_state(m, mi[:-1])
+
+
+def test_count_zero_and_argument_errors(rngx):
+    g = rngx.rng_create("lcg32", 64, 1)
+    img = rngx.rng_get_state(g)
+    out = torch.zeros(64 * 4 + 8, dtype=torch.int32, device="cuda")
+    rngx.rng_fill_u32(g, out, 0)
+    assert np.array_equal(rngx.rng_get_state(g), img)
+    with pytest.raises(rngx.RngxError) as e:  # 4-byte but not 16-byte aligned
+        rngx.rng_fill_u32(g, out.data_ptr() + 4, 1)
+    assert e.value.status == -2
+    with pytest.raises(rngx.RngxError) as e:
+        rngx.rng_fill_u32(g, out.data_ptr(), 1 << 62)
+    assert e.value.status == -5
+    assert np.array_equal(rngx.rng_get_state(g), img)
+
+
+def test_results_do_not_depend_on_the_stream(rngx):
+    s1 = torch.cuda.Stream()
+    outs = []
+    for stream in (None, s1):
+        g = rngx.rng_create("xs1024w", 4096, 2)
+        out = torch.empty(4096 * 64, dtype=torch.int32, device="cuda")
+        with torch.cuda.stream(s1 if stream is not None else torch.cuda.current_stream()):
+            rngx.rng_fill_u32(g, out, 64, stream=stream)
+        torch.cuda.synchronize()
+        outs.append(out.cpu())
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_xs1024w_config_4096_streams_x_1024(rngx, orc):
+    """The paper's generator: 4096 streams seeded from master seed 1, 1024
+    outputs each (4,194,304 values), the whole array bit-exact."""
+    S, count = 4096, 1024
+    g = rngx.rng_create("xs1024w", S, 1)
+    got = _fill(rngx, g, count)
+    want = orc.generate("xs1024w", S, orc.seed("xs1024w", S, 1), count)
+    assert np.array_equal(got, want)
+
+
+def _xor_fold(x):
+    while x.shape[0] > 1:
+        h = x.shape[0] // 2
+        x = torch.bitwise_xor(x[:h], x[h:2 * h]) if x.shape[0] % 2 == 0 else torch.cat(
+            [torch.bitwise_xor(x[:h], x[h:2 * h]), x[2 * h:]])
+    return x[0]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_full_size_sampled_parity(rngx, orc, kind):
+    """2^20 streams x 4096 outputs (16 GiB) as the benchmark launches it:
+    sampled stream ranges equal the oracle; the consume variant on a second
+    handle equals the XOR of the full output; a skip of 4096 on a third
+    handle lands on the first handle's state."""
+    S, count = 1 << 20, 4096
+    print(f"case full-size {kind}", flush=True)
+    g = rngx.rng_create(kind, S, 1)
+    out = torch.empty(S * count, dtype=torch.int32, device="cuda")
+    rngx.rng_fill_u32(g, out, count)
+    view = out.view(count, S)
+    st = orc.seed(kind, S, 1)
+    for lo, hi in ((0, 512), (S // 2 - 256, S // 2 + 256), (S - 512, S)):
+        want = orc.generate(kind, S, st, count, lo=lo, hi=hi)
+        got = view[:, lo:hi].contiguous().cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, want), (kind, lo, hi)
+    xor_all = _xor_fold(view)
+    del out, view
+    g2 = rngx.rng_create(kind, S, 1)
+    acc = torch.empty(S, dtype=torch.int32, device="cuda")
+    rngx.rng_consume(g2, acc, count)
+    assert torch.equal(acc, xor_all)
+    g3 = rngx.rng_create(kind, S, 1)
+    rngx.rng_skip(g3, count)
+    assert np.array_equal(rngx.rng_get_state(g3), rngx.rng_get_state(g))
+    assert np.array_equal(rngx.rng_get_state(g2), rngx.rng_get_state(g))
+    torch.cuda.empty_cache()
