@@ -29,7 +29,7 @@ S_FULL, COUNT_FULL = 1 << 20, 4096
 KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10"]
 # state bytes read + written once per launch, per stream
 STATE_BYTES = {"lcg32": 4, "lcg64": 8, "mwc": 8, "xorwow": 24, "philox4x32_10": 16, "xs1024w": 4 + 8 / 32}
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "xs1024w_fill_u32_2p20x4096_traffic.json")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "xs1024w_fill_u32_2p20x4096_hbm_traffic.md")
 KERNEL_SOURCES = ["paper_1204_6193_amd/csrc/gen.hip", "paper_1204_6193_amd/csrc/rngx_internal.h"]
 
 
@@ -107,8 +107,9 @@ def traffic_from_profile():
     only while the kernel sources are the ones it was taken from."""
     try:
         with open(PROFILE_TRAFFIC) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
+            text = f.read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
         return None
     if rec.get("kernel_hash") != kernel_hash():
         return None
@@ -154,6 +155,9 @@ def main():
     ap.add_argument("--ising-sweeps", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (for profiling)")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="for rocprofv3: the headline fill `steps` times, then a plain 4 GiB device-to-device "
+                         "copy `steps` times as the reference for scaling HBM byte counters; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -165,6 +169,19 @@ def main():
     rx.load()
     torch.cuda.set_device(0)
     out = torch.empty(S_FULL * COUNT_FULL, dtype=torch.int32, device="cuda")
+    if args.profile_pass:
+        g = rx.rng_create("xs1024w", S_FULL, 1)
+        for _ in range(args.steps):
+            rx.rng_fill_u32(g, out, COUNT_FULL)
+        torch.cuda.synchronize()
+        src = out[: 1 << 30]
+        dst = torch.empty(1 << 30, dtype=torch.int32, device="cuda")
+        for _ in range(args.steps):
+            dst.copy_(src)  # reads 4 GiB, writes 4 GiB
+        torch.cuda.synchronize()
+        print(f"profile pass done: {args.steps} fills of {S_FULL}x{COUNT_FULL}, {args.steps} copies of 4 GiB",
+              flush=True)
+        return
 
     head = bench_fill(rx, "xs1024w", "u32", out, args.steps, args.warmup)
     print(f"# headline xs1024w u32 fill: {head}", file=sys.stderr, flush=True)
