@@ -162,6 +162,13 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
 rngx_status ising_sweep(rngx_ising lat, double beta, uint64_t n_sweeps, int32_t *d_energy_trace,
                         void *stream);
 
+/* How the lattice is swept: *strips receives the number of workgroups that
+ * hold the lattice on chip as horizontal strips for a whole ising_sweep call
+ * (1 = a single workgroup), or 0 when every colour pass is a separate launch
+ * that streams spins and state through memory (large L).  Results do not
+ * depend on it.  Any output pointer may be NULL. */
+rngx_status ising_info(rngx_ising lat, uint32_t *L, rngx_kind *kind, uint32_t *strips);
+
 /* Borrow the device pointer of the spins (L*L int8, row-major).  The
  * pointer stays valid until ising_destroy; writes through it are allowed
  * (values must stay +-1) and are ordered by the caller's streams. */

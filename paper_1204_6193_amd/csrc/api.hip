@@ -243,6 +243,17 @@ rngx_status rng_set_state(rngx_gen h, const void *host_buf, size_t bytes, void *
     return RNGX_OK;
 }
 
+static void free_ising(Ising *lat) {
+    (void)hipFree(lat->d_spins);
+    (void)hipFree(lat->d_halo);
+    (void)hipFree(lat->d_flags);
+    (void)hipFree(lat->d_err);
+    (void)hipFree(lat->d_partial);
+    free_gen(lat->gen);
+    lat->magic = 0;
+    delete lat;
+}
+
 rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *out) {
     if (!out) return fail(RNGX_E_INVALID, "out is NULL");
     if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind " + std::to_string(kind));
@@ -257,20 +268,28 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
     lat->device = g->device;
     lat->gen = g;
     g->owner = lat;
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess) n_cu = 0;
+    if (!ising_plan(L, kind, n_cu, &lat->plan)) lat->plan.strips = false;
     hipError_t e = hipMalloc(&lat->d_spins, static_cast<size_t>(L) * L);
+    if (e == hipSuccess) e = hipMalloc(&lat->d_err, 4);
+    if (e == hipSuccess && lat->plan.strips && lat->plan.nwg > 1) {
+        e = hipMalloc(&lat->d_halo, static_cast<size_t>(4) * lat->plan.nwg * L);
+        if (e == hipSuccess) e = hipMalloc(&lat->d_flags, 4ull * lat->plan.nwg);
+    }
+    if (e == hipSuccess && !lat->plan.strips) e = hipMalloc(&lat->d_partial, 4 * ising_partials(L));
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        free_gen(g);
-        delete lat;
-        return fail(RNGX_E_NOMEM, "hipMalloc of the lattice failed");
+        free_ising(lat);
+        return fail(RNGX_E_NOMEM, "device allocation for the lattice failed");
     }
     e = launch_seed(g, seed, nullptr);
     if (e == hipSuccess) e = launch_hot_start(lat, seed, nullptr);
+    if (e == hipSuccess) e = launch_zero(lat->d_err, 1, nullptr);
+    if (e == hipSuccess && lat->d_flags) e = launch_zero(lat->d_flags, lat->plan.nwg, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
-        (void)hipFree(lat->d_spins);
-        free_gen(g);
-        delete lat;
+        free_ising(lat);
         return hip_fail(e, "lattice initialisation");
     }
     reg(g);
@@ -293,6 +312,16 @@ rngx_status ising_sweep(rngx_ising h, double beta, uint64_t n_sweeps, int32_t *d
     return RNGX_OK;
 }
 
+rngx_status ising_info(rngx_ising h, uint32_t *L, rngx_kind *kind, uint32_t *strips) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (L) *L = lat->L;
+    if (kind) *kind = lat->gen->kind;
+    if (strips) *strips = lat->plan.strips ? lat->plan.nwg : 0;
+    clear_error();
+    return RNGX_OK;
+}
+
 rngx_status ising_spins(rngx_ising h, int8_t **d_spins) {
     Ising *lat;
     if (rngx_status s = check_ising(h, &lat)) return s;
@@ -309,9 +338,12 @@ rngx_status ising_get_spins(rngx_ising h, int8_t *host_spins, void *stream) {
     DeviceScope ds(lat->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t n = static_cast<size_t>(lat->L) * lat->L;
+    uint32_t err = 0;
     hipError_t e = hipMemcpyAsync(host_spins, lat->d_spins, n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&err, lat->d_err, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "spin copy to host");
+    if (err) return fail(RNGX_E_HIP, "a strip gave up waiting for its neighbours; the lattice is invalid");
     clear_error();
     return RNGX_OK;
 }
@@ -349,10 +381,7 @@ rngx_status ising_destroy(rngx_ising h) {
     (void)hipDeviceSynchronize();
     unreg(lat);
     unreg(lat->gen);
-    (void)hipFree(lat->d_spins);
-    free_gen(lat->gen);
-    lat->magic = 0;
-    delete lat;
+    free_ising(lat);
     clear_error();
     return RNGX_OK;
 }

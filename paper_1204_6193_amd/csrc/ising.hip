@@ -1,13 +1,31 @@
 // Checkerboard Metropolis update of the 2D Ising ferromagnet (the paper's
 // application test, Sec. 2) driven by the per-stream generators.
 //
-// Stream s = y*(L/4) + x/4 owns the 4-site word x0..x0+3 of row y.  In colour
+// Stream s = y*(L/4) + x/4 owns the 4-site run x0..x0+3 of row y.  In colour
 // pass c it updates sites x0 + ((c+y)&1) and x0 + 2 + ((c+y)&1) with its next
-// two outputs.  One launch per colour pass: a thread loads its stream
-// state, its spin word and the neighbouring words, makes both updates and
-// writes back.  The energy after a sweep is accumulated in the colour-1 pass:
-// every bond has exactly one colour-1 end, and colour 0 is final by then, so
-// E = -sum over colour-1 sites of s_i * (sum of its 4 neighbours).
+// two outputs (XS1024W: one lane pair = streams 2u, 2u+1 = an 8-site run).
+//
+// Strip kernel (L up to ~5800): the lattice is cut into horizontal strips of
+// R rows, one workgroup each.  A workgroup keeps its strip's spins in LDS and
+// its streams' state in VGPRs for all sweeps of the call; only the two
+// boundary rows of a strip go through global memory after each pass, and
+// neighbouring strips synchronise through per-strip flags (release/acquire at
+// agent scope).  Cooperative launch guarantees that every strip is resident,
+// so every wait ends; the waits are also bounded.  A lattice that fits one
+// workgroup (one strip, R = L) wraps its halo rows inside LDS.
+//
+// Per-pass kernels (larger L): one launch per colour pass, state and spins
+// streamed from memory, energy reduced per block and then across blocks.
+//
+// Site update: with spins stored as int8 +1 = 0x01, -1 = 0xFF, bit 1 marks a
+// down spin; the number m of neighbours that differ from a site is summed
+// bytewise for a whole run (SWAR).  dE = 2 s h = 8 - 4 m, so a flip is
+// accepted iff m >= 2, or m = 1 and r < T4, or m = 0 and r < T8.  After the
+// colour-1 pass colour 0 is final and every bond has exactly one colour-1
+// end, so E = -sum over colour-1 sites of s h = -sum (4 - 2 m_after).
+#include <algorithm>
+#include <cmath>
+
 #include "rngx_internal.h"
 
 namespace rngx {
@@ -15,6 +33,7 @@ namespace rngx {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr uint64_t kOnes8 = 0x0101010101010101ull;
 
 __global__ __launch_bounds__(kBlock) void k_hot_start(int8_t *spins, uint64_t n_words, uint64_t seed) {
     const uint64_t q = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -30,142 +49,456 @@ __global__ __launch_bounds__(kBlock) void k_hot_start(int8_t *spins, uint64_t n_
     reinterpret_cast<uint32_t *>(spins)[q] = w;
 }
 
-__device__ __forceinline__ int spin_at(uint64_t word, int i) { return static_cast<int8_t>(word >> (8 * i)); }
-
-// Update byte i of `word` (a 4- or 8-site run of one row).  lft/rgt are the
-// spins just outside the run, up/dn the words of the rows above and below.
-// Returns the post-update s_i * (neighbour sum) for the energy.
-template <int NBYTES>
-__device__ __forceinline__ int update_site(uint64_t &word, int i, int lft, int rgt, uint64_t up, uint64_t dn,
-                                           uint32_t r, uint64_t T4, uint64_t T8) {
-    const int s = spin_at(word, i);
-    const int l = i > 0 ? spin_at(word, i - 1) : lft;
-    const int rr = i < NBYTES - 1 ? spin_at(word, i + 1) : rgt;
-    const int nb = l + rr + spin_at(up, i) + spin_at(dn, i);
-    const int dE = 2 * s * nb;
-    const uint64_t thr = dE == 4 ? T4 : T8;
-    const bool acc = dE <= 0 || static_cast<uint64_t>(r) < thr;
-    const int s_new = acc ? -s : s;
-    const uint64_t m = 0xFFull << (8 * i);
-    word = (word & ~m) | (static_cast<uint64_t>(static_cast<uint8_t>(s_new)) << (8 * i));
-    return s_new * nb;
+__global__ __launch_bounds__(kBlock) void k_zero_u32(uint32_t *p, uint64_t n) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
-__device__ __forceinline__ void block_energy_add(int e, int32_t *dst) {
-    // wave reduction, then one atomic per wave
+// Bytewise count (0..4) of neighbours that differ from each site of an
+// NB-site run w; up/dn are the runs above and below, lb/rb the spins left of
+// byte 0 and right of byte NB-1.
+template <int NB>
+__device__ __forceinline__ uint64_t mismatches(uint64_t w, uint64_t up, uint64_t dn, uint32_t lb, uint32_t rb) {
+    constexpr uint64_t M = NB == 8 ? kOnes8 : 0x01010101ull;
+    const uint64_t nw = (w >> 1) & M, nu = (up >> 1) & M, nd = (dn >> 1) & M;
+    const uint64_t nl = ((nw << 8) | ((lb >> 1) & 1u)) & M;
+    const uint64_t nr = (nw >> 8) | (static_cast<uint64_t>((rb >> 1) & 1u) << (8 * (NB - 1)));
+    return (nu ^ nw) + (nd ^ nw) + (nl ^ nw) + (nr ^ nw);
+}
+
+// Metropolis decision for byte i; returns s_i h_i after the update.
+__device__ __forceinline__ int metropolis(uint64_t &w, uint64_t m, int i, uint32_t r, uint64_t T4, uint64_t T8) {
+    const int mi = static_cast<int>((m >> (8 * i)) & 0xFF);
+    const bool acc = mi >= 2 || static_cast<uint64_t>(r) < (mi == 1 ? T4 : T8);
+    if (acc) w ^= 0xFEull << (8 * i);
+    return acc ? 2 * mi - 4 : 4 - 2 * mi;
+}
+
+// ---------------------------------------------------------------- units
+// A unit is what one thread updates with one set of draws: a stream (4
+// sites) for the small-state kinds, a lane pair of an XS1024W instance (8
+// sites) for the paper's generator.  Units are numbered like the stream
+// (small kinds) or stream/2 (XS1024W).
+template <class G>
+struct SmallUnit {
+    static constexpr int kNB = 4;
+    G g;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t u) { g.load(st, S, u); }
+    __device__ void store(uint8_t *st, uint64_t S, uint64_t u, uint64_t) const { g.store(st, S, u); }
+    __device__ void draw(uint32_t (&r)[2]) { r[0] = g.next(); r[1] = g.next(); }
+};
+
+// Philox with only key and position held: the two draws of a pass come from
+// one block unless they straddle a block boundary.
+struct PhiloxUnit {
+    static constexpr int kNB = 4;
+    uint32_t k0, k1;
+    uint64_t pos;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t u) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
+        k0 = p[u]; k1 = p[S + u];
+        pos = reinterpret_cast<const uint64_t *>(st + 8 * S)[u];
+    }
+    __device__ void store(uint8_t *st, uint64_t S, uint64_t u, uint64_t) const {
+        reinterpret_cast<uint64_t *>(st + 8 * S)[u] = pos;
+    }
+    __device__ void draw(uint32_t (&r)[2]) {
+        uint32_t b0, b1, b2, b3;
+        philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);
+        const uint32_t j = static_cast<uint32_t>(pos) & 3;
+        r[0] = j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3;
+        if (j == 3) philox_block(k0, k1, (pos >> 2) + 1, b0, b1, b2, b3);
+        r[1] = j == 0 ? b1 : j == 1 ? b2 : j == 2 ? b3 : b0;
+        pos += 2;
+    }
+};
+
+// XS1024W lane pair u: lane u%16 of instance u/16 of the handle (words 2u,
+// 2u+1 = streams 2u and 2u+1).  Two instance steps per pass; the draws are
+// ordered stream 2u first, stream 2u+1 second, each in step order.
+struct XsUnit {
+    static constexpr int kNB = 8;
+    uint32_t a, b, y;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t u) {
+        const uint2 w = reinterpret_cast<const uint2 *>(st)[u];
+        a = w.x; b = w.y;
+        const uint64_t n = reinterpret_cast<const uint64_t *>(st + 4 * S)[u >> 4];
+        y = *reinterpret_cast<const uint32_t *>(st + 4 * S + 8 * (S / 32)) + static_cast<uint32_t>(n) * kWeylC;
+    }
+    __device__ void store(uint8_t *st, uint64_t S, uint64_t u, uint64_t steps) const {
+        reinterpret_cast<uint2 *>(st)[u] = make_uint2(a, b);
+        if ((u & 15) == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[u >> 4] += steps;
+    }
+    __device__ void draw(uint32_t (&r)[4]) {
+        xs1024_step(a, b);
+        y += kWeylC;
+        uint32_t m = weyl_mix(y);
+        r[0] = a + m; r[2] = b + m;
+        xs1024_step(a, b);
+        y += kWeylC;
+        m = weyl_mix(y);
+        r[1] = a + m; r[3] = b + m;
+    }
+};
+
+template <int NB>
+__device__ __forceinline__ uint64_t lds_run(const uint8_t *p) {
+    if constexpr (NB == 8) return *reinterpret_cast<const uint64_t *>(p);
+    else return *reinterpret_cast<const uint32_t *>(p);
+}
+template <int NB>
+__device__ __forceinline__ void lds_put(uint8_t *p, uint64_t w) {
+    if constexpr (NB == 8) *reinterpret_cast<uint64_t *>(p) = w;
+    else *reinterpret_cast<uint32_t *>(p) = static_cast<uint32_t>(w);
+}
+
+// ---------------------------------------------------------------- strips
+struct StripArgs {
+    int8_t *spins;
+    uint8_t *st;
+    uint64_t S;
+    uint32_t L, R, nwg, units;  // units per strip
+    uint64_t T4, T8, n_sweeps;
+    int32_t *trace;             // may be null
+    uint8_t *halo;              // 2 slots x nwg x 2 rows x L bytes
+    uint32_t *flags;            // nwg pass counters
+    uint32_t epoch0;
+    uint32_t *err;
+};
+
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+// Wait (one wavefront, all lanes reading the same words) until both flags
+// reach `target`.  Gives up after kSpinLimit polls and records that in *err;
+// once *err is set every later wait returns at once, so a failed exchange
+// ends the kernel quickly (with an invalid lattice) instead of stalling it.
+__device__ __forceinline__ void wait_both(uint32_t *f0, uint32_t *f1, uint32_t target, uint32_t *err) {
+    for (uint32_t it = 0; it < kSpinLimit; ++it) {
+        const uint32_t v0 = __hip_atomic_load(f0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t v1 = __hip_atomic_load(f1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (static_cast<int32_t>(v0 - target) >= 0 && static_cast<int32_t>(v1 - target) >= 0) return;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void copy_bytes(uint8_t *dst, const uint8_t *src, uint32_t n, uint32_t t, uint32_t nt) {
+    for (uint32_t i = 4 * t; i < n; i += 4 * nt)
+        *reinterpret_cast<uint32_t *>(dst + i) = *reinterpret_cast<const uint32_t *>(src + i);
+}
+
+// Sum of v over the block (result valid in thread 0).
+__device__ __forceinline__ int block_sum(int v, int *scratch) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
-    if ((threadIdx.x & 63) == 0 && e != 0) atomicAdd(dst, -e);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const uint32_t w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) scratch[w] = v;
+    __syncthreads();
+    int s = 0;
+    if (threadIdx.x == 0)
+        for (uint32_t i = 0; i < nw; ++i) s += scratch[i];
+    __syncthreads();
+    return s;
 }
 
-// Small-state kinds: one stream (4-site word) per thread.
-template <class G>
-__global__ __launch_bounds__(kBlock) void k_pass_small(int8_t *spins, uint8_t *st, uint64_t S, uint32_t L, int c,
-                                                        uint64_t T4, uint64_t T8, int32_t *trace_t) {
-    const uint64_t s = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c == 0 && trace_t && s == 0) *trace_t = 0;
-    int e = 0;
-    if (s < S) {
-        const uint32_t spr = L >> 2;
-        const uint32_t y = static_cast<uint32_t>(s / spr), x0 = 4 * static_cast<uint32_t>(s % spr);
-        const uint64_t row = static_cast<uint64_t>(y) * L;
-        const uint64_t up_row = static_cast<uint64_t>(y == 0 ? L - 1 : y - 1) * L;
-        const uint64_t dn_row = static_cast<uint64_t>(y == L - 1 ? 0 : y + 1) * L;
-        uint64_t word = *reinterpret_cast<const uint32_t *>(spins + row + x0);
-        const uint64_t up = *reinterpret_cast<const uint32_t *>(spins + up_row + x0);
-        const uint64_t dn = *reinterpret_cast<const uint32_t *>(spins + dn_row + x0);
-        const int lft = spins[row + (x0 == 0 ? L - 1 : x0 - 1)];
-        const int rgt = spins[row + (x0 + 4 == L ? 0 : x0 + 4)];
-        const int p = (c + y) & 1;
-        G g;
-        g.load(st, S, s);
-        const uint32_t r0 = g.next();
-        const uint32_t r1 = g.next();
-        g.store(st, S, s);
-        e += update_site<4>(word, p, lft, rgt, up, dn, r0, T4, T8);
-        e += update_site<4>(word, p + 2, lft, rgt, up, dn, r1, T4, T8);
-        *reinterpret_cast<uint32_t *>(spins + row + x0) = static_cast<uint32_t>(word);
-    }
-    if (c == 1 && trace_t) block_energy_add(e, trace_t);
+// Unit k of the strip sits at byte offset `off` of LDS (row yl+1); bit 29:
+// run starts at x = 0, bit 30: run ends at x = L-1, bit 31: (row0+yl) odd.
+template <int NB>
+__device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint64_t row0) {
+    const uint32_t upr = L / NB;
+    const uint32_t yl = k / upr, x0 = (k % upr) * NB;
+    uint32_t off = (yl + 1) * L + x0;
+    if (x0 == 0) off |= 1u << 29;
+    if (x0 + NB == L) off |= 1u << 30;
+    if ((row0 + yl) & 1) off |= 1u << 31;
+    return off;
 }
 
-// XS1024W: lane j of instance g (one 16-lane row) owns streams 32g+2j and
-// 32g+2j+1, i.e. the 8-site run x0..x0+7 of one row.  Two instance steps
-// give every lane its two draws for the pass.
-__global__ __launch_bounds__(kBlock) void k_pass_xs(int8_t *spins, uint8_t *st, uint64_t S, uint32_t L, int c,
-                                                     uint64_t T4, uint64_t T8, int32_t *trace_t) {
-    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint64_t G = S / 32, g = t >> 4;
-    if (c == 0 && trace_t && t == 0) *trace_t = 0;
-    int e = 0;
-    if (g < G) {  // whole rows are in or out
-        uint2 *W = reinterpret_cast<uint2 *>(st);
-        uint64_t *N = reinterpret_cast<uint64_t *>(st + 4 * S);
-        const uint32_t y0 = *reinterpret_cast<const uint32_t *>(st + 4 * S + 8 * G);
-        const uint2 w = W[t];
-        uint32_t a = w.x, b = w.y;
-        const uint64_t n = N[g];
-        uint32_t yw = y0 + static_cast<uint32_t>(n) * kWeylC;
-        xs1024_step(a, b);
-        yw += kWeylC;
-        uint32_t m = weyl_mix(yw);
-        const uint32_t ra0 = a + m, rb0 = b + m;
-        xs1024_step(a, b);
-        yw += kWeylC;
-        m = weyl_mix(yw);
-        const uint32_t ra1 = a + m, rb1 = b + m;
-        W[t] = make_uint2(a, b);
-        if ((t & 15) == 0) N[g] = n + 2;
+template <class Unit, int SPT>
+__global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
+    constexpr int NB = Unit::kNB;
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint32_t L = a.L, R = a.R, nwg = a.nwg, t = threadIdx.x, nt = blockDim.x;
+    // Blocks b, b+8, b+16, ... share an XCD: give them consecutive strips so
+    // that most neighbour exchanges stay inside one L2.
+    const uint32_t b = blockIdx.x;
+    const uint32_t r = (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
+    const uint64_t row0 = static_cast<uint64_t>(r) * R;
+    const uint32_t strip_bytes = R * L;
+    int *red = reinterpret_cast<int *>(lds + (R + 2) * L);
 
-        const uint64_t sa = 2 * t;  // = 32 g + 2 j
-        const uint32_t spr = L >> 2;
-        const uint32_t y = static_cast<uint32_t>(sa / spr), x0 = 4 * static_cast<uint32_t>(sa % spr);
-        const uint64_t row = static_cast<uint64_t>(y) * L;
-        const uint64_t up_row = static_cast<uint64_t>(y == 0 ? L - 1 : y - 1) * L;
-        const uint64_t dn_row = static_cast<uint64_t>(y == L - 1 ? 0 : y + 1) * L;
-        uint64_t word = *reinterpret_cast<const uint64_t *>(spins + row + x0);
-        const uint64_t up = *reinterpret_cast<const uint64_t *>(spins + up_row + x0);
-        const uint64_t dn = *reinterpret_cast<const uint64_t *>(spins + dn_row + x0);
-        const int lft = spins[row + (x0 == 0 ? L - 1 : x0 - 1)];
-        const int rgt = spins[row + (x0 + 8 == L ? 0 : x0 + 8)];
-        const int p = (c + y) & 1;
-        e += update_site<8>(word, p, lft, rgt, up, dn, ra0, T4, T8);
-        e += update_site<8>(word, p + 2, lft, rgt, up, dn, ra1, T4, T8);
-        e += update_site<8>(word, p + 4, lft, rgt, up, dn, rb0, T4, T8);
-        e += update_site<8>(word, p + 6, lft, rgt, up, dn, rb1, T4, T8);
-        *reinterpret_cast<uint64_t *>(spins + row + x0) = word;
-    }
-    if (c == 1 && trace_t) block_energy_add(e, trace_t);
-}
+    // strip and initial halo rows from the lattice
+    const int8_t *gs = a.spins;
+    copy_bytes(lds + L, reinterpret_cast<const uint8_t *>(gs + row0 * L), strip_bytes, t, nt);
+    const uint64_t up_row = (row0 + L - 1) % L, dn_row = (row0 + R) % L;
+    copy_bytes(lds, reinterpret_cast<const uint8_t *>(gs + up_row * L), L, t, nt);
+    copy_bytes(lds + (R + 1) * L, reinterpret_cast<const uint8_t *>(gs + dn_row * L), L, t, nt);
 
-template <class G>
-hipError_t sweeps_small(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
-    const uint64_t S = lat->gen->S;
-    const unsigned blocks = static_cast<unsigned>((S + kBlock - 1) / kBlock);
-    for (uint64_t t = 0; t < n; ++t) {
-        int32_t *tt = tr ? tr + t : nullptr;
-        for (int c = 0; c < 2; ++c) {
-            hipLaunchKernelGGL((k_pass_small<G>), dim3(blocks), dim3(kBlock), 0, st, lat->d_spins, lat->gen->d_state,
-                               S, lat->L, c, T4, T8, tt);
+    const uint64_t ubase = static_cast<uint64_t>(r) * a.units;
+    Unit u[SPT];
+    uint32_t place[SPT];
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+        const uint32_t k = t + i * nt;
+        if (k < a.units) {
+            u[i].load(a.st, a.S, ubase + k);
+            place[i] = unit_place<NB>(k, L, row0);
         }
+    }
+    __syncthreads();
+
+    const uint32_t up_wg = (r + nwg - 1) % nwg, dn_wg = (r + 1) % nwg;
+    uint32_t q = 0;  // pass counter
+    for (uint64_t sweep = 0; sweep < a.n_sweeps; ++sweep) {
+        for (int c = 0; c < 2; ++c, ++q) {
+            int sh = 0;
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+                const uint32_t k = t + i * nt;
+                if (k < a.units) {
+                    uint32_t pl = place[i];
+                    asm volatile("" : "+v"(pl));  // recompute addresses here rather than hold them per unit
+                    const uint32_t off = pl & 0x1FFFFFFFu;
+                    uint64_t w = lds_run<NB>(lds + off);
+                    const uint64_t upw = lds_run<NB>(lds + off - L), dnw = lds_run<NB>(lds + off + L);
+                    const uint32_t lb = lds[(pl >> 29) & 1 ? off + L - 1 : off - 1];
+                    const uint32_t rb = lds[(pl >> 30) & 1 ? off + NB - L : off + NB];
+                    const uint64_t m = mismatches<NB>(w, upw, dnw, lb, rb);
+                    const int p = (c + (pl >> 31)) & 1;
+                    uint32_t rr[NB / 2];
+                    u[i].draw(rr);
+#pragma unroll
+                    for (int h = 0; h < NB / 2; ++h) sh += metropolis(w, m, p + 2 * h, rr[h], a.T4, a.T8);
+                    lds_put<NB>(lds + off, w);
+                }
+                // keep units apart: only the held states stay live across units
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+            if (nwg == 1) {
+                copy_bytes(lds, lds + R * L, L, t, nt);            // row above row 0 = last row
+                copy_bytes(lds + (R + 1) * L, lds + L, L, t, nt);  // row below the last = row 0
+            } else if (t < 64) {
+                // Wavefront 0 alone exchanges the boundary rows: publish mine,
+                // release, raise my flag, wait for both neighbours, acquire,
+                // read theirs.  Its own wait counters and cache write-back /
+                // invalidate then cover every access of the exchange.
+                const uint32_t slot = q & 1;
+                uint8_t *mine = a.halo + ((static_cast<uint64_t>(slot) * nwg + r) * 2) * L;
+                copy_bytes(mine, lds + L, L, t, 64);            // my top row
+                copy_bytes(mine + L, lds + R * L, L, t, 64);    // my bottom row
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(a.flags + r, a.epoch0 + q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                wait_both(a.flags + up_wg, a.flags + dn_wg, a.epoch0 + q + 1, a.err);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const uint8_t *upn = a.halo + ((static_cast<uint64_t>(slot) * nwg + up_wg) * 2) * L + L;  // its bottom
+                const uint8_t *dnn = a.halo + ((static_cast<uint64_t>(slot) * nwg + dn_wg) * 2) * L;      // its top
+                copy_bytes(lds, upn, L, t, 64);
+                copy_bytes(lds + (R + 1) * L, dnn, L, t, 64);
+            }
+            if (c == 1 && a.trace) {
+                const int tot = block_sum(sh, red);
+                if (t == 0) atomicAdd(a.trace + sweep, -tot);
+            }
+            __syncthreads();
+        }
+    }
+
+    // write back spins and state
+    copy_bytes(reinterpret_cast<uint8_t *>(a.spins + row0 * L), lds + L, strip_bytes, t, nt);
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+        const uint32_t k = t + i * nt;
+        if (k < a.units) u[i].store(a.st, a.S, ubase + k, 4 * a.n_sweeps);
+    }
+}
+
+// ---------------------------------------------------------------- per pass
+struct PassArgs {
+    int8_t *spins;
+    uint8_t *st;
+    uint64_t S;
+    uint32_t L;
+    int c;
+    uint64_t T4, T8;
+    int32_t *partial;  // one per block, or null
+};
+
+template <class Unit>
+__global__ __launch_bounds__(kBlock) void k_ising_pass(PassArgs a, uint64_t n_units) {
+    constexpr int NB = Unit::kNB;
+    const uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int sh = 0;
+    if (k < n_units) {  // XS1024W: n_units is a multiple of 16, so rows stay whole
+        const uint32_t L = a.L, upr = L / NB;
+        const uint64_t y = k / upr;
+        const uint32_t x0 = static_cast<uint32_t>(k % upr) * NB;
+        const uint64_t row = y * L, up_row = (y == 0 ? L - 1 : y - 1) * static_cast<uint64_t>(L);
+        const uint64_t dn_row = (y == L - 1 ? 0 : y + 1) * static_cast<uint64_t>(L);
+        const uint8_t *sp = reinterpret_cast<const uint8_t *>(a.spins);
+        uint64_t w = lds_run<NB>(sp + row + x0);
+        const uint64_t upw = lds_run<NB>(sp + up_row + x0), dnw = lds_run<NB>(sp + dn_row + x0);
+        const uint32_t lb = sp[row + (x0 == 0 ? L - 1 : x0 - 1)];
+        const uint32_t rb = sp[row + (x0 + NB == L ? 0 : x0 + NB)];
+        const uint64_t m = mismatches<NB>(w, upw, dnw, lb, rb);
+        const int p = static_cast<int>((a.c + y) & 1);
+        Unit u;
+        u.load(a.st, a.S, k);
+        uint32_t rr[NB / 2];
+        u.draw(rr);
+        u.store(a.st, a.S, k, 2);
+#pragma unroll
+        for (int h = 0; h < NB / 2; ++h) sh += metropolis(w, m, p + 2 * h, rr[h], a.T4, a.T8);
+        lds_put<NB>(reinterpret_cast<uint8_t *>(a.spins) + row + x0, w);
+    }
+    if (a.partial) {
+        __shared__ int red[kBlock / 64];
+        const int tot = block_sum(sh, red);
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
+    }
+}
+
+// trace[t] = -(sum of n partials); one block, deterministic order.
+__global__ __launch_bounds__(1024) void k_reduce_partials(const int32_t *partial, uint64_t n, int32_t *out) {
+    __shared__ int red[16];
+    int s = 0;
+    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+    const int tot = block_sum(s, red);
+    if (threadIdx.x == 0) *out = -tot;
+}
+
+// ---------------------------------------------------------------- host side
+constexpr uint32_t kLdsMax = 160 * 1024;
+constexpr uint32_t kMaxThreads = 1024;
+
+template <class Unit, int SPT>
+const void *strip_kernel() { return reinterpret_cast<const void *>(&k_ising_strip<Unit, SPT>); }
+
+template <class Unit>
+const void *strip_kernel_for(int spt) {
+    switch (spt) {
+    case 1: return strip_kernel<Unit, 1>();
+    case 2: return strip_kernel<Unit, 2>();
+    case 4: return strip_kernel<Unit, 4>();
+    case 8: return strip_kernel<Unit, 8>();
+    case 16: return strip_kernel<Unit, 16>();
+    }
+    return nullptr;
+}
+
+template <class Unit>
+hipError_t run_passes(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
+    constexpr int NB = Unit::kNB;
+    const uint64_t L = lat->L, n_units = L * L / NB;
+    const unsigned blocks = static_cast<unsigned>((n_units + kBlock - 1) / kBlock);
+    PassArgs pa{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, 0, T4, T8, nullptr};
+    for (uint64_t t = 0; t < n; ++t) {
+        for (int c = 0; c < 2; ++c) {
+            pa.c = c;
+            pa.partial = (c == 1 && tr) ? lat->d_partial : nullptr;
+            hipLaunchKernelGGL(k_ising_pass<Unit>, dim3(blocks), dim3(kBlock), 0, st, pa, n_units);
+        }
+        if (tr) hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, st, lat->d_partial,
+                                   static_cast<uint64_t>(blocks), tr + t);
     }
     return hipGetLastError();
 }
 
-hipError_t sweeps_xs(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
-    const uint64_t S = lat->gen->S;
-    const unsigned blocks = static_cast<unsigned>((S / 2 + kBlock - 1) / kBlock);
-    for (uint64_t t = 0; t < n; ++t) {
-        int32_t *tt = tr ? tr + t : nullptr;
-        for (int c = 0; c < 2; ++c) {
-            hipLaunchKernelGGL(k_pass_xs, dim3(blocks), dim3(kBlock), 0, st, lat->d_spins, lat->gen->d_state, S,
-                               lat->L, c, T4, T8, tt);
-        }
+template <class Unit>
+hipError_t run_strips(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
+    const IsingPlan &pl = lat->plan;
+    if (tr) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           reinterpret_cast<uint32_t *>(tr), n);
     }
+    if (lat->epoch + 2 * n + 2 >= (1ull << 31)) {  // restart the pass counters before they wrap
+        hipLaunchKernelGGL(k_zero_u32, dim3((pl.nwg + kBlock - 1) / kBlock), dim3(kBlock), 0, st, lat->d_flags,
+                           static_cast<uint64_t>(pl.nwg));
+        lat->epoch = 0;
+    }
+    StripArgs a{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, pl.R, pl.nwg, pl.units, T4, T8, n,
+                tr, lat->d_halo, lat->d_flags, static_cast<uint32_t>(lat->epoch), lat->d_err};
+    void *args[] = {&a};
+    const void *fn = strip_kernel_for<Unit>(pl.spt);
+    hipError_t e;
+    if (pl.nwg == 1)
+        e = hipLaunchKernel(fn, dim3(1), dim3(pl.threads), args, pl.lds, st);
+    else
+        e = hipLaunchCooperativeKernel(fn, dim3(pl.nwg), dim3(pl.threads), args, pl.lds, st);
+    if (e != hipSuccess) return e;
+    lat->epoch += 2 * n;
     return hipGetLastError();
+}
+
+// Try one decomposition into nwg strips; fills *out if it fits on chip.
+template <class Unit>
+bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out) {
+    constexpr uint32_t NB = Unit::kNB;
+    if (nwg == 0 || L % nwg) return false;
+    const uint32_t R = L / nwg;
+    const uint64_t lds = static_cast<uint64_t>(R + 2) * L + 64;
+    if (lds > kLdsMax) return false;
+    const uint64_t sites = static_cast<uint64_t>(R) * L;
+    if (NB == 8 && sites % 128) return false;  // whole XS1024W instances per strip
+    const uint32_t units = static_cast<uint32_t>(sites / NB);
+    int spt = 1;
+    while (spt <= max_spt && (units + spt - 1) / spt > kMaxThreads) spt *= 2;
+    if (spt > max_spt) return false;
+    uint32_t threads = (units + spt - 1) / spt;
+    threads = (threads + 63) / 64 * 64;
+    const void *fn = strip_kernel_for<Unit>(spt);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    (void)hipGetLastError();
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, static_cast<int>(threads), lds) != hipSuccess ||
+        occ < 1) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (static_cast<uint64_t>(occ) * n_cu < nwg) return false;
+    *out = IsingPlan{true, R, nwg, units, static_cast<uint32_t>(spt), threads, static_cast<uint32_t>(lds)};
+    return true;
+}
+
+// Lattices up to 256 x 256 run in one workgroup (barriers stay inside the
+// CU).  Larger ones take the most strips (at most one per CU) that still
+// leave each strip >= 2048 sites, else the fewest strips that fit.
+template <class Unit>
+bool plan_strips(uint32_t L, int max_spt, int n_cu, IsingPlan *out) {
+    *out = IsingPlan{};
+    if (n_cu < 1) return false;
+    if (L <= 256 && try_strips<Unit>(L, 1, max_spt, n_cu, out)) return true;
+    const uint32_t top = std::min<uint32_t>(L, static_cast<uint32_t>(n_cu));
+    for (uint32_t nwg = top; nwg >= 1; --nwg)
+        if (static_cast<uint64_t>(L / nwg) * L >= 2048 && try_strips<Unit>(L, nwg, max_spt, n_cu, out)) return true;
+    for (uint32_t nwg = 1; nwg <= top; ++nwg)
+        if (try_strips<Unit>(L, nwg, max_spt, n_cu, out)) return true;
+    *out = IsingPlan{};
+    return false;
+}
+
+template <class Unit>
+hipError_t run(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
+    if (lat->plan.strips) return run_strips<Unit>(lat, T4, T8, n, tr, st);
+    return run_passes<Unit>(lat, T4, T8, n, tr, st);
 }
 
 }  // namespace
+
+bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
+    switch (kind) {
+    case RNGX_LCG32: return plan_strips<SmallUnit<Lcg32>>(L, 16, n_cu, out);
+    case RNGX_LCG64: return plan_strips<SmallUnit<Lcg64>>(L, 16, n_cu, out);
+    case RNGX_MWC: return plan_strips<SmallUnit<Mwc>>(L, 16, n_cu, out);
+    case RNGX_XORWOW: return plan_strips<SmallUnit<Xorwow>>(L, 16, n_cu, out);
+    case RNGX_PHILOX4X32_10: return plan_strips<PhiloxUnit>(L, 16, n_cu, out);
+    case RNGX_XS1024W: return plan_strips<XsUnit>(L, 16, n_cu, out);
+    }
+    return false;
+}
+
+uint64_t ising_partials(uint32_t L) { return (static_cast<uint64_t>(L) * L / 4 + kBlock - 1) / kBlock; }
 
 hipError_t launch_hot_start(Ising *lat, uint64_t seed, hipStream_t st) {
     const uint64_t n_words = static_cast<uint64_t>(lat->L) * lat->L / 4;
@@ -174,17 +507,23 @@ hipError_t launch_hot_start(Ising *lat, uint64_t seed, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_zero(uint32_t *p, uint64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st) {
     // Thresholds floor(exp(-beta dE) 2^32) in IEEE double on the host.
     const uint64_t T4 = static_cast<uint64_t>(std::floor(std::exp(-4.0 * beta) * 4294967296.0));
     const uint64_t T8 = static_cast<uint64_t>(std::floor(std::exp(-8.0 * beta) * 4294967296.0));
     switch (lat->gen->kind) {
-    case RNGX_LCG32: return sweeps_small<Lcg32>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_LCG64: return sweeps_small<Lcg64>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_MWC: return sweeps_small<Mwc>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_XORWOW: return sweeps_small<Xorwow>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_PHILOX4X32_10: return sweeps_small<Philox>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_XS1024W: return sweeps_xs(lat, T4, T8, n_sweeps, d_trace, st);
+    case RNGX_LCG32: return run<SmallUnit<Lcg32>>(lat, T4, T8, n_sweeps, d_trace, st);
+    case RNGX_LCG64: return run<SmallUnit<Lcg64>>(lat, T4, T8, n_sweeps, d_trace, st);
+    case RNGX_MWC: return run<SmallUnit<Mwc>>(lat, T4, T8, n_sweeps, d_trace, st);
+    case RNGX_XORWOW: return run<SmallUnit<Xorwow>>(lat, T4, T8, n_sweeps, d_trace, st);
+    case RNGX_PHILOX4X32_10: return run<PhiloxUnit>(lat, T4, T8, n_sweeps, d_trace, st);
+    case RNGX_XS1024W: return run<XsUnit>(lat, T4, T8, n_sweeps, d_trace, st);
     }
     return hipErrorInvalidValue;
 }

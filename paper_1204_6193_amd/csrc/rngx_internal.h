@@ -39,12 +39,30 @@ struct Gen {
     const void *owner;  // the lattice that owns this generator, if any
 };
 
+// How a lattice is swept: as strips held on chip by co-resident
+// workgroups (strips = true) or by one launch per colour pass.
+struct IsingPlan {
+    bool strips;
+    uint32_t R;        // rows per strip
+    uint32_t nwg;      // strips = workgroups
+    uint32_t units;    // update units per strip
+    uint32_t spt;      // units per thread
+    uint32_t threads;  // threads per workgroup
+    uint32_t lds;      // dynamic LDS bytes per workgroup
+};
+
 struct Ising {
     uint64_t magic;
     uint32_t L;
     int device;
     int8_t *d_spins;
     Gen *gen;
+    IsingPlan plan;
+    uint8_t *d_halo;     // strips: 2 slots x nwg x 2 rows x L bytes
+    uint32_t *d_flags;   // strips: per-strip pass counters
+    uint32_t *d_err;     // strips: set if a neighbour wait gave up
+    int32_t *d_partial;  // per-pass path: per-block energy partials
+    uint64_t epoch;      // pass counter value the flags have reached
 };
 
 size_t state_bytes(rngx_kind kind, uint64_t S);
@@ -61,6 +79,9 @@ hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
 hipError_t launch_hot_start(Ising *lat, uint64_t seed, hipStream_t st);
 hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st);
+hipError_t launch_zero(uint32_t *p, uint64_t n, hipStream_t st);
+bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out);
+uint64_t ising_partials(uint32_t L);
 
 enum { kOutU32 = 0, kOutF32 = 1, kOutXor = 2 };
 

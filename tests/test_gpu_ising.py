@@ -89,11 +89,35 @@ def test_checkpoint_resume(rngx):
     assert np.array_equal(rngx.ising_get_spins(a), rngx.ising_get_spins(b))
 
 
-@pytest.mark.parametrize("kind", ["xs1024w", "philox4x32_10", "lcg32"])
+@pytest.mark.parametrize("kind", ["xs1024w", "philox4x32_10", "lcg32", "xorwow"])
 def test_large_lattice_parity(rngx, orc, kind):
-    """L = 4096 (the throughput workload) for 2 sweeps, bit-exact."""
+    """L = 4096 (the throughput workload) for 3 sweeps in two calls, bit-exact."""
     print(f"case ising L=4096 {kind}", flush=True)
-    _run_both(rngx, orc, 4096, kind, 0.4, 2)
+    lat = _run_both(rngx, orc, 4096, kind, 0.4, 3, chunks=(2, 1))
+    assert rngx.ising_info(lat)["strips"] == 256
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("L", [368, 512, 1024, 2064])
+def test_multi_strip_parity(rngx, orc, kind, L):
+    """Lattices held as several on-chip strips that exchange halo rows."""
+    print(f"case ising strips {kind} L={L}", flush=True)
+    lat = _run_both(rngx, orc, L, kind, ex.BETA_C, 7, chunks=(4, 3))
+    assert rngx.ising_info(lat)["strips"] > 1
+
+
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "philox4x32_10"])
+def test_per_pass_path_parity(rngx, orc, kind):
+    """L = 8192 does not fit on chip: one launch per colour pass."""
+    print(f"case ising per-pass {kind} L=8192", flush=True)
+    lat = _run_both(rngx, orc, 8192, kind, 0.4, 1)
+    assert rngx.ising_info(lat)["strips"] == 0
+
+
+def test_small_lattices_use_one_workgroup(rngx):
+    for L in (16, 64, 128, 256):
+        for kind in ("lcg32", "xs1024w"):
+            assert rngx.ising_info(rngx.ising_create(L, kind, 1))["strips"] == 1
 
 
 def _exact(L, beta):
