@@ -90,6 +90,8 @@ typedef enum {
 
 typedef struct rngx_gen_s *rngx_gen;     /* opaque; owns the device state of S streams      */
 typedef struct rngx_ising_s *rngx_ising; /* opaque; owns L*L int8 spins and L*L/4 streams    */
+typedef struct rngx_ising_batch_s *rngx_ising_batch; /* opaque; lattices swept together   */
+typedef struct rngx_ragged_s *rngx_ragged;           /* opaque; uneven per-stream requests */
 
 /* Create S = n_streams streams of `kind` seeded from `seed` as above, on the
  * current device.  Seeding runs on the device; the call returns when it is
@@ -130,6 +132,27 @@ rngx_status rng_consume(rngx_gen g, uint32_t *d_xor, uint64_t count_per_stream, 
  * term, Philox by its counter.  The result equals producing and discarding
  * n outputs. */
 rngx_status rng_skip(rngx_gen g, uint64_t n, void *stream);
+
+/* Uneven per-stream requests (streams of very different length served in one
+ * pass, the batched form of rng_fill_u32).  `offsets` (host memory, copied)
+ * holds n_units + 1 non-decreasing element indices, n_units = S, or S/32
+ * instances for XS1024W.  Each rng_fill_ragged_u32 call writes
+ *   small-state kinds: the next offsets[s+1]-offsets[s] outputs of stream s
+ *                      to d_out[offsets[s] ...], in order;
+ *   XS1024W:           len = offsets[g+1]-offsets[g] values of instance g in
+ *                      warp order (step k, lane i at d_out[offsets[g] + 32k+i]);
+ *                      the instance takes ceil(len/32) steps and the lanes
+ *                      of a last partial step are dropped;
+ * and advances the streams accordingly.  Long requests are cut into chunks
+ * whose start states come from jump-ahead, so a call costs two launches on
+ * `stream` whatever the lengths; it may be captured in a HIP graph.  d_out
+ * must be 4-byte aligned and hold offsets[n_units] elements.  The generator
+ * must outlive the plan (rng_destroy returns RNGX_E_BUSY meanwhile).
+ * Errors: RNGX_E_INVALID (wrong count, decreasing offsets, NULL),
+ * RNGX_E_OVERFLOW, RNGX_E_NOMEM. */
+rngx_status rng_ragged_create(rngx_gen g, const uint64_t *offsets, uint64_t n_offsets, rngx_ragged *out);
+rngx_status rng_fill_ragged_u32(rngx_ragged r, uint32_t *d_out, void *stream);
+rngx_status rng_ragged_destroy(rngx_ragged r);
 
 /* Copy the handle's state image (layout above) to host memory.  If host_buf
  * is NULL only *bytes is set to the image size.  Otherwise *bytes must be at
@@ -187,6 +210,23 @@ rngx_status ising_rng(rngx_ising lat, rngx_gen *g);
 
 /* Release the lattice, its spins and its streams. */
 rngx_status ising_destroy(rngx_ising lat);
+
+/* Batched replicas: group n lattices of one kind (distinct handles, one
+ * device) so that one launch sweeps them all -- many independent Ising
+ * replicas of uneven size and temperature, as in the paper's use of one
+ * generator instance per updating thread.  Each ising_batch_run gives
+ * replica i n_sweeps[i] sweeps at betas[i] (finite, >= 0) and, when d_traces
+ * and d_traces[i] are not NULL, its energies in d_traces[i] (n_sweeps[i]
+ * int32, as ising_sweep writes them).  Results equal ising_sweep on each
+ * lattice.  A run is a one-word reset plus one kernel launch on `stream`
+ * and may be captured in a HIP graph.  The lattices must outlive the batch:
+ * ising_destroy returns RNGX_E_BUSY for a lattice that a batch holds.
+ * Errors: RNGX_E_INVALID (n = 0, NULL arrays, unknown or repeated handles,
+ * mixed kinds or devices, bad beta). */
+rngx_status ising_batch_create(const rngx_ising *lats, uint32_t n, const double *betas, const uint64_t *n_sweeps,
+                               int32_t *const *d_traces, rngx_ising_batch *out);
+rngx_status ising_batch_run(rngx_ising_batch b, void *stream);
+rngx_status ising_batch_destroy(rngx_ising_batch b);
 
 /* Description of the calling thread's most recent error ("" if none). */
 const char *rngx_last_error(void);

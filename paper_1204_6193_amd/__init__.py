@@ -33,6 +33,9 @@ SIGNATURES = {
     "rng_fill_f32": (_i32, [_vp, _vp, _u64, _vp]),
     "rng_consume": (_i32, [_vp, _vp, _u64, _vp]),
     "rng_skip": (_i32, [_vp, _u64, _vp]),
+    "rng_ragged_create": (_i32, [_vp, _vp, _u64, ctypes.POINTER(_vp)]),
+    "rng_fill_ragged_u32": (_i32, [_vp, _vp, _vp]),
+    "rng_ragged_destroy": (_i32, [_vp]),
     "rng_get_state": (_i32, [_vp, _vp, ctypes.POINTER(_sz), _vp]),
     "rng_set_state": (_i32, [_vp, _vp, _sz, _vp]),
     "ising_create": (_i32, [ctypes.c_uint32, _i32, _u64, ctypes.POINTER(_vp)]),
@@ -43,6 +46,10 @@ SIGNATURES = {
     "ising_set_spins": (_i32, [_vp, _vp, _vp]),
     "ising_rng": (_i32, [_vp, ctypes.POINTER(_vp)]),
     "ising_destroy": (_i32, [_vp]),
+    "ising_batch_create": (_i32, [ctypes.POINTER(_vp), ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(_u64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "ising_batch_run": (_i32, [_vp, _vp]),
+    "ising_batch_destroy": (_i32, [_vp]),
     "rngx_last_error": (ctypes.c_char_p, []),
 }
 
@@ -154,6 +161,42 @@ def rng_skip(g: Gen, n: int, stream=None):
     _check(load().rng_skip(g.handle, n, _stream(stream)))
 
 
+class Ragged:
+    """A plan of uneven per-stream requests (keeps its generator alive)."""
+
+    def __init__(self, handle, gen, total):
+        self.handle = handle
+        self.gen = gen
+        self.total = total
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.rng_ragged_destroy(self.handle)
+            self.handle = None
+
+    def destroy(self):
+        if self.handle:
+            _check(load().rng_ragged_destroy(self.handle))
+        self.handle = None
+
+
+def rng_ragged_create(g: Gen, offsets) -> Ragged:
+    """offsets: n_units + 1 non-decreasing element indices (host array-like)."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    h = _vp()
+    _check(load().rng_ragged_create(g.handle, off.ctypes.data, off.size, ctypes.byref(h)))
+    return Ragged(h.value, g, int(off[-1]))
+
+
+def rng_fill_ragged_u32(r: Ragged, out, stream=None):
+    _check(load().rng_fill_ragged_u32(r.handle, _dptr(out, r.total, 4), _stream(stream)))
+
+
+def rng_ragged_destroy(r: Ragged):
+    r.destroy()
+
+
 def rng_get_state(g: Gen, stream=None):
     """State image as a numpy uint8 array (layout in include/rngx.h)."""
     import numpy as np
@@ -254,3 +297,44 @@ def ising_rng(lat: Ising) -> Gen:
 
 def ising_destroy(lat: Ising):
     lat.destroy()
+
+
+class IsingBatch:
+    """Lattices swept together by one launch per run (keeps its members alive)."""
+
+    def __init__(self, handle, members, traces):
+        self.handle = handle
+        self.members = members
+        self.traces = traces
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ising_batch_destroy(self.handle)
+            self.handle = None
+
+    def destroy(self):
+        if self.handle:
+            _check(load().ising_batch_destroy(self.handle))
+        self.handle = None
+
+
+def ising_batch_create(lats, betas, n_sweeps, traces=None) -> IsingBatch:
+    """traces: None, or a list of int32 device tensors (or None entries) of n_sweeps[i] elements."""
+    n = len(lats)
+    harr = (_vp * n)(*[l.handle for l in lats])
+    barr = (ctypes.c_double * n)(*[float(b) for b in betas])
+    sarr = (_u64 * n)(*[int(x) for x in n_sweeps])
+    tarr = None
+    if traces is not None:
+        tarr = (_vp * n)(*[_dptr(t, int(x), 4) if t is not None else None for t, x in zip(traces, n_sweeps)])
+    h = _vp()
+    _check(load().ising_batch_create(harr, n, barr, sarr, tarr, ctypes.byref(h)))
+    return IsingBatch(h.value, list(lats), traces)
+
+
+def ising_batch_run(batch: IsingBatch, stream=None):
+    _check(load().ising_batch_run(batch.handle, _stream(stream)))
+
+
+def ising_batch_destroy(batch: IsingBatch):
+    batch.destroy()

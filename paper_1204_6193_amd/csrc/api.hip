@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <unordered_set>
+#include <vector>
 
 #include "rngx_internal.h"
 
@@ -17,6 +18,8 @@ namespace {
 
 constexpr uint64_t kGenMagic = 0x52474E5847454E31ull;    // "RGNXGEN1"
 constexpr uint64_t kIsingMagic = 0x52474E584953474Eull;  // "RGNXISGN"
+constexpr uint64_t kBatchMagic = 0x52474E5842415443ull;  // "RGNXBATC"
+constexpr uint64_t kRaggedMagic = 0x52474E5852414747ull; // "RGNXRAGG"
 constexpr uint64_t kMaxStreams = 1ull << 36;
 constexpr uint32_t kMaxL = 16384;  // |E| <= 2 L^2 must fit int32
 
@@ -51,6 +54,38 @@ rngx_status check_ising(rngx_ising h, Ising **lat) {
     *lat = reinterpret_cast<Ising *>(h);
     if ((*lat)->magic != kIsingMagic) return fail(RNGX_E_INVALID, "corrupt lattice handle");
     return RNGX_OK;
+}
+
+rngx_status check_batch(rngx_ising_batch h, IsingBatch **b) {
+    if (!live(h)) return fail(RNGX_E_INVALID, "unknown or destroyed batch handle");
+    *b = reinterpret_cast<IsingBatch *>(h);
+    if ((*b)->magic != kBatchMagic) return fail(RNGX_E_INVALID, "corrupt batch handle");
+    return RNGX_OK;
+}
+
+rngx_status check_ragged(rngx_ragged h, Ragged **r) {
+    if (!live(h)) return fail(RNGX_E_INVALID, "unknown or destroyed ragged plan");
+    *r = reinterpret_cast<Ragged *>(h);
+    if ((*r)->magic != kRaggedMagic) return fail(RNGX_E_INVALID, "corrupt ragged plan");
+    return RNGX_OK;
+}
+
+void free_ragged(Ragged *r) {
+    (void)hipFree(r->d_items);
+    (void)hipFree(r->d_scratch);
+    (void)hipFree(r->d_t64);
+    (void)hipFree(r->d_t32);
+    r->magic = 0;
+    delete r;
+}
+
+void free_batch(IsingBatch *b) {
+    (void)hipFree(b->d_reps);
+    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_next);
+    delete[] b->lats;
+    b->magic = 0;
+    delete b;
 }
 
 rngx_status alloc_gen(rngx_kind kind, uint64_t S, Gen **out) {
@@ -169,6 +204,7 @@ rngx_status rng_destroy(rngx_gen h) {
     Gen *g;
     if (rngx_status s = check_gen(h, &g)) return s;
     if (g->owner) return fail(RNGX_E_INVALID, "this generator belongs to a lattice; destroy the lattice instead");
+    if (g->plans) return fail(RNGX_E_BUSY, "a ragged plan still holds this generator; destroy it first");
     DeviceScope ds(g->device);
     (void)hipDeviceSynchronize();
     unreg(g);
@@ -205,6 +241,76 @@ rngx_status rng_skip(rngx_gen h, uint64_t n, void *stream) {
     DeviceScope ds(g->device);
     hipError_t e = launch_skip(g, n, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "skip kernel launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_offsets, rngx_ragged *out) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (!offsets || !out) return fail(RNGX_E_INVALID, "NULL argument");
+    const uint64_t units = g->kind == RNGX_XS1024W ? g->S / 32 : g->S;
+    if (n_offsets != units + 1)
+        return fail(RNGX_E_INVALID, "need " + std::to_string(units + 1) + " offsets, got " + std::to_string(n_offsets));
+    for (uint64_t u = 0; u < units; ++u)
+        if (offsets[u + 1] < offsets[u]) return fail(RNGX_E_INVALID, "offsets decrease at " + std::to_string(u));
+    uint64_t bytes;
+    if (mul_overflows(offsets[units], 4, &bytes)) return fail(RNGX_E_OVERFLOW, "output size overflows");
+    std::vector<RaggedItem> items;
+    uint64_t max_chunks = 1;
+    ragged_plan(g->kind, offsets, units, &items, &max_chunks);
+    std::vector<uint64_t> t64;
+    std::vector<uint32_t> t32;
+    jump_table(g->kind, ragged_chunk(g->kind), max_chunks, &t64, &t32);
+    DeviceScope ds(g->device);
+    Ragged *r = new Ragged{};
+    r->magic = kRaggedMagic;
+    r->gen = g;
+    r->n_items = items.size();
+    r->total = offsets[units];
+    hipError_t e = hipSuccess;
+    if (!items.empty()) {
+        e = hipMalloc(&r->d_items, sizeof(RaggedItem) * items.size());
+        if (e == hipSuccess) e = hipMalloc(&r->d_scratch, ragged_scratch_bytes(g->kind, items.size()));
+        if (e == hipSuccess && !t64.empty()) e = hipMalloc(&r->d_t64, 8 * t64.size());
+        if (e == hipSuccess && !t32.empty()) e = hipMalloc(&r->d_t32, 4 * t32.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(r->d_items, items.data(), sizeof(RaggedItem) * items.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !t64.empty()) e = hipMemcpy(r->d_t64, t64.data(), 8 * t64.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !t32.empty()) e = hipMemcpy(r->d_t32, t32.data(), 4 * t32.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        free_ragged(r);
+        (void)hipGetLastError();
+        return fail(RNGX_E_NOMEM, std::string("ragged plan allocation failed: ") + hipGetErrorString(e));
+    }
+    ++g->plans;
+    reg(r);
+    *out = reinterpret_cast<rngx_ragged>(r);
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_fill_ragged_u32(rngx_ragged h, uint32_t *d_out, void *stream) {
+    Ragged *r;
+    if (rngx_status s = check_ragged(h, &r)) return s;
+    if (!d_out && r->total) return fail(RNGX_E_INVALID, "output pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(d_out) % 4) return fail(RNGX_E_ALIGN, "output must be 4-byte aligned");
+    DeviceScope ds(r->gen->device);
+    hipError_t e = launch_ragged(r, d_out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "ragged fill launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_ragged_destroy(rngx_ragged h) {
+    Ragged *r;
+    if (rngx_status s = check_ragged(h, &r)) return s;
+    DeviceScope ds(r->gen->device);
+    (void)hipDeviceSynchronize();
+    --r->gen->plans;
+    unreg(r);
+    free_ragged(r);
     clear_error();
     return RNGX_OK;
 }
@@ -374,9 +480,70 @@ rngx_status ising_rng(rngx_ising h, rngx_gen *g) {
     return RNGX_OK;
 }
 
+rngx_status ising_batch_create(const rngx_ising *lats, uint32_t n, const double *betas, const uint64_t *n_sweeps,
+                               int32_t *const *d_traces, rngx_ising_batch *out) {
+    if (!out || !lats || !betas || !n_sweeps) return fail(RNGX_E_INVALID, "NULL argument");
+    if (n == 0) return fail(RNGX_E_INVALID, "a batch needs at least one lattice");
+    std::vector<Ising *> members(n);
+    std::unordered_set<const void *> seen;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (rngx_status s = check_ising(lats[i], &members[i])) return s;
+        if (!seen.insert(members[i]).second) return fail(RNGX_E_INVALID, "lattice " + std::to_string(i) + " repeats");
+        if (members[i]->gen->kind != members[0]->gen->kind) return fail(RNGX_E_INVALID, "mixed generator kinds");
+        if (members[i]->device != members[0]->device) return fail(RNGX_E_INVALID, "lattices on different devices");
+        if (!std::isfinite(betas[i]) || betas[i] < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");
+        if (d_traces && d_traces[i] && reinterpret_cast<uintptr_t>(d_traces[i]) % 4)
+            return fail(RNGX_E_ALIGN, "traces must be 4-byte aligned");
+    }
+    DeviceScope ds(members[0]->device);
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, members[0]->device) != hipSuccess)
+        return hip_fail(hipErrorInvalidDevice, "device query");
+    IsingBatch *b = new IsingBatch{};
+    b->magic = kBatchMagic;
+    b->device = members[0]->device;
+    b->kind = members[0]->gen->kind;
+    b->n = n;
+    b->lats = new Ising *[n];
+    for (uint32_t i = 0; i < n; ++i) b->lats[i] = members[i];
+    hipError_t e = batch_prepare(b, members.data(), betas, n_sweeps, d_traces, n_cu);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return hip_fail(e, "batch preparation");
+    }
+    for (uint32_t i = 0; i < n; ++i) ++members[i]->batches;
+    reg(b);
+    *out = reinterpret_cast<rngx_ising_batch>(b);
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_batch_run(rngx_ising_batch h, void *stream) {
+    IsingBatch *b;
+    if (rngx_status s = check_batch(h, &b)) return s;
+    DeviceScope ds(b->device);
+    hipError_t e = launch_batch(b, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_batch_destroy(rngx_ising_batch h) {
+    IsingBatch *b;
+    if (rngx_status s = check_batch(h, &b)) return s;
+    DeviceScope ds(b->device);
+    (void)hipDeviceSynchronize();
+    for (uint32_t i = 0; i < b->n; ++i) --b->lats[i]->batches;
+    unreg(b);
+    free_batch(b);
+    clear_error();
+    return RNGX_OK;
+}
+
 rngx_status ising_destroy(rngx_ising h) {
     Ising *lat;
     if (rngx_status s = check_ising(h, &lat)) return s;
+    if (lat->batches) return fail(RNGX_E_BUSY, "a batch still holds this lattice; destroy the batch first");
     DeviceScope ds(lat->device);
     (void)hipDeviceSynchronize();
     unreg(lat);

@@ -25,6 +25,7 @@
 // end, so E = -sum over colour-1 sites of s h = -sum (4 - 2 m_after).
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "rngx_internal.h"
 
@@ -153,6 +154,15 @@ __device__ __forceinline__ void lds_put(uint8_t *p, uint64_t w) {
 }
 
 // ---------------------------------------------------------------- strips
+struct ReplicaDesc {
+    int8_t *spins;
+    uint8_t *st;
+    uint64_t S;
+    uint32_t L, on_chip;
+    uint64_t T4, T8, n_sweeps;
+    int32_t *trace;  // may be null
+};
+
 struct StripArgs {
     int8_t *spins;
     uint8_t *st;
@@ -215,18 +225,17 @@ __device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint64_t 
     return off;
 }
 
+// All sweeps of strip r (R rows at row r*R) held in `lds` ((R+2)*L + 80
+// bytes: rows, block-sum scratch, a zero word) by the calling workgroup.
 template <class Unit, int SPT>
-__global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
+__device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8_t *lds) {
     constexpr int NB = Unit::kNB;
-    extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t L = a.L, R = a.R, nwg = a.nwg, t = threadIdx.x, nt = blockDim.x;
-    // Blocks b, b+8, b+16, ... share an XCD: give them consecutive strips so
-    // that most neighbour exchanges stay inside one L2.
-    const uint32_t b = blockIdx.x;
-    const uint32_t r = (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
     const uint64_t row0 = static_cast<uint64_t>(r) * R;
     const uint32_t strip_bytes = R * L;
     int *red = reinterpret_cast<int *>(lds + (R + 2) * L);
+    uint32_t *zero_word = reinterpret_cast<uint32_t *>(lds + (R + 2) * L + 64);
+    if (t == 0) *zero_word = 0;
 
     // strip and initial halo rows from the lattice
     const int8_t *gs = a.spins;
@@ -253,12 +262,15 @@ __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
     for (uint64_t sweep = 0; sweep < a.n_sweeps; ++sweep) {
         for (int c = 0; c < 2; ++c, ++q) {
             int sh = 0;
+            const uint32_t zero = *zero_word;
 #pragma unroll
             for (int i = 0; i < SPT; ++i) {
                 const uint32_t k = t + i * nt;
                 if (k < a.units) {
-                    uint32_t pl = place[i];
-                    asm volatile("" : "+v"(pl));  // recompute addresses here rather than hold them per unit
+                    // `zero` is reloaded from LDS every pass, so the addresses
+                    // below cannot be hoisted out of the sweep loop and held
+                    // per unit in registers.
+                    const uint32_t pl = place[i] + zero;
                     const uint32_t off = pl & 0x1FFFFFFFu;
                     uint64_t w = lds_run<NB>(lds + off);
                     const uint64_t upw = lds_run<NB>(lds + off - L), dnw = lds_run<NB>(lds + off + L);
@@ -299,7 +311,10 @@ __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
             }
             if (c == 1 && a.trace) {
                 const int tot = block_sum(sh, red);
-                if (t == 0) atomicAdd(a.trace + sweep, -tot);
+                if (t == 0) {
+                    if (nwg == 1) a.trace[sweep] = -tot;  // the only contributor
+                    else atomicAdd(a.trace + sweep, -tot);
+                }
             }
             __syncthreads();
         }
@@ -314,6 +329,16 @@ __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
     }
 }
 
+template <class Unit, int SPT>
+__global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    // Blocks b, b+8, b+16, ... share an XCD: give them consecutive strips so
+    // that most neighbour exchanges stay inside one L2.
+    const uint32_t b = blockIdx.x, nwg = a.nwg;
+    const uint32_t r = (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
+    strip_body<Unit, SPT>(a, r, lds);
+}
+
 // ---------------------------------------------------------------- per pass
 struct PassArgs {
     int8_t *spins;
@@ -325,37 +350,102 @@ struct PassArgs {
     int32_t *partial;  // one per block, or null
 };
 
+// Update unit k of colour c with spins and state in global memory; returns
+// the sum of s*h over the updated sites.  A unit reads only other-colour
+// bytes of its neighbour runs, which no thread writes during the pass.
+template <class Unit>
+__device__ __forceinline__ int unit_in_memory(uint8_t *sp, uint8_t *st, uint64_t S, uint32_t L, uint64_t k, int c,
+                                              uint64_t T4, uint64_t T8) {
+    constexpr int NB = Unit::kNB;
+    const uint32_t upr = L / NB;
+    const uint64_t y = k / upr;
+    const uint32_t x0 = static_cast<uint32_t>(k % upr) * NB;
+    const uint64_t row = y * L, up_row = (y == 0 ? L - 1 : y - 1) * static_cast<uint64_t>(L);
+    const uint64_t dn_row = (y == L - 1 ? 0 : y + 1) * static_cast<uint64_t>(L);
+    uint64_t w = lds_run<NB>(sp + row + x0);
+    const uint64_t upw = lds_run<NB>(sp + up_row + x0), dnw = lds_run<NB>(sp + dn_row + x0);
+    const uint32_t lb = sp[row + (x0 == 0 ? L - 1 : x0 - 1)];
+    const uint32_t rb = sp[row + (x0 + NB == L ? 0 : x0 + NB)];
+    const uint64_t m = mismatches<NB>(w, upw, dnw, lb, rb);
+    const int p = static_cast<int>((c + y) & 1);
+    Unit u;
+    u.load(st, S, k);
+    uint32_t rr[NB / 2];
+    u.draw(rr);
+    u.store(st, S, k, 2);
+    int sh = 0;
+#pragma unroll
+    for (int h = 0; h < NB / 2; ++h) sh += metropolis(w, m, p + 2 * h, rr[h], T4, T8);
+    lds_put<NB>(sp + row + x0, w);
+    return sh;
+}
+
 template <class Unit>
 __global__ __launch_bounds__(kBlock) void k_ising_pass(PassArgs a, uint64_t n_units) {
-    constexpr int NB = Unit::kNB;
     const uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     int sh = 0;
-    if (k < n_units) {  // XS1024W: n_units is a multiple of 16, so rows stay whole
-        const uint32_t L = a.L, upr = L / NB;
-        const uint64_t y = k / upr;
-        const uint32_t x0 = static_cast<uint32_t>(k % upr) * NB;
-        const uint64_t row = y * L, up_row = (y == 0 ? L - 1 : y - 1) * static_cast<uint64_t>(L);
-        const uint64_t dn_row = (y == L - 1 ? 0 : y + 1) * static_cast<uint64_t>(L);
-        const uint8_t *sp = reinterpret_cast<const uint8_t *>(a.spins);
-        uint64_t w = lds_run<NB>(sp + row + x0);
-        const uint64_t upw = lds_run<NB>(sp + up_row + x0), dnw = lds_run<NB>(sp + dn_row + x0);
-        const uint32_t lb = sp[row + (x0 == 0 ? L - 1 : x0 - 1)];
-        const uint32_t rb = sp[row + (x0 + NB == L ? 0 : x0 + NB)];
-        const uint64_t m = mismatches<NB>(w, upw, dnw, lb, rb);
-        const int p = static_cast<int>((a.c + y) & 1);
-        Unit u;
-        u.load(a.st, a.S, k);
-        uint32_t rr[NB / 2];
-        u.draw(rr);
-        u.store(a.st, a.S, k, 2);
-#pragma unroll
-        for (int h = 0; h < NB / 2; ++h) sh += metropolis(w, m, p + 2 * h, rr[h], a.T4, a.T8);
-        lds_put<NB>(reinterpret_cast<uint8_t *>(a.spins) + row + x0, w);
-    }
+    if (k < n_units)  // XS1024W: n_units is a multiple of 16, so rows stay whole
+        sh = unit_in_memory<Unit>(reinterpret_cast<uint8_t *>(a.spins), a.st, a.S, a.L, k, a.c, a.T4, a.T8);
     if (a.partial) {
         __shared__ int red[kBlock / 64];
         const int tot = block_sum(sh, red);
         if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
+    }
+}
+
+// ---------------------------------------------------------------- batches
+// A batch is a fixed list of replicas (same kind) swept in one launch: each
+// workgroup takes the next replica from a counter (replicas ordered by
+// decreasing work) and runs all its sweeps alone -- on chip when the
+// lattice fits, otherwise streaming it through memory -- so no workgroup
+// ever waits for another.
+template <class Unit>
+__device__ void replica_in_memory(const ReplicaDesc &d, int *red) {
+    constexpr int NB = Unit::kNB;
+    const uint64_t n_units = static_cast<uint64_t>(d.L) * d.L / NB;
+    uint8_t *sp = reinterpret_cast<uint8_t *>(d.spins);
+    for (uint64_t sweep = 0; sweep < d.n_sweeps; ++sweep) {
+        for (int c = 0; c < 2; ++c) {
+            int sh = 0;
+            // XS1024W: n_units and blockDim are multiples of 16, rows stay whole
+            for (uint64_t k = threadIdx.x; k < n_units; k += blockDim.x)
+                sh += unit_in_memory<Unit>(sp, d.st, d.S, d.L, k, c, d.T4, d.T8);
+            __syncthreads();
+            if (c == 1 && d.trace) {
+                const int tot = block_sum(sh, red);
+                if (threadIdx.x == 0) d.trace[sweep] = -tot;
+            }
+        }
+    }
+}
+
+// Units per thread of an on-chip replica (at most 16384 four-site or 8192
+// eight-site units, i.e. L <= 256, with 1024 threads).
+template <class Unit>
+constexpr int batch_spt() { return Unit::kNB == 8 ? 8 : 16; }
+constexpr uint32_t kBatchThreads = 1024;
+
+template <class Unit>
+__global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc *reps, const uint32_t *order, uint32_t n,
+                                                              uint32_t *next) {
+    constexpr int NB = Unit::kNB;
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t idx_s;
+    __shared__ int red_s[16];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) idx_s = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint32_t idx = idx_s;
+        if (idx >= n) break;  // every workgroup leaves once the list is drained
+        const ReplicaDesc d = reps[order[idx]];
+        if (d.on_chip) {
+            const StripArgs a{d.spins, d.st, d.S, d.L, d.L, 1, static_cast<uint32_t>(static_cast<uint64_t>(d.L) * d.L / NB),
+                              d.T4, d.T8, d.n_sweeps, d.trace, nullptr, nullptr, 0, nullptr};
+            strip_body<Unit, batch_spt<Unit>()>(a, 0, lds);
+        } else {
+            replica_in_memory<Unit>(d, red_s);
+        }
     }
 }
 
@@ -408,7 +498,7 @@ hipError_t run_passes(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t 
 template <class Unit>
 hipError_t run_strips(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
     const IsingPlan &pl = lat->plan;
-    if (tr) {
+    if (tr && pl.nwg > 1) {
         hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                            reinterpret_cast<uint32_t *>(tr), n);
     }
@@ -437,7 +527,7 @@ bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out)
     constexpr uint32_t NB = Unit::kNB;
     if (nwg == 0 || L % nwg) return false;
     const uint32_t R = L / nwg;
-    const uint64_t lds = static_cast<uint64_t>(R + 2) * L + 64;
+    const uint64_t lds = static_cast<uint64_t>(R + 2) * L + 80;
     if (lds > kLdsMax) return false;
     const uint64_t sites = static_cast<uint64_t>(R) * L;
     if (NB == 8 && sites % 128) return false;  // whole XS1024W instances per strip
@@ -484,7 +574,81 @@ hipError_t run(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hi
     return run_passes<Unit>(lat, T4, T8, n, tr, st);
 }
 
+constexpr uint32_t kBatchLdsCap = 80 * 1024;  // keeps two batch workgroups per CU
+
+template <class Unit>
+const void *batch_kernel() { return reinterpret_cast<const void *>(&k_ising_batch<Unit>); }
+
+const void *batch_kernel_for(rngx_kind kind) {
+    switch (kind) {
+    case RNGX_LCG32: return batch_kernel<SmallUnit<Lcg32>>();
+    case RNGX_LCG64: return batch_kernel<SmallUnit<Lcg64>>();
+    case RNGX_MWC: return batch_kernel<SmallUnit<Mwc>>();
+    case RNGX_XORWOW: return batch_kernel<SmallUnit<Xorwow>>();
+    case RNGX_PHILOX4X32_10: return batch_kernel<PhiloxUnit>();
+    case RNGX_XS1024W: return batch_kernel<XsUnit>();
+    }
+    return nullptr;
+}
+
+uint64_t threshold(double beta, int dE) {
+    return static_cast<uint64_t>(std::floor(std::exp(-beta * dE) * 4294967296.0));
+}
+
 }  // namespace
+
+hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas, const uint64_t *n_sweeps,
+                         int32_t *const *traces, int n_cu) {
+    const uint32_t n = b->n;
+    const uint32_t nb = b->kind == RNGX_XS1024W ? 8 : 4;
+    std::vector<ReplicaDesc> reps(n);
+    uint32_t lds = 80;
+    for (uint32_t i = 0; i < n; ++i) {
+        const Ising *l = lats[i];
+        const uint64_t L = l->L, units = L * L / nb, bytes = (L + 2) * L + 80;
+        const uint64_t spt = nb == 8 ? 8 : 16;
+        const bool on_chip = units <= spt * kBatchThreads && bytes <= kBatchLdsCap;
+        reps[i] = ReplicaDesc{l->d_spins, l->gen->d_state, l->gen->S, l->L, on_chip ? 1u : 0u,
+                              threshold(betas[i], 4), threshold(betas[i], 8), n_sweeps[i], traces ? traces[i] : nullptr};
+        if (on_chip) lds = std::max<uint32_t>(lds, static_cast<uint32_t>(bytes));
+    }
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return static_cast<double>(reps[x].L) * reps[x].L * reps[x].n_sweeps >
+               static_cast<double>(reps[y].L) * reps[y].L * reps[y].n_sweeps;
+    });
+    const void *fn = batch_kernel_for(b->kind);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    (void)hipGetLastError();
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBatchThreads, lds);
+    if (e != hipSuccess) return e;
+    if (occ < 1) return hipErrorOutOfMemory;
+    b->lds = lds;
+    b->grid = std::min<uint32_t>(n, static_cast<uint32_t>(occ * std::max(n_cu, 1)));
+    if ((e = hipMalloc(&b->d_reps, sizeof(ReplicaDesc) * n)) != hipSuccess) return e;
+    if ((e = hipMalloc(&b->d_order, 4ull * n)) != hipSuccess) return e;
+    if ((e = hipMalloc(&b->d_next, 4)) != hipSuccess) return e;
+    if ((e = hipMemcpy(b->d_reps, reps.data(), sizeof(ReplicaDesc) * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    return hipMemcpy(b->d_order, order.data(), 4ull * n, hipMemcpyHostToDevice);
+}
+
+hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
+    if (b->n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, st, b->d_next, static_cast<uint64_t>(1));
+    const dim3 grid(b->grid), block(kBatchThreads);
+    const auto *reps = static_cast<const ReplicaDesc *>(b->d_reps);
+    switch (b->kind) {
+    case RNGX_LCG32: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg32>>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
+    case RNGX_LCG64: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg64>>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
+    case RNGX_MWC: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Mwc>>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
+    case RNGX_XORWOW: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Xorwow>>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
+    case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ising_batch<PhiloxUnit>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
+    case RNGX_XS1024W: hipLaunchKernelGGL(k_ising_batch<XsUnit>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
+    }
+    return hipGetLastError();
+}
 
 bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
     switch (kind) {

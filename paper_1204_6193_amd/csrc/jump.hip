@@ -79,6 +79,15 @@ Poly x_pow_mod(uint64_t n, const Poly &P) {
     return r;
 }
 
+// a * b mod P (carry-less product, then reduction).
+Poly poly_mulmod(const Poly &a, const Poly &b, const Poly &P) {
+    Poly r(a.size() + b.size() + 1, 0);
+    for (size_t w = 0; w < a.size(); ++w)
+        for (int i = 0; i < 64; ++i)
+            if ((a[w] >> i) & 1u) poly_xor_shifted(r, b, static_cast<int>(64 * w + i));
+    return poly_mod(r, P);
+}
+
 // Minimal polynomial of a bit sequence (Berlekamp-Massey), as x^L C(1/x).
 Poly berlekamp_massey(const std::vector<uint8_t> &s, int words) {
     const int n = static_cast<int>(s.size());
@@ -168,7 +177,6 @@ const Poly &xorwow_minpoly() {
 struct JumpPoly1024 { uint32_t c[32]; };  // coefficient i at bit i%32 of c[i/32]
 struct JumpPoly160 { uint32_t c[5]; };
 
-__device__ __forceinline__ bool coef(const uint32_t *c, int i) { return (c[i >> 5] >> (i & 31)) & 1u; }
 
 __global__ __launch_bounds__(kBlock) void k_skip_affine32(uint32_t *x, uint64_t S, uint32_t A, uint32_t C) {
     const uint64_t s = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -179,21 +187,9 @@ __global__ __launch_bounds__(kBlock) void k_skip_affine64(uint64_t *x, uint64_t 
     if (s < S) x[s] = A * x[s] + C;
 }
 
-// y * A mod p for p = a 2^32 - 1, using 2^64 = R (mod p), R = 2^64 - p < 2^41.
-__device__ __forceinline__ uint64_t mulmod_p(uint64_t y, uint64_t A) {
-    constexpr uint64_t R = 0ull - kMwcP;  // 2^64 - p
-    uint64_t lo = y * A, hi = __umul64hi(y, A);
-    while (hi) {  // (hi, lo) <- hi * R + lo; hi shrinks by >= 23 bits a round
-        const uint64_t plo = hi * R, phi = __umul64hi(hi, R);
-        const uint64_t s = plo + lo;
-        hi = phi + (s < plo ? 1 : 0);
-        lo = s;
-    }
-    return lo >= kMwcP ? lo - kMwcP : lo;
-}
 __global__ __launch_bounds__(kBlock) void k_skip_mwc(uint64_t *y, uint64_t S, uint64_t A) {
     const uint64_t s = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s < S) y[s] = mulmod_p(y[s], A);
+    if (s < S) y[s] = mwc_mulmod(y[s], A);
 }
 
 __global__ __launch_bounds__(kBlock) void k_skip_philox(uint64_t *pos, uint64_t S, uint64_t n) {
@@ -204,16 +200,10 @@ __global__ __launch_bounds__(kBlock) void k_skip_philox(uint64_t *pos, uint64_t 
 __global__ __launch_bounds__(kBlock) void k_skip_xorwow(uint32_t *st, uint64_t S, JumpPoly160 J, uint32_t dAdd) {
     const uint64_t s = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= S) return;
-    uint32_t v[5], acc[5] = {0, 0, 0, 0, 0};
+    uint32_t v[5];
     for (int i = 0; i < 5; ++i) v[i] = st[i * S + s];
-    for (int i = 159; i >= 0; --i) {  // acc <- M acc + c_i v
-        const uint32_t t = acc[0] ^ (acc[0] >> 2);
-        acc[0] = acc[1]; acc[1] = acc[2]; acc[2] = acc[3]; acc[3] = acc[4];
-        acc[4] = (acc[4] ^ (acc[4] << 4)) ^ (t ^ (t << 1));
-        if (coef(J.c, i))
-            for (int q = 0; q < 5; ++q) acc[q] ^= v[q];
-    }
-    for (int i = 0; i < 5; ++i) st[i * S + s] = acc[i];
+    xorwow_apply_poly(J.c, v);
+    for (int i = 0; i < 5; ++i) st[i * S + s] = v[i];
     st[5 * S + s] += dAdd;
 }
 
@@ -223,11 +213,8 @@ __global__ __launch_bounds__(kBlock) void k_skip_xs(uint8_t *st, uint64_t S, Jum
     if (g >= G) return;  // whole 16-lane rows
     uint2 *W = reinterpret_cast<uint2 *>(st);
     const uint2 w = W[t];
-    uint32_t a = 0, b = 0;
-    for (int i = 1023; i >= 0; --i) {
-        xs1024_step(a, b);
-        if (coef(J.c, i)) { a ^= w.x; b ^= w.y; }
-    }
+    uint32_t a = w.x, b = w.y;
+    xs1024_apply_poly(J.c, a, b);
     W[t] = make_uint2(a, b);
     if ((t & 15) == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[g] += n;
 }
@@ -248,7 +235,53 @@ uint64_t host_powmod_p(uint64_t a, uint64_t n) {
 
 unsigned blocks_for(uint64_t threads) { return static_cast<unsigned>((threads + kBlock - 1) / kBlock); }
 
+template <int NBITS>
+void poly_table(const Poly &P, uint64_t step, uint64_t count, std::vector<uint32_t> *out) {
+    constexpr int NW = NBITS / 32;
+    out->assign(count * NW, 0);
+    const Poly xs = x_pow_mod(step, P);
+    Poly cur(P.size(), 0);
+    cur[0] = 1;  // x^0
+    for (uint64_t j = 0; j < count; ++j) {
+        for (int i = 0; i < NBITS; ++i)
+            if (poly_bit(cur, i)) (*out)[j * NW + i / 32] |= 1u << (i % 32);
+        cur = poly_mulmod(cur, xs, P);
+    }
+}
+
 }  // namespace
+
+void jump_table(rngx_kind kind, uint64_t step, uint64_t count, std::vector<uint64_t> *u64s,
+                std::vector<uint32_t> *u32s) {
+    u64s->clear();
+    u32s->clear();
+    switch (kind) {
+    case RNGX_LCG32:
+    case RNGX_LCG64: {
+        const Aff f = kind == RNGX_LCG32 ? Aff{kLcg32A, kLcg32C} : Aff{kLcg64A, kLcg64C};
+        const Aff fs = aff_pow(f, step);
+        Aff cur{1, 0};
+        for (uint64_t j = 0; j < count; ++j) {
+            u64s->push_back(cur.a);
+            u64s->push_back(cur.c);
+            cur = aff_after(fs, cur);
+        }
+        break;
+    }
+    case RNGX_MWC: {
+        const unsigned __int128 as = host_powmod_p(kMwcA, step);
+        unsigned __int128 cur = 1;
+        for (uint64_t j = 0; j < count; ++j) {
+            u64s->push_back(static_cast<uint64_t>(cur));
+            cur = (cur * as) % kMwcP;
+        }
+        break;
+    }
+    case RNGX_XORWOW: poly_table<160>(xorwow_minpoly(), step, count, u32s); break;
+    case RNGX_XS1024W: poly_table<1024>(xs1024_minpoly(), step, count, u32s); break;
+    case RNGX_PHILOX4X32_10: break;
+    }
+}
 
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st) {
     const uint64_t S = g->S;

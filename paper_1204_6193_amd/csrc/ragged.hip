@@ -1,0 +1,201 @@
+// Uneven ("ragged") fills: every stream receives a request of its own length
+// in one launch pair, however long or short the requests are.
+//
+// Stream s (small-state kinds) writes its next len_s outputs to
+// out[off_s .. off_s + len_s); XS1024W instance g writes len_g values in warp
+// order (step k, lane i -> out[off_g + 32 k + i]), taking ceil(len_g / 32)
+// steps and dropping the lanes of a last partial step.
+//
+// A request is cut into chunks of C outputs (XS1024W: C instance steps) so
+// that long requests spread over many threads.  The first kernel puts the
+// start state of every chunk j into scratch by jumping the stream's state by
+// j*C (precomputed powers of the C-step map: affine pairs, a^(jC) mod p, or
+// GF(2) polynomials x^(jC) mod P applied by Horner's rule); the second
+// kernel generates every chunk from its start state, and the last chunk of a
+// stream writes the stream's final state back.
+#include <algorithm>
+#include <vector>
+
+#include "rngx_internal.h"
+
+namespace rngx {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <class G>
+__global__ __launch_bounds__(kBlock) void k_ragged_gen_small(const RaggedItem *items, uint64_t n_items,
+                                                              const uint8_t *scratch, uint8_t *st, uint64_t S,
+                                                              uint32_t *out) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const RaggedItem it = items[i];
+    G g;
+    g.load(scratch, n_items, i);
+    uint32_t *o = out + it.out;
+    for (uint32_t k = 0; k < it.len; ++k) o[k] = g.next();
+    if (it.last) g.store(st, S, it.unit);
+}
+
+// Start states of the chunks of the small-state kinds, written to scratch in
+// the kind's structure-of-arrays layout with n_items streams.
+__global__ __launch_bounds__(kBlock) void k_ragged_start_small(rngx_kind kind, const RaggedItem *items,
+                                                                uint64_t n_items, const uint8_t *st, uint64_t S,
+                                                                uint8_t *scratch, const uint64_t *t64,
+                                                                const uint32_t *t32, uint64_t chunk) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    const RaggedItem it = items[i];
+    const uint64_t s = it.unit, j = it.j;
+    switch (kind) {
+    case RNGX_LCG32: {
+        const uint32_t x = reinterpret_cast<const uint32_t *>(st)[s];
+        reinterpret_cast<uint32_t *>(scratch)[i] =
+            static_cast<uint32_t>(t64[2 * j]) * x + static_cast<uint32_t>(t64[2 * j + 1]);
+        break;
+    }
+    case RNGX_LCG64: {
+        const uint64_t x = reinterpret_cast<const uint64_t *>(st)[s];
+        reinterpret_cast<uint64_t *>(scratch)[i] = t64[2 * j] * x + t64[2 * j + 1];
+        break;
+    }
+    case RNGX_MWC: {
+        const uint64_t y = reinterpret_cast<const uint64_t *>(st)[s];
+        reinterpret_cast<uint64_t *>(scratch)[i] = mwc_mulmod(y, t64[j]);
+        break;
+    }
+    case RNGX_XORWOW: {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
+        uint32_t v[5];
+        for (int q = 0; q < 5; ++q) v[q] = p[q * S + s];
+        if (j) xorwow_apply_poly(t32 + 5 * j, v);
+        uint32_t *o = reinterpret_cast<uint32_t *>(scratch);
+        for (int q = 0; q < 5; ++q) o[q * n_items + i] = v[q];
+        o[5 * n_items + i] = p[5 * S + s] + static_cast<uint32_t>(j * chunk) * kWeylC;
+        break;
+    }
+    case RNGX_PHILOX4X32_10: {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
+        uint32_t *o = reinterpret_cast<uint32_t *>(scratch);
+        o[i] = p[s];
+        o[n_items + i] = p[S + s];
+        reinterpret_cast<uint64_t *>(scratch + 8 * n_items)[i] =
+            reinterpret_cast<const uint64_t *>(st + 8 * S)[s] + j * chunk;
+        break;
+    }
+    default: break;
+    }
+}
+
+// XS1024W: 16 lanes (one DPP row) per chunk.  Scratch holds, per item, the
+// 32 words (as 16 lane pairs) and the step counter.
+__global__ __launch_bounds__(kBlock) void k_ragged_start_xs(const RaggedItem *items, uint64_t n_items,
+                                                             const uint8_t *st, uint64_t S, uint8_t *scratch,
+                                                             const uint32_t *t32, uint64_t chunk) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t i = t >> 4, lane = t & 15;
+    if (i >= n_items) return;  // whole rows
+    const RaggedItem it = items[i];
+    const uint2 w = reinterpret_cast<const uint2 *>(st)[16 * it.unit + lane];
+    uint32_t a = w.x, b = w.y;
+    if (it.j) xs1024_apply_poly(t32 + 32 * it.j, a, b);
+    reinterpret_cast<uint2 *>(scratch)[t] = make_uint2(a, b);
+    if (lane == 0)
+        reinterpret_cast<uint64_t *>(scratch + 128 * n_items)[i] =
+            reinterpret_cast<const uint64_t *>(st + 4 * S)[it.unit] + it.j * chunk;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ragged_gen_xs(const RaggedItem *items, uint64_t n_items,
+                                                           const uint8_t *scratch, uint8_t *st, uint64_t S,
+                                                           uint32_t *out) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t i = t >> 4, lane = t & 15;
+    if (i >= n_items) return;  // whole rows
+    const RaggedItem it = items[i];
+    const uint2 w = reinterpret_cast<const uint2 *>(scratch)[t];
+    uint32_t a = w.x, b = w.y;
+    const uint64_t n = reinterpret_cast<const uint64_t *>(scratch + 128 * n_items)[i];
+    const uint32_t y0 = *reinterpret_cast<const uint32_t *>(st + 4 * S + 8 * (S / 32));
+    uint32_t y = y0 + static_cast<uint32_t>(n) * kWeylC;
+    uint32_t *o = out + it.out;
+    const uint64_t v0 = 2 * lane;
+    for (uint32_t k = 0; k < it.len; ++k) {
+        xs1024_step(a, b);
+        y += kWeylC;
+        const uint32_t m = weyl_mix(y);
+        const uint64_t v = 32ull * k + v0;
+        if (v < it.nvals) o[v] = a + m;
+        if (v + 1 < it.nvals) o[v + 1] = b + m;
+    }
+    if (it.last) {
+        reinterpret_cast<uint2 *>(st)[16 * it.unit + lane] = make_uint2(a, b);
+        if (lane == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[it.unit] = n + it.len;
+    }
+}
+
+unsigned blocks_for(uint64_t threads) { return static_cast<unsigned>((threads + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+uint64_t ragged_chunk(rngx_kind kind) { return kind == RNGX_XS1024W ? 8192 : 4096; }
+
+void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, std::vector<RaggedItem> *items,
+                 uint64_t *max_chunks) {
+    const uint64_t C = ragged_chunk(kind);
+    const bool xs = kind == RNGX_XS1024W;
+    items->clear();
+    *max_chunks = 1;
+    for (uint64_t u = 0; u < n_units; ++u) {
+        const uint64_t total = off[u + 1] - off[u];
+        const uint64_t steps = xs ? (total + 31) / 32 : total;
+        const uint64_t nch = (steps + C - 1) / C;
+        *max_chunks = std::max(*max_chunks, nch);
+        for (uint64_t j = 0; j < nch; ++j) {
+            RaggedItem it{};
+            it.unit = u;
+            it.j = j;
+            it.len = static_cast<uint32_t>(std::min(C, steps - j * C));
+            it.last = j + 1 == nch;
+            if (xs) {
+                it.out = off[u] + 32 * j * C;
+                it.nvals = std::min<uint64_t>(32ull * it.len, total - 32 * j * C);
+            } else {
+                it.out = off[u] + j * C;
+                it.nvals = it.len;
+            }
+            items->push_back(it);
+        }
+    }
+}
+
+size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items) {
+    return kind == RNGX_XS1024W ? 136 * n_items : state_bytes(kind, n_items);
+}
+
+hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st) {
+    Gen *g = r->gen;
+    const uint64_t n = r->n_items;
+    if (n == 0) return hipSuccess;
+    const uint64_t C = ragged_chunk(g->kind);
+    if (g->kind == RNGX_XS1024W) {
+        hipLaunchKernelGGL(k_ragged_start_xs, dim3(blocks_for(16 * n)), dim3(kBlock), 0, st, r->d_items, n,
+                           g->d_state, g->S, r->d_scratch, r->d_t32, C);
+        hipLaunchKernelGGL(k_ragged_gen_xs, dim3(blocks_for(16 * n)), dim3(kBlock), 0, st, r->d_items, n,
+                           r->d_scratch, g->d_state, g->S, d_out);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_ragged_start_small, dim3(blocks_for(n)), dim3(kBlock), 0, st, g->kind, r->d_items, n,
+                       g->d_state, g->S, r->d_scratch, r->d_t64, r->d_t32, C);
+    switch (g->kind) {
+    case RNGX_LCG32: hipLaunchKernelGGL(k_ragged_gen_small<Lcg32>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    case RNGX_LCG64: hipLaunchKernelGGL(k_ragged_gen_small<Lcg64>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    case RNGX_MWC: hipLaunchKernelGGL(k_ragged_gen_small<Mwc>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    case RNGX_XORWOW: hipLaunchKernelGGL(k_ragged_gen_small<Xorwow>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ragged_gen_small<Philox>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    default: break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rngx

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "rngx.h"
 
@@ -37,6 +38,27 @@ struct Gen {
     uint8_t *d_state;
     size_t state_bytes;
     const void *owner;  // the lattice that owns this generator, if any
+    uint32_t plans;     // ragged plans that hold this generator
+};
+
+// One chunk of one stream's (XS1024W: one instance's) ragged request.
+struct RaggedItem {
+    uint64_t unit;   // stream, or XS1024W instance
+    uint64_t out;    // output index of the chunk's first value
+    uint64_t j;      // chunk index: the chunk starts j*C outputs (steps) in
+    uint64_t nvals;  // values the chunk writes
+    uint32_t len;    // outputs (XS1024W: instance steps) the chunk takes
+    uint32_t last;   // the chunk ends the request: it writes the state back
+};
+
+struct Ragged {
+    uint64_t magic;
+    Gen *gen;
+    uint64_t n_items, total;
+    RaggedItem *d_items;
+    uint8_t *d_scratch;  // chunk start states
+    uint64_t *d_t64;     // jump tables (see jump_table)
+    uint32_t *d_t32;
 };
 
 // How a lattice is swept: as strips held on chip by co-resident
@@ -63,6 +85,20 @@ struct Ising {
     uint32_t *d_err;     // strips: set if a neighbour wait gave up
     int32_t *d_partial;  // per-pass path: per-block energy partials
     uint64_t epoch;      // pass counter value the flags have reached
+    uint32_t batches;    // batches that hold this lattice
+};
+
+// A fixed list of lattices swept together in one launch.
+struct IsingBatch {
+    uint64_t magic;
+    int device;
+    rngx_kind kind;
+    uint32_t n;
+    void *d_reps;        // replica descriptors (device)
+    uint32_t *d_order;   // replicas in decreasing order of work
+    uint32_t *d_next;    // work counter
+    uint32_t lds, grid;  // launch shape
+    Ising **lats;        // host copy of the members
 };
 
 size_t state_bytes(rngx_kind kind, uint64_t S);
@@ -77,10 +113,26 @@ void clear_error();
 hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st);
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st);
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
+
+// Host-side jump tables for j = 0 .. count-1 steps of size `step`:
+//  LCG32/LCG64: (A, C) pairs of the affine map f^(j step), 2 u64 each;
+//  MWC: a^(j step) mod p, 1 u64 each;
+//  XORWOW / XS1024W: x^(j step) mod P packed in 5 / 32 u32 each;
+//  PHILOX: empty (the counter jumps by j step).
+void jump_table(rngx_kind kind, uint64_t step, uint64_t count, std::vector<uint64_t> *u64s,
+                std::vector<uint32_t> *u32s);
 hipError_t launch_hot_start(Ising *lat, uint64_t seed, hipStream_t st);
 hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st);
 hipError_t launch_zero(uint32_t *p, uint64_t n, hipStream_t st);
 bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out);
+hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas, const uint64_t *n_sweeps,
+                         int32_t *const *traces, int n_cu);
+hipError_t launch_batch(IsingBatch *b, hipStream_t st);
+uint64_t ragged_chunk(rngx_kind kind);
+void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, std::vector<RaggedItem> *items,
+                 uint64_t *max_chunks);
+size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items);
+hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st);
 uint64_t ising_partials(uint32_t L);
 
 enum { kOutU32 = 0, kOutF32 = 1, kOutXor = 2 };
@@ -215,5 +267,45 @@ __device__ __forceinline__ void xs1024_step(uint32_t &a, uint32_t &b) {
 
 // Weyl output term y (I + R^16) with y = y0 + n c.
 __device__ __forceinline__ uint32_t weyl_mix(uint32_t y) { return y ^ (y >> 16); }
+
+// J(M) v for the XS1024W transition matrix M and J(x) = sum c_i x^i
+// (coefficient i at bit i%32 of c[i/32], degree < 1024), by Horner's rule:
+// 1024 generator steps.  (a, b) is the calling lane's word pair of v.
+__device__ __forceinline__ void xs1024_apply_poly(const uint32_t *c, uint32_t &a, uint32_t &b) {
+    const uint32_t va = a, vb = b;
+    a = 0;
+    b = 0;
+    for (int i = 1023; i >= 0; --i) {
+        xs1024_step(a, b);
+        if ((c[i >> 5] >> (i & 31)) & 1u) { a ^= va; b ^= vb; }
+    }
+}
+
+// Same for XORWOW's 160-bit xorshift part (x, y, z, w, v) = s[0..4].
+__device__ __forceinline__ void xorwow_apply_poly(const uint32_t *c, uint32_t (&s)[5]) {
+    uint32_t acc[5] = {0, 0, 0, 0, 0};
+    for (int i = 159; i >= 0; --i) {
+        const uint32_t t = acc[0] ^ (acc[0] >> 2);
+        acc[0] = acc[1]; acc[1] = acc[2]; acc[2] = acc[3]; acc[3] = acc[4];
+        acc[4] = (acc[4] ^ (acc[4] << 4)) ^ (t ^ (t << 1));
+        if ((c[i >> 5] >> (i & 31)) & 1u)
+            for (int q = 0; q < 5; ++q) acc[q] ^= s[q];
+    }
+    for (int q = 0; q < 5; ++q) s[q] = acc[q];
+}
+
+// y * A mod p for the MWC modulus p = a 2^32 - 1, using 2^64 = R (mod p)
+// with R = 2^64 - p < 2^41.
+__device__ __forceinline__ uint64_t mwc_mulmod(uint64_t y, uint64_t A) {
+    constexpr uint64_t R = 0ull - kMwcP;
+    uint64_t lo = y * A, hi = __umul64hi(y, A);
+    while (hi) {  // (hi, lo) <- hi * R + lo; hi shrinks by >= 23 bits a round
+        const uint64_t plo = hi * R, phi = __umul64hi(hi, R);
+        const uint64_t sum = plo + lo;
+        hi = phi + (sum < plo ? 1 : 0);
+        lo = sum;
+    }
+    return lo >= kMwcP ? lo - kMwcP : lo;
+}
 
 }  // namespace rngx

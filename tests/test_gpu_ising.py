@@ -33,7 +33,7 @@ def _run_both(rx, orc, L, kind, beta, sweeps, seed=1, chunks=(None,)):
 
 
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("L", [16, 32, 48, 80])
+@pytest.mark.parametrize("L", [16, 32, 48, 80, 160])
 def test_sweep_parity(rngx, orc, kind, L):
     print(f"case ising {kind} L={L}", flush=True)
     for beta in (0.4, ex.BETA_C):
@@ -143,3 +143,86 @@ def test_statistics_L32(rngx, kind, beta):
           f"C={c:.5f}+-{sc:.5f} (exact {ce:.5f})", flush=True)
     assert abs(e - ee) < 3 * se
     assert abs(c - ce) < 3 * sc
+
+
+# ---------------------------------------------------------------- batches
+def _batch_case(rngx, kind, seed, n=24, max_L=512, big=(400, 512)):
+    rng = np.random.default_rng(seed)
+    Ls = list(rng.choice(np.arange(16, max_L + 1, 16), size=n - len(big))) + list(big)
+    betas = list(rng.uniform(0.3, 0.6, size=n))
+    sweeps = list(rng.integers(1, 12, size=n))
+    return [int(L) for L in Ls], betas, [int(x) for x in sweeps]
+
+
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "philox4x32_10", "xorwow"])
+def test_batch_equals_individual_sweeps(rngx, kind):
+    """One launch over replicas of uneven L and beta (on-chip and streamed)
+    gives every replica exactly what ising_sweep gives it alone."""
+    print(f"case batch {kind}", flush=True)
+    Ls, betas, sweeps = _batch_case(rngx, kind, 5)
+    lats = [rngx.ising_create(L, kind, 100 + i) for i, L in enumerate(Ls)]
+    twins = [rngx.ising_create(L, kind, 100 + i) for i, L in enumerate(Ls)]
+    traces = [torch.full((s,), 7, dtype=torch.int32, device="cuda") for s in sweeps]
+    batch = rngx.ising_batch_create(lats, betas, sweeps, traces)
+    for rep in range(2):
+        rngx.ising_batch_run(batch)
+        for i, tw in enumerate(twins):
+            tt = torch.zeros(sweeps[i], dtype=torch.int32, device="cuda")
+            rngx.ising_sweep(tw, betas[i], sweeps[i], tt)
+            assert torch.equal(traces[i], tt), (rep, i, Ls[i])
+            assert np.array_equal(rngx.ising_get_spins(lats[i]), rngx.ising_get_spins(tw)), (rep, i, Ls[i])
+            assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[i])),
+                                  rngx.rng_get_state(rngx.ising_rng(tw))), (rep, i)
+
+
+def test_batch_small_replicas_match_oracle(rngx, orc):
+    kind = "xs1024w"
+    Ls, betas, sweeps = [16, 48, 96], [0.31, 0.44, 0.58], [3, 5, 2]
+    lats = [rngx.ising_create(L, kind, 7 + i) for i, L in enumerate(Ls)]
+    traces = [torch.zeros(s, dtype=torch.int32, device="cuda") for s in sweeps]
+    batch = rngx.ising_batch_create(lats, betas, sweeps, traces)
+    rngx.ising_batch_run(batch)
+    for i, L in enumerate(Ls):
+        sp, st = orc.ising_create(L, kind, 7 + i)
+        tr = orc.ising_sweeps(L, kind, betas[i], st, sp, sweeps[i])
+        assert np.array_equal(traces[i].cpu().numpy(), tr)
+        assert np.array_equal(rngx.ising_get_spins(lats[i]).ravel(), sp)
+
+
+def test_batch_graph_replay(rngx):
+    """The batch run captured in a HIP graph: every replay equals an eager run."""
+    kind = "xs1024w"
+    Ls, betas, sweeps = _batch_case(rngx, kind, 9, n=10, max_L=256, big=(320,))
+    a = [rngx.ising_create(L, kind, 50 + i) for i, L in enumerate(Ls)]
+    b = [rngx.ising_create(L, kind, 50 + i) for i, L in enumerate(Ls)]
+    ta = [torch.zeros(s, dtype=torch.int32, device="cuda") for s in sweeps]
+    tb = [torch.zeros(s, dtype=torch.int32, device="cuda") for s in sweeps]
+    ba = rngx.ising_batch_create(a, betas, sweeps, ta)
+    bb = rngx.ising_batch_create(b, betas, sweeps, tb)
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        rngx.ising_batch_run(ba, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        rngx.ising_batch_run(bb)
+        torch.cuda.synchronize()
+        for i in range(len(Ls)):
+            assert torch.equal(ta[i], tb[i]), (rep, i)
+            assert np.array_equal(rngx.ising_get_spins(a[i]), rngx.ising_get_spins(b[i])), (rep, i)
+
+
+def test_batch_argument_errors(rngx):
+    x = rngx.ising_create(32, "lcg32", 1)
+    y = rngx.ising_create(32, "mwc", 1)
+    with pytest.raises(rngx.RngxError):
+        rngx.ising_batch_create([x, x], [0.4, 0.4], [1, 1])
+    with pytest.raises(rngx.RngxError):
+        rngx.ising_batch_create([x, y], [0.4, 0.4], [1, 1])
+    with pytest.raises(rngx.RngxError):
+        rngx.ising_batch_create([x], [float("nan")], [1])
+    b = rngx.ising_batch_create([x], [0.4], [1])
+    assert rngx.load().ising_destroy(x.handle) == -7  # held by the batch
+    b.destroy()

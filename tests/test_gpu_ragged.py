@@ -1,0 +1,89 @@
+"""GPU <-> oracle parity of uneven per-stream requests (rng_fill_ragged_u32)."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w"]
+
+
+def _lengths(kind, n_units, seed):
+    rng = np.random.default_rng(seed)
+    lens = np.floor(2.0 ** rng.uniform(0, 14, size=n_units)).astype(np.int64)
+    lens[0] = 0                                  # an empty request
+    lens[1] = 1
+    lens[-1] = 600_000 if kind == "xs1024w" else 20_000   # several chunks
+    if kind == "xs1024w":
+        lens[2] = 262_144 + 31                   # one full chunk and a partial step
+    return lens
+
+
+def _oracle_ragged(orc, kind, S, st, lens):
+    parts = []
+    if kind == "xs1024w":
+        for g, n in enumerate(lens):
+            steps = (int(n) + 31) // 32
+            vals = orc.generate(kind, S, st, steps, lo=32 * g, hi=32 * g + 32).ravel()
+            parts.append(vals[: int(n)])
+    else:
+        for s, n in enumerate(lens):
+            parts.append(orc.generate(kind, S, st, int(n), lo=s, hi=s + 1).ravel())
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_ragged_parity(rngx, orc, kind):
+    print(f"case ragged {kind}", flush=True)
+    S = 320 if kind == "xs1024w" else 37
+    n_units = S // 32 if kind == "xs1024w" else S
+    lens = _lengths(kind, n_units, 3)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    g = rngx.rng_create(kind, S, 11)
+    plan = rngx.rng_ragged_create(g, off)
+    st = orc.seed(kind, S, 11)
+    for rep in range(2):
+        out = torch.full((int(off[-1]) + 8,), -1, dtype=torch.int32, device="cuda")
+        rngx.rng_fill_ragged_u32(plan, out)
+        got = out.cpu().numpy().view(np.uint32)
+        want = _oracle_ragged(orc, kind, S, st, lens)
+        assert np.array_equal(got[: int(off[-1])], want), (kind, rep)
+        assert np.all(got[int(off[-1]):] == 0xFFFFFFFF)      # nothing written past the end
+        assert np.array_equal(rngx.rng_get_state(g), st), (kind, rep)
+    # a uniform fill continues from where the ragged requests left the streams
+    u = torch.empty(S * 5, dtype=torch.int32, device="cuda")
+    rngx.rng_fill_u32(g, u, 5)
+    assert np.array_equal(u.cpu().numpy().view(np.uint32).reshape(5, S), orc.generate(kind, S, st, 5))
+
+
+def test_ragged_graph_replay(rngx, orc):
+    kind, S = "xs1024w", 256
+    lens = _lengths(kind, S // 32, 8)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    ga, gb = rngx.rng_create(kind, S, 2), rngx.rng_create(kind, S, 2)
+    pa, pb = rngx.rng_ragged_create(ga, off), rngx.rng_ragged_create(gb, off)
+    oa = torch.zeros(int(off[-1]), dtype=torch.int32, device="cuda")
+    ob = torch.zeros(int(off[-1]), dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        rngx.rng_fill_ragged_u32(pa, oa, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        rngx.rng_fill_ragged_u32(pb, ob)
+        torch.cuda.synchronize()
+        assert torch.equal(oa, ob), rep
+        assert np.array_equal(rngx.rng_get_state(ga), rngx.rng_get_state(gb)), rep
+
+
+def test_ragged_argument_errors(rngx):
+    g = rngx.rng_create("lcg32", 8, 1)
+    with pytest.raises(rngx.RngxError):
+        rngx.rng_ragged_create(g, [0, 1, 2])            # wrong count
+    with pytest.raises(rngx.RngxError):
+        rngx.rng_ragged_create(g, [0, 5, 3, 6, 7, 8, 9, 10, 11])  # decreasing
+    p = rngx.rng_ragged_create(g, list(range(0, 18, 2)))
+    assert rngx.load().rng_destroy(g.handle) == -7     # held by the plan
+    p.destroy()
