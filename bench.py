@@ -102,6 +102,123 @@ def bench_ising(rx, kind, L, sweeps, beta=0.4):
     return {"sweeps": sweeps, "ms": round(ms, 3), "flips_per_ns": round(L * L * sweeps / (ms * 1e6), 2)}
 
 
+def bench_ising_batch(rx, n=512, sweeps=10000, base_sweeps=1000, seed=1):
+    """512 XS1024W replicas, L uniform over {16, 32, ..., 1024}, beta uniform in
+    [0.3, 0.6], drawn with numpy default_rng(seed): one batched launch for
+    `sweeps` sweeps, then the same replicas one ising_sweep call each for
+    `base_sweeps` sweeps (the per-launch form, scaled down to keep the run
+    short; rates are per flip)."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    Ls = [int(x) for x in rng.choice(np.arange(16, 1025, 16), size=n)]
+    betas = [float(b) for b in rng.uniform(0.3, 0.6, size=n)]
+    lats = [rx.ising_create(L, "xs1024w", 1000 + i) for i, L in enumerate(Ls)]
+    sites = sum(L * L for L in Ls)
+    batch = rx.ising_batch_create(lats, betas, [sweeps] * n)
+    durs, _ = time_launches(lambda: rx.ising_batch_run(batch), 1, 0)
+    batched_ms = durs[0]
+    batch.destroy()
+    t = time.perf_counter()
+    for lat, b in zip(lats, betas):
+        rx.ising_sweep(lat, b, base_sweeps)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t) * 1e3
+    return {"replicas": n, "sites": sites, "sweeps": sweeps, "batched_ms": round(batched_ms, 2),
+            "batched_flips_per_ns": round(sites * sweeps / (batched_ms * 1e6), 2),
+            "per_launch_sweeps": base_sweeps, "per_launch_ms": round(single_ms, 2),
+            "per_launch_flips_per_ns": round(sites * base_sweeps / (single_ms * 1e6), 2)}
+
+
+def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_units=64):
+    """10^4 requests with lengths log-uniform in [2^10, 2^22] (numpy
+    default_rng(seed)); XS1024W requests are per instance.  One ragged call
+    vs one single-stream launch per request on a subset (rate compared)."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    lens = np.floor(2.0 ** (10 + 12 * rng.random(n))).astype(np.uint64)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    S = 32 * n if kind == "xs1024w" else n
+    g = rx.rng_create(kind, S, 1)
+    plan = rx.rng_ragged_create(g, off)
+    out = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
+    durs, _ = time_launches(lambda: rx.rng_fill_ragged_u32(plan, out), 3, 1)
+    ms = sum(durs) / len(durs)
+    total = int(off[-1])
+    # one launch per request: a single-stream (XS1024W: one-instance) generator
+    # per request filling its own length, for the first `baseline_units`
+    width = 32 if kind == "xs1024w" else 1
+    sub = 0
+    t = time.perf_counter()
+    for u in range(baseline_units):
+        gu = rx.rng_create(kind, width, 1 + u)
+        cnt = -(-int(lens[u]) // width)
+        rx.rng_fill_u32(gu, out, cnt)
+        sub += int(lens[u])
+    torch.cuda.synchronize()
+    base_s = time.perf_counter() - t
+    return {"kind": kind, "requests": n, "values": total, "ms": round(ms, 3),
+            "gsamples_s": round(total / ms / 1e6, 2), "gbs": round(total * 4 / ms / 1e6, 1),
+            "per_launch_requests": baseline_units, "per_launch_gsamples_s": round(sub / base_s / 1e9, 3)}
+
+
+def bench_serve(rx, n_req=5000, rate=2000.0, clients=64, slots=8, inflight=32, seed=1, budget=64 << 30):
+    """Poisson arrivals (numpy default_rng(seed)); 90% fills (kind uniform over
+    the six, count = floor(2^(10 + 18 u)), u32/f32 half each), 10% Ising jobs
+    (L in {64, ..., 2048} powers of two, 100 sweeps, beta uniform in
+    [0.3, 0.6], kind uniform).  Latency = submission to completion."""
+    import threading
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    kinds = list(rx.KINDS)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+    reqs = []
+    for i in range(n_req):
+        c = int(rng.integers(clients))
+        k = kinds[int(rng.integers(6))]
+        if rng.random() < 0.9:
+            reqs.append(("fill", c, k, int(2 ** (10 + 18 * rng.random())), bool(rng.random() < 0.5)))
+        else:
+            reqs.append(("ising", c, k, int(2 ** rng.integers(6, 12)), float(rng.uniform(0.3, 0.6))))
+    srv = rx.Server(slots=slots, max_inflight=inflight, memory_budget=budget, seed=seed)
+    tickets = [None] * n_req
+    ising_tickets = set()
+
+    def submitter():
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            dt = arrivals[i] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            if r[0] == "fill":
+                tickets[i] = srv.submit_fill(r[1], r[2], r[3], r[4])
+            else:
+                tickets[i] = srv.submit_ising(r[1], r[2], r[3], r[4], 100)
+                ising_tickets.add(tickets[i])
+
+    t0 = time.perf_counter()
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, done = [], []
+    # results are consumed in completion order, as independent clients would
+    for _ in range(n_req):
+        ticket, res = srv.wait_any()
+        lat.append(res.latency_s)
+        done.append((ticket, res.n_values))
+        srv.release(ticket)
+    th.join()
+    wall = time.perf_counter() - t0
+    flips = sum(n * 100 for t, n in done if t in ising_tickets)
+    samples = sum(n for t, n in done if t not in ising_tickets)
+    srv.destroy()
+    lat = np.array(lat)
+    return {"requests": n_req, "rate_per_s": rate, "slots": slots, "max_inflight": inflight,
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "wall_s": round(wall, 2),
+            "gsamples_s": round(samples / wall / 1e9, 3), "flips_per_ns": round(flips / wall / 1e9, 3)}
+
+
 def traffic_from_profile():
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     only while the kernel sources are the ones it was taken from."""
@@ -154,6 +271,8 @@ def main():
     ap.add_argument("--parts", default="all", help="all | none: per-kind parts and Ising")
     ap.add_argument("--ising-sweeps", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-serve", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="time the headline kernel only (for profiling)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3: the headline fill `steps` times, then a plain 4 GiB device-to-device "
@@ -204,6 +323,14 @@ def main():
             ising[kind] = bench_ising(rx, kind, 4096, sweeps)
             print(f"# ising L=4096 {kind}: {ising[kind]}", file=sys.stderr, flush=True)
         parts["ising_L4096_beta0.4"] = ising
+        if not args.skip_batched:
+            parts["ising_batch"] = bench_ising_batch(rx)
+            print(f"# ising batch: {parts['ising_batch']}", file=sys.stderr, flush=True)
+            parts["ragged"] = [bench_ragged(rx, k) for k in ("xs1024w", "lcg32")]
+            print(f"# ragged: {parts['ragged']}", file=sys.stderr, flush=True)
+        if not args.skip_serve:
+            parts["serve"] = {"continuous": bench_serve(rx), "fifo_one_at_a_time": bench_serve(rx, slots=1, inflight=1)}
+            print(f"# serve: {parts['serve']}", file=sys.stderr, flush=True)
 
     samples = S_FULL * COUNT_FULL
     alg_bytes = samples * 4 + 2 * STATE_BYTES["xs1024w"] * S_FULL

@@ -92,6 +92,21 @@ typedef struct rngx_gen_s *rngx_gen;     /* opaque; owns the device state of S s
 typedef struct rngx_ising_s *rngx_ising; /* opaque; owns L*L int8 spins and L*L/4 streams    */
 typedef struct rngx_ising_batch_s *rngx_ising_batch; /* opaque; lattices swept together   */
 typedef struct rngx_ragged_s *rngx_ragged;           /* opaque; uneven per-stream requests */
+typedef struct rngx_server_s *rngx_server;           /* opaque; request server             */
+
+typedef struct {
+    uint32_t slots;          /* HIP streams the requests are spread over (>= 1)                 */
+    uint32_t max_inflight;   /* requests on the device at once (>= 1); 1 with 1 slot = plain FIFO */
+    uint64_t memory_budget;  /* bytes of device memory: request outputs, Ising jobs, jump tables  */
+    uint64_t seed;           /* master seed of every client generator and Ising job              */
+} rngx_server_config;
+
+typedef struct {
+    int32_t status;    /* RNGX_OK once done                                                       */
+    void *d_output;    /* device memory owned by the server until srv_release (see srv_submit_*) */
+    uint64_t n_values; /* fill: count; Ising: L*L                                                 */
+    double latency_s;  /* from submission to completion on the device                             */
+} rngx_request_result;
 
 /* Create S = n_streams streams of `kind` seeded from `seed` as above, on the
  * current device.  Seeding runs on the device; the call returns when it is
@@ -227,6 +242,44 @@ rngx_status ising_batch_create(const rngx_ising *lats, uint32_t n, const double 
                                int32_t *const *d_traces, rngx_ising_batch *out);
 rngx_status ising_batch_run(rngx_ising_batch b, void *stream);
 rngx_status ising_batch_destroy(rngx_ising_batch b);
+
+/* Served form.  A server admits requests in arrival order as soon as its
+ * device-memory budget and in-flight limit allow (continuous batching:
+ * requests that arrive while others run are started without waiting for
+ * them), spreads them over `slots` streams so that their work overlaps, and
+ * keeps one generator stream per (client, kind) resident on the device:
+ * stream 0 (XS1024W: instance 0) of rng_create(kind, 1 (XS1024W: 32),
+ * splitmix64 output 16*client + kind of cfg->seed).  A client's requests of
+ * one kind run in submission order; results depend only on the client's own
+ * requests, not on what else is served.  The server allocates its budget
+ * once; no request allocates device memory.
+ *   srv_submit_fill:  the next `count` (<= 2^28) outputs of the (client, kind)
+ *     stream, contiguous (XS1024W: the instance's values in warp order), as
+ *     uint32 or as FP32 (u >> 8) * 2^-24 if as_f32.  Long requests are cut
+ *     into chunks that start from jump-ahead, so one request uses the whole
+ *     device.
+ *   srv_submit_ising: a hot-started L x L lattice (L % 16 == 0, L >= 16) of
+ *     the client's Ising job number j (counting that client's jobs from 0),
+ *     seeded with splitmix64 output 2^62 + 2^24 client + j of cfg->seed as
+ *     ising_create would seed it, swept n_sweeps times at beta; the output
+ *     holds the L*L int8 spins, then (at offset L*L rounded up to 16) the
+ *     n_sweeps int32 energies.
+ * Both return a ticket at once; a request larger than the whole budget is
+ * refused with RNGX_E_NOMEM.  srv_wait blocks up to timeout_s seconds (< 0:
+ * no limit) and returns RNGX_E_BUSY if the request is not done;
+ * srv_wait_any blocks likewise until some request finishes that no
+ * srv_wait_any call has returned yet (completion order) and reports it;
+ * srv_release returns the output memory to the budget.  srv_destroy waits
+ * for the device and frees everything. */
+rngx_status srv_create(const rngx_server_config *cfg, rngx_server *out);
+rngx_status srv_submit_fill(rngx_server s, uint32_t client, rngx_kind kind, uint64_t count, int as_f32,
+                            uint64_t *ticket);
+rngx_status srv_submit_ising(rngx_server s, uint32_t client, rngx_kind kind, uint32_t L, double beta,
+                             uint32_t n_sweeps, uint64_t *ticket);
+rngx_status srv_wait(rngx_server s, uint64_t ticket, double timeout_s, rngx_request_result *res);
+rngx_status srv_wait_any(rngx_server s, double timeout_s, uint64_t *ticket, rngx_request_result *res);
+rngx_status srv_release(rngx_server s, uint64_t ticket);
+rngx_status srv_destroy(rngx_server s);
 
 /* Description of the calling thread's most recent error ("" if none). */
 const char *rngx_last_error(void);

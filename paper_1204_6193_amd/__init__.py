@@ -50,8 +50,26 @@ SIGNATURES = {
                                   ctypes.POINTER(_u64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "ising_batch_run": (_i32, [_vp, _vp]),
     "ising_batch_destroy": (_i32, [_vp]),
+    "srv_create": (_i32, [ctypes.c_void_p, ctypes.POINTER(_vp)]),
+    "srv_submit_fill": (_i32, [_vp, ctypes.c_uint32, _i32, _u64, _i32, ctypes.POINTER(_u64)]),
+    "srv_submit_ising": (_i32, [_vp, ctypes.c_uint32, _i32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32,
+                                ctypes.POINTER(_u64)]),
+    "srv_wait": (_i32, [_vp, _u64, ctypes.c_double, ctypes.c_void_p]),
+    "srv_wait_any": (_i32, [_vp, ctypes.c_double, ctypes.POINTER(_u64), ctypes.c_void_p]),
+    "srv_release": (_i32, [_vp, _u64]),
+    "srv_destroy": (_i32, [_vp]),
     "rngx_last_error": (ctypes.c_char_p, []),
 }
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32), ("memory_budget", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("d_output", ctypes.c_void_p), ("n_values", ctypes.c_uint64),
+                ("latency_s", ctypes.c_double)]
 
 
 class RngxError(RuntimeError):
@@ -258,6 +276,25 @@ def ising_spins(lat: Ising) -> int:
     return p.value
 
 
+_hip = None
+
+
+def copy_to_host(d_ptr: int, nbytes: int, dtype="uint8"):
+    """Copy nbytes of device memory (e.g. a server result) into a new numpy
+    array, with the HIP runtime torch loaded (same process-wide runtime)."""
+    import numpy as np
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so"))
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    out = np.empty(nbytes, dtype=np.uint8)
+    rc = _hip.hipMemcpy(out.ctypes.data, d_ptr, nbytes, 2)  # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed with {rc}")
+    return out.view(dtype)
+
+
 class _DeviceArray:
     """Exposes a borrowed device allocation through __cuda_array_interface__."""
 
@@ -338,3 +375,48 @@ def ising_batch_run(batch: IsingBatch, stream=None):
 
 def ising_batch_destroy(batch: IsingBatch):
     batch.destroy()
+
+
+class Server:
+    """Request server (continuous batching over `slots` streams, memory budget)."""
+
+    def __init__(self, slots=8, max_inflight=32, memory_budget=8 << 30, seed=1):
+        cfg = ServerConfig(slots, max_inflight, memory_budget, seed)
+        h = _vp()
+        _check(load().srv_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h.value
+
+    def submit_fill(self, client: int, kind, count: int, f32: bool = False) -> int:
+        t = _u64()
+        _check(load().srv_submit_fill(self.handle, client, _kind(kind), count, int(f32), ctypes.byref(t)))
+        return t.value
+
+    def submit_ising(self, client: int, kind, L: int, beta: float, sweeps: int) -> int:
+        t = _u64()
+        _check(load().srv_submit_ising(self.handle, client, _kind(kind), L, beta, sweeps, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> RequestResult:
+        r = RequestResult()
+        _check(load().srv_wait(self.handle, ticket, timeout_s, ctypes.byref(r)))
+        return r
+
+    def wait_any(self, timeout_s: float = -1.0):
+        """(ticket, RequestResult) of the next request to finish."""
+        r = RequestResult()
+        t = _u64()
+        _check(load().srv_wait_any(self.handle, timeout_s, ctypes.byref(t), ctypes.byref(r)))
+        return t.value, r
+
+    def release(self, ticket: int):
+        _check(load().srv_release(self.handle, ticket))
+
+    def destroy(self):
+        if self.handle:
+            _check(load().srv_destroy(self.handle))
+        self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.srv_destroy(self.handle)
+            self.handle = None

@@ -553,4 +553,84 @@ rngx_status ising_destroy(rngx_ising h) {
     return RNGX_OK;
 }
 
+rngx_status srv_create(const rngx_server_config *cfg, rngx_server *out) {
+    if (!cfg || !out) return fail(RNGX_E_INVALID, "NULL argument");
+    if (cfg->slots < 1 || cfg->max_inflight < 1) return fail(RNGX_E_INVALID, "slots and max_inflight must be >= 1");
+    if (cfg->memory_budget == 0) return fail(RNGX_E_INVALID, "memory_budget must be positive");
+    Server *s;
+    if (rngx_status st = server_create(cfg, &s)) return st;
+    reg(s);
+    *out = reinterpret_cast<rngx_server>(s);
+    clear_error();
+    return RNGX_OK;
+}
+
+static rngx_status check_server(rngx_server h, Server **s) {
+    if (!live(h)) return fail(RNGX_E_INVALID, "unknown or destroyed server");
+    *s = reinterpret_cast<Server *>(h);
+    return RNGX_OK;
+}
+
+rngx_status srv_submit_fill(rngx_server h, uint32_t client, rngx_kind kind, uint64_t count, int as_f32,
+                            uint64_t *ticket) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    if (!ticket) return fail(RNGX_E_INVALID, "ticket is NULL");
+    if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind");
+    if (count == 0) return fail(RNGX_E_INVALID, "count must be positive");
+    if (count > kMaxServedValues) return fail(RNGX_E_OVERFLOW, "count exceeds 2^28");
+    if (rngx_status st = server_submit_fill(s, client, kind, count, as_f32, ticket)) return st;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status srv_submit_ising(rngx_server h, uint32_t client, rngx_kind kind, uint32_t L, double beta,
+                             uint32_t n_sweeps, uint64_t *ticket) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    if (!ticket) return fail(RNGX_E_INVALID, "ticket is NULL");
+    if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind");
+    if (L < 16 || L % 16) return fail(RNGX_E_ALIGN, "L must be a multiple of 16 and at least 16");
+    if (L > kMaxL) return fail(RNGX_E_OVERFLOW, "L must not exceed 16384");
+    if (!std::isfinite(beta) || beta < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");
+    if (rngx_status st = server_submit_ising(s, client, kind, L, beta, n_sweeps, ticket)) return st;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status srv_wait(rngx_server h, uint64_t ticket, double timeout_s, rngx_request_result *res) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    if (!res) return fail(RNGX_E_INVALID, "res is NULL");
+    if (rngx_status st = server_wait(s, ticket, timeout_s, res)) return st;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status srv_wait_any(rngx_server h, double timeout_s, uint64_t *ticket, rngx_request_result *res) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    if (!res || !ticket) return fail(RNGX_E_INVALID, "NULL argument");
+    if (rngx_status st = server_wait_any(s, timeout_s, ticket, res)) return st;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status srv_release(rngx_server h, uint64_t ticket) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    if (rngx_status st = server_release(s, ticket)) return st;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status srv_destroy(rngx_server h) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    unreg(s);
+    server_destroy(s);
+    clear_error();
+    return RNGX_OK;
+}
+
 }  // extern "C"

@@ -24,18 +24,44 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Each lane owns one chunk.  Rounds of 32 outputs go through a per-wave LDS
+// tile so that the wave writes two lanes' 32 consecutive values with one
+// store (two contiguous 128-byte pieces) instead of 64 scattered words.
+constexpr int kSeg = 32;
+
 template <class G>
 __global__ __launch_bounds__(kBlock) void k_ragged_gen_small(const RaggedItem *items, uint64_t n_items,
                                                               const uint8_t *scratch, uint8_t *st, uint64_t S,
                                                               uint32_t *out) {
+    __shared__ uint32_t tile[kBlock / 64][64][kSeg + 1];
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n_items) return;
-    const RaggedItem it = items[i];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
+    const bool mine = i < n_items;
+    RaggedItem it{};
     G g;
-    g.load(scratch, n_items, i);
-    uint32_t *o = out + it.out;
-    for (uint32_t k = 0; k < it.len; ++k) o[k] = g.next();
-    if (it.last) g.store(st, S, it.unit);
+    if (mine) {
+        it = items[i];
+        g.load(scratch, n_items, i);
+    }
+    const uint32_t len = mine ? it.len : 0;
+    uint32_t rounds = (len + kSeg - 1) / kSeg;  // rounds needed by the longest chunk of the wave
+    for (int off = 32; off > 0; off >>= 1) rounds = max(rounds, static_cast<uint32_t>(__shfl_xor(static_cast<int>(rounds), off)));
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t base = rd * kSeg;
+        const uint32_t cnt = len > base ? min(static_cast<uint32_t>(kSeg), len - base) : 0;
+        for (uint32_t k = 0; k < cnt; ++k) tile[w][lane][k] = g.next();
+        __builtin_amdgcn_wave_barrier();
+        // lanes 0-31 write lane j's segment, lanes 32-63 lane j+1's
+        for (uint32_t j = 0; j < 64; j += 2) {
+            const uint32_t src = j + half;
+            const uint32_t len_j = static_cast<uint32_t>(__shfl(static_cast<int>(len), src));
+            const uint64_t out_j = static_cast<uint64_t>(__shfl(static_cast<long long>(it.out), src));
+            const uint32_t cnt_j = len_j > base ? min(static_cast<uint32_t>(kSeg), len_j - base) : 0;
+            if (col < cnt_j) out[out_j + base + col] = tile[w][src][col];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (mine && it.last) g.store(st, S, it.unit);
 }
 
 // Start states of the chunks of the small-state kinds, written to scratch in
@@ -136,7 +162,109 @@ __global__ __launch_bounds__(kBlock) void k_ragged_gen_xs(const RaggedItem *item
 
 unsigned blocks_for(uint64_t threads) { return static_cast<unsigned>((threads + kBlock - 1) / kBlock); }
 
+// ---------------------------------------------------------------- one stream
+// The next N outputs of ONE stream (small kinds: contiguous; XS1024W: one
+// instance in warp order) produced by many threads: chunk j of C outputs
+// (XS1024W: C instance steps) starts from the state jumped by j*C.  The
+// state is read from st_in and the final state written to st_out, a
+// different buffer, so no chunk can read what the last one writes.
+__device__ __forceinline__ void put(void *out, uint64_t idx, uint32_t u, int f32) {
+    if (f32) static_cast<float *>(out)[idx] = static_cast<float>(u >> 8) * 0x1.0p-24f;
+    else static_cast<uint32_t *>(out)[idx] = u;
+}
+
+template <class G>
+__global__ __launch_bounds__(kBlock) void k_stream_fill_small(const uint8_t *st_in, uint8_t *st_out, uint64_t N,
+                                                               uint64_t C, const uint64_t *t64, const uint32_t *t32,
+                                                               void *out, int f32) {
+    __shared__ uint32_t tile[kBlock / 64][64][kSeg + 1];
+    const uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t nch = (N + C - 1) / C;
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
+    const bool mine = j < nch;
+    G g;
+    uint32_t len = 0;
+    if (mine) {
+        g.load(st_in, 1, 0);
+        jump(g, t64, t32, j, C);
+        len = static_cast<uint32_t>(min(C, N - j * C));
+    }
+    uint32_t rounds = (len + kSeg - 1) / kSeg;
+    for (int off = 32; off > 0; off >>= 1) rounds = max(rounds, static_cast<uint32_t>(__shfl_xor(static_cast<int>(rounds), off)));
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t base = rd * kSeg;
+        const uint32_t cnt = len > base ? min(static_cast<uint32_t>(kSeg), len - base) : 0;
+        for (uint32_t k = 0; k < cnt; ++k) tile[w][lane][k] = g.next();
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t q = 0; q < 64; q += 2) {
+            const uint32_t src = q + half;
+            const uint32_t len_q = static_cast<uint32_t>(__shfl(static_cast<int>(len), src));
+            const uint64_t j_q = static_cast<uint64_t>(__shfl(static_cast<long long>(j), src));
+            const uint32_t cnt_q = len_q > base ? min(static_cast<uint32_t>(kSeg), len_q - base) : 0;
+            if (col < cnt_q) put(out, j_q * C + base + col, tile[w][src][col], f32);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (mine && j == nch - 1) g.store(st_out, 1, 0);
+}
+
+// XS1024W instance (state: 32 words, step counter, Weyl seed): one 16-lane
+// DPP row per chunk of C steps.
+__global__ __launch_bounds__(kBlock) void k_stream_fill_xs(const uint8_t *st_in, uint8_t *st_out, uint64_t N,
+                                                            uint64_t C, const uint32_t *t32, void *out, int f32) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t j = t >> 4, lane = t & 15;
+    const uint64_t total_steps = (N + 31) / 32, nch = (total_steps + C - 1) / C;
+    if (j >= nch) return;  // whole rows
+    const uint2 w = reinterpret_cast<const uint2 *>(st_in)[lane];
+    uint32_t a = w.x, b = w.y;
+    if (j) xs1024_apply_poly(t32 + 32 * j, a, b);
+    const uint64_t n0 = *reinterpret_cast<const uint64_t *>(st_in + 128);
+    const uint32_t y0 = *reinterpret_cast<const uint32_t *>(st_in + 136);
+    uint32_t y = y0 + static_cast<uint32_t>(n0 + j * C) * kWeylC;
+    const uint64_t steps = min(C, total_steps - j * C);
+    for (uint64_t k = 0; k < steps; ++k) {
+        xs1024_step(a, b);
+        y += kWeylC;
+        const uint32_t m = weyl_mix(y);
+        const uint64_t v = 32 * (j * C + k) + 2 * lane;
+        if (v < N) put(out, v, a + m, f32);
+        if (v + 1 < N) put(out, v + 1, b + m, f32);
+    }
+    if (j == nch - 1) {
+        reinterpret_cast<uint2 *>(st_out)[lane] = make_uint2(a, b);
+        if (lane == 0) {
+            *reinterpret_cast<uint64_t *>(st_out + 128) = n0 + total_steps;
+            *reinterpret_cast<uint32_t *>(st_out + 136) = y0;
+        }
+    }
+}
+
 }  // namespace
+
+uint64_t stream_fill_chunk(rngx_kind) { return 4096; }
+
+hipError_t launch_stream_fill(rngx_kind kind, const uint8_t *st_in, uint8_t *st_out, uint64_t N, int f32,
+                              const uint64_t *t64, const uint32_t *t32, void *out, hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    const uint64_t C = stream_fill_chunk(kind);
+    if (kind == RNGX_XS1024W) {
+        const uint64_t nch = ((N + 31) / 32 + C - 1) / C;
+        hipLaunchKernelGGL(k_stream_fill_xs, dim3(blocks_for(16 * nch)), dim3(kBlock), 0, st, st_in, st_out, N, C, t32,
+                           out, f32);
+        return hipGetLastError();
+    }
+    const unsigned blocks = blocks_for((N + C - 1) / C);
+    switch (kind) {
+    case RNGX_LCG32: hipLaunchKernelGGL(k_stream_fill_small<Lcg32>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
+    case RNGX_LCG64: hipLaunchKernelGGL(k_stream_fill_small<Lcg64>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
+    case RNGX_MWC: hipLaunchKernelGGL(k_stream_fill_small<Mwc>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
+    case RNGX_XORWOW: hipLaunchKernelGGL(k_stream_fill_small<Xorwow>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
+    case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_stream_fill_small<Philox>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
+    default: break;
+    }
+    return hipGetLastError();
+}
 
 uint64_t ragged_chunk(rngx_kind kind) { return kind == RNGX_XS1024W ? 8192 : 4096; }
 

@@ -101,6 +101,17 @@ struct IsingBatch {
     Ising **lats;        // host copy of the members
 };
 
+struct Server;  // request server (server.hip)
+constexpr uint64_t kMaxServedValues = 1ull << 28;  // largest served fill
+rngx_status server_create(const rngx_server_config *cfg, Server **out);
+rngx_status server_submit_fill(Server *s, uint32_t client, rngx_kind kind, uint64_t count, int f32, uint64_t *ticket);
+rngx_status server_submit_ising(Server *s, uint32_t client, rngx_kind kind, uint32_t L, double beta, uint32_t sweeps,
+                                uint64_t *ticket);
+rngx_status server_wait(Server *s, uint64_t ticket, double timeout_s, rngx_request_result *res);
+rngx_status server_wait_any(Server *s, double timeout_s, uint64_t *ticket, rngx_request_result *res);
+rngx_status server_release(Server *s, uint64_t ticket);
+void server_destroy(Server *s);
+
 size_t state_bytes(rngx_kind kind, uint64_t S);
 bool kind_valid(int kind);
 
@@ -133,6 +144,9 @@ void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, std::vec
                  uint64_t *max_chunks);
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items);
 hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st);
+uint64_t stream_fill_chunk(rngx_kind kind);
+hipError_t launch_stream_fill(rngx_kind kind, const uint8_t *st_in, uint8_t *st_out, uint64_t N, int f32,
+                              const uint64_t *t64, const uint32_t *t32, void *out, hipStream_t st);
 uint64_t ising_partials(uint32_t L);
 
 enum { kOutU32 = 0, kOutF32 = 1, kOutXor = 2 };
@@ -292,6 +306,31 @@ __device__ __forceinline__ void xorwow_apply_poly(const uint32_t *c, uint32_t (&
             for (int q = 0; q < 5; ++q) acc[q] ^= s[q];
     }
     for (int q = 0; q < 5; ++q) s[q] = acc[q];
+}
+
+// Jumps by j*C outputs with tables made by jump_table(kind, C, ...):
+// t64 = affine pairs (LCG) or a^(jC) mod p (MWC), t32 = x^(jC) mod P
+// polynomials (XORWOW).  Philox needs none.
+__device__ __forceinline__ uint64_t mwc_mulmod(uint64_t y, uint64_t A);
+__device__ __forceinline__ void jump(Lcg32 &g, const uint64_t *t64, const uint32_t *, uint64_t j, uint64_t) {
+    g.x = static_cast<uint32_t>(t64[2 * j]) * g.x + static_cast<uint32_t>(t64[2 * j + 1]);
+}
+__device__ __forceinline__ void jump(Lcg64 &g, const uint64_t *t64, const uint32_t *, uint64_t j, uint64_t) {
+    g.x = t64[2 * j] * g.x + t64[2 * j + 1];
+}
+__device__ __forceinline__ void jump(Mwc &g, const uint64_t *t64, const uint32_t *, uint64_t j, uint64_t) {
+    g.y = mwc_mulmod(g.y, t64[j]);
+}
+__device__ __forceinline__ void jump(Xorwow &g, const uint64_t *, const uint32_t *t32, uint64_t j, uint64_t C) {
+    if (!j) return;
+    uint32_t s[5] = {g.x, g.y, g.z, g.w, g.v};
+    xorwow_apply_poly(t32 + 5 * j, s);
+    g.x = s[0]; g.y = s[1]; g.z = s[2]; g.w = s[3]; g.v = s[4];
+    g.d += static_cast<uint32_t>(j * C) * kWeylC;
+}
+__device__ __forceinline__ void jump(Philox &g, const uint64_t *, const uint32_t *, uint64_t j, uint64_t C) {
+    g.pos += j * C;
+    if (g.pos & 3) philox_block(g.k0, g.k1, g.pos >> 2, g.b0, g.b1, g.b2, g.b3);  // resume mid-block
 }
 
 // y * A mod p for the MWC modulus p = a 2^32 - 1, using 2^64 = R (mod p)
