@@ -67,12 +67,15 @@ __device__ __forceinline__ uint64_t mismatches(uint64_t w, uint64_t up, uint64_t
     return (nu ^ nw) + (nd ^ nw) + (nl ^ nw) + (nr ^ nw);
 }
 
-// Metropolis decision for byte i; returns s_i h_i after the update.
+// Metropolis decision for byte i; returns s_i h_i after the update.  Written
+// without branches: the flip is a masked xor and the result a select.
 __device__ __forceinline__ int metropolis(uint64_t &w, uint64_t m, int i, uint32_t r, uint64_t T4, uint64_t T8) {
-    const int mi = static_cast<int>((m >> (8 * i)) & 0xFF);
-    const bool acc = mi >= 2 || static_cast<uint64_t>(r) < (mi == 1 ? T4 : T8);
-    if (acc) w ^= 0xFEull << (8 * i);
-    return acc ? 2 * mi - 4 : 4 - 2 * mi;
+    const uint32_t mi = static_cast<uint32_t>(m >> (8 * i)) & 0xFFu;
+    const uint64_t thr = mi == 1 ? T4 : T8;
+    const uint32_t acc = static_cast<uint32_t>(mi >= 2) | static_cast<uint32_t>(static_cast<uint64_t>(r) < thr);
+    w ^= static_cast<uint64_t>(acc * 0xFEu) << (8 * i);
+    const int e = 2 * static_cast<int>(mi) - 4;
+    return acc ? e : -e;
 }
 
 // ---------------------------------------------------------------- units
@@ -193,9 +196,45 @@ __device__ __forceinline__ void wait_both(uint32_t *f0, uint32_t *f1, uint32_t t
     __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// n bytes, n a multiple of 16 and both ends 16-byte aligned (rows are L
+// bytes with L a multiple of 16).
 __device__ __forceinline__ void copy_bytes(uint8_t *dst, const uint8_t *src, uint32_t n, uint32_t t, uint32_t nt) {
-    for (uint32_t i = 4 * t; i < n; i += 4 * nt)
-        *reinterpret_cast<uint32_t *>(dst + i) = *reinterpret_cast<const uint32_t *>(src + i);
+    for (uint32_t i = 16 * t; i < n; i += 16 * nt)
+        *reinterpret_cast<uint4 *>(dst + i) = *reinterpret_cast<const uint4 *>(src + i);
+}
+
+// Two rows of L bytes (src0 -> dst0, src1 -> dst1) by the whole block: all
+// loads are issued before the first LDS write, one round trip in all.
+__device__ __forceinline__ void copy_rows(uint8_t *dst0, const uint8_t *src0, uint8_t *dst1, const uint8_t *src1,
+                                          uint32_t L, uint32_t t, uint32_t nt) {
+    const uint32_t n = L / 16;  // 16-byte pieces per row
+    for (uint32_t i = t; i < 2 * n; i += nt) {
+        const bool second = i >= n;
+        const uint32_t o = 16 * (second ? i - n : i);
+        const uint4 v = *reinterpret_cast<const uint4 *>((second ? src1 : src0) + o);
+        *reinterpret_cast<uint4 *>((second ? dst1 : dst0) + o) = v;
+    }
+}
+
+// s_waitcnt immediate that waits for vector memory counter 0 only (gfx9
+// encoding: vmcnt bits 3:0 and 15:14 zero, expcnt 7, lgkmcnt 15).
+constexpr unsigned kWaitVm0 = 0x0F70;
+
+// Make this pass's halo stores of every thread visible at agent scope, then
+// raise the strip's pass counter.  Each wave waits until its own stores have
+// reached this XCD's L2 (a workgroup barrier does not wait for them); after
+// the barrier wavefront 0 alone writes the L2 back (agent-scope release,
+// one write-back for the whole block) and waits for it before the counter
+// store.  A release fence in every wave would work too but costs one L2
+// write-back per wave.
+__device__ __forceinline__ void publish(uint32_t *flag, uint32_t target, uint32_t t) {
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    if (t < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        if (t == 0) __hip_atomic_store(flag, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Sum of v over the block (result valid in thread 0).
@@ -212,13 +251,17 @@ __device__ __forceinline__ int block_sum(int v, int *scratch) {
     return s;
 }
 
-// Unit k of the strip sits at byte offset `off` of LDS (row yl+1); bit 29:
-// run starts at x = 0, bit 30: run ends at x = L-1, bit 31: (row0+yl) odd.
+// Unit k of the strip sits at byte offset `off` of LDS (row yl+1); bit 27:
+// unit in the strip's top row, bit 28: in its bottom row, bit 29: run starts
+// at x = 0, bit 30: run ends at x = L-1, bit 31: (row0+yl) odd.
+constexpr uint32_t kOffMask = (1u << 27) - 1;
 template <int NB>
-__device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint64_t row0) {
+__device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint32_t R, uint64_t row0) {
     const uint32_t upr = L / NB;
     const uint32_t yl = k / upr, x0 = (k % upr) * NB;
     uint32_t off = (yl + 1) * L + x0;
+    if (yl == 0) off |= 1u << 27;
+    if (yl == R - 1) off |= 1u << 28;
     if (x0 == 0) off |= 1u << 29;
     if (x0 + NB == L) off |= 1u << 30;
     if ((row0 + yl) & 1) off |= 1u << 31;
@@ -227,12 +270,27 @@ __device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint64_t 
 
 // All sweeps of strip r (R rows at row r*R) held in `lds` ((R+2)*L + 80
 // bytes: rows, block-sum scratch, a zero word) by the calling workgroup.
+//
+// With several strips, each colour pass is scheduled around the exchange of
+// boundary rows with the strips above and below:
+//   1. update the slots holding the strip's top and bottom rows; each thread
+//      also stores its updated boundary runs into this pass's halo slot;
+//   2. publish: every wave fences its stores at agent scope, then after a
+//      barrier wavefront 0 raises the strip's pass counter;
+//   3. update the interior slots while the neighbours do the same;
+//   4. wavefront 0 waits for both neighbours' counters and acquires; after a
+//      barrier all threads pull the two neighbour rows into LDS.
+// Sites of one colour are independent within a pass, so the slot order does
+// not change any result.  When a row does not fit in one slot (wide lattices,
+// few threads) the publish moves after the last slot.
 template <class Unit, int SPT>
 __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8_t *lds) {
     constexpr int NB = Unit::kNB;
     const uint32_t L = a.L, R = a.R, nwg = a.nwg, t = threadIdx.x, nt = blockDim.x;
     const uint64_t row0 = static_cast<uint64_t>(r) * R;
     const uint32_t strip_bytes = R * L;
+    const uint32_t upr = L / NB;               // units per row
+    const uint32_t last0 = a.units - upr;      // first unit of the bottom row
     int *red = reinterpret_cast<int *>(lds + (R + 2) * L);
     uint32_t *zero_word = reinterpret_cast<uint32_t *>(lds + (R + 2) * L + 64);
     if (t == 0) *zero_word = 0;
@@ -252,26 +310,32 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
         const uint32_t k = t + i * nt;
         if (k < a.units) {
             u[i].load(a.st, a.S, ubase + k);
-            place[i] = unit_place<NB>(k, L, row0);
+            place[i] = unit_place<NB>(k, L, R, row0);
         }
     }
     __syncthreads();
 
     const uint32_t up_wg = (r + nwg - 1) % nwg, dn_wg = (r + 1) % nwg;
+    // top row entirely in slot 0 and bottom row entirely in slot SPT-1
+    const bool early = nwg > 1 && SPT > 2 && upr <= nt && last0 >= (SPT - 1) * nt;
     uint32_t q = 0;  // pass counter
     for (uint64_t sweep = 0; sweep < a.n_sweeps; ++sweep) {
         for (int c = 0; c < 2; ++c, ++q) {
             int sh = 0;
             const uint32_t zero = *zero_word;
+            const uint32_t slot = q & 1;
+            uint8_t *mine = nwg > 1 ? a.halo + ((static_cast<uint64_t>(slot) * nwg + r) * 2) * L : nullptr;
+            const uint32_t target = a.epoch0 + q + 1;
 #pragma unroll
-            for (int i = 0; i < SPT; ++i) {
+            for (int j = 0; j < SPT; ++j) {
+                const int i = j == 0 ? SPT - 1 : j - 1;  // bottom-row slot, top-row slot, then the rest
                 const uint32_t k = t + i * nt;
                 if (k < a.units) {
                     // `zero` is reloaded from LDS every pass, so the addresses
                     // below cannot be hoisted out of the sweep loop and held
                     // per unit in registers.
                     const uint32_t pl = place[i] + zero;
-                    const uint32_t off = pl & 0x1FFFFFFFu;
+                    const uint32_t off = pl & kOffMask;
                     uint64_t w = lds_run<NB>(lds + off);
                     const uint64_t upw = lds_run<NB>(lds + off - L), dnw = lds_run<NB>(lds + off + L);
                     const uint32_t lb = lds[(pl >> 29) & 1 ? off + L - 1 : off - 1];
@@ -283,31 +347,29 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
 #pragma unroll
                     for (int h = 0; h < NB / 2; ++h) sh += metropolis(w, m, p + 2 * h, rr[h], a.T4, a.T8);
                     lds_put<NB>(lds + off, w);
+                    if (nwg > 1) {
+                        if ((pl >> 27) & 1) lds_put<NB>(mine + off - L, w);                // my top row
+                        if ((pl >> 28) & 1) lds_put<NB>(mine + off + L - R * L, w);        // my bottom row
+                    }
                 }
                 // keep units apart: only the held states stay live across units
                 __builtin_amdgcn_sched_barrier(0);
+                if (j == 1 && early) publish(a.flags + r, target, t);
             }
-            __syncthreads();
             if (nwg == 1) {
+                __syncthreads();
                 copy_bytes(lds, lds + R * L, L, t, nt);            // row above row 0 = last row
                 copy_bytes(lds + (R + 1) * L, lds + L, L, t, nt);  // row below the last = row 0
-            } else if (t < 64) {
-                // Wavefront 0 alone exchanges the boundary rows: publish mine,
-                // release, raise my flag, wait for both neighbours, acquire,
-                // read theirs.  Its own wait counters and cache write-back /
-                // invalidate then cover every access of the exchange.
-                const uint32_t slot = q & 1;
-                uint8_t *mine = a.halo + ((static_cast<uint64_t>(slot) * nwg + r) * 2) * L;
-                copy_bytes(mine, lds + L, L, t, 64);            // my top row
-                copy_bytes(mine + L, lds + R * L, L, t, 64);    // my bottom row
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __hip_atomic_store(a.flags + r, a.epoch0 + q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                wait_both(a.flags + up_wg, a.flags + dn_wg, a.epoch0 + q + 1, a.err);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            } else {
+                if (!early) publish(a.flags + r, target, t);
+                if (t < 64) {
+                    wait_both(a.flags + up_wg, a.flags + dn_wg, target, a.err);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+                __syncthreads();
                 const uint8_t *upn = a.halo + ((static_cast<uint64_t>(slot) * nwg + up_wg) * 2) * L + L;  // its bottom
                 const uint8_t *dnn = a.halo + ((static_cast<uint64_t>(slot) * nwg + dn_wg) * 2) * L;      // its top
-                copy_bytes(lds, upn, L, t, 64);
-                copy_bytes(lds + (R + 1) * L, dnn, L, t, 64);
+                copy_rows(lds, upn, lds + (R + 1) * L, dnn, L, t, nt);
             }
             if (c == 1 && a.trace) {
                 const int tot = block_sum(sh, red);

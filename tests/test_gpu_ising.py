@@ -89,7 +89,7 @@ def test_checkpoint_resume(rngx):
     assert np.array_equal(rngx.ising_get_spins(a), rngx.ising_get_spins(b))
 
 
-@pytest.mark.parametrize("kind", ["xs1024w", "philox4x32_10", "lcg32", "xorwow"])
+@pytest.mark.parametrize("kind", KINDS)
 def test_large_lattice_parity(rngx, orc, kind):
     """L = 4096 (the throughput workload) for 3 sweeps in two calls, bit-exact."""
     print(f"case ising L=4096 {kind}", flush=True)
@@ -98,7 +98,7 @@ def test_large_lattice_parity(rngx, orc, kind):
 
 
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("L", [368, 512, 1024, 2064])
+@pytest.mark.parametrize("L", [368, 512, 1024, 2048, 2064])
 def test_multi_strip_parity(rngx, orc, kind, L):
     """Lattices held as several on-chip strips that exchange halo rows."""
     print(f"case ising strips {kind} L={L}", flush=True)
