@@ -352,7 +352,6 @@ rngx_status rng_set_state(rngx_gen h, const void *host_buf, size_t bytes, void *
 static void free_ising(Ising *lat) {
     (void)hipFree(lat->d_spins);
     (void)hipFree(lat->d_halo);
-    (void)hipFree(lat->d_flags);
     (void)hipFree(lat->d_err);
     (void)hipFree(lat->d_partial);
     free_gen(lat->gen);
@@ -380,8 +379,7 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
     hipError_t e = hipMalloc(&lat->d_spins, static_cast<size_t>(L) * L);
     if (e == hipSuccess) e = hipMalloc(&lat->d_err, 4);
     if (e == hipSuccess && lat->plan.strips && lat->plan.nwg > 1) {
-        e = hipMalloc(&lat->d_halo, static_cast<size_t>(4) * lat->plan.nwg * L);
-        if (e == hipSuccess) e = hipMalloc(&lat->d_flags, 4ull * lat->plan.nwg);
+        e = hipMalloc(&lat->d_halo, static_cast<size_t>(8) * lat->plan.nwg * L);
     }
     if (e == hipSuccess && !lat->plan.strips) e = hipMalloc(&lat->d_partial, 4 * ising_partials(L));
     if (e != hipSuccess) {
@@ -392,7 +390,8 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
     e = launch_seed(g, seed, nullptr);
     if (e == hipSuccess) e = launch_hot_start(lat, seed, nullptr);
     if (e == hipSuccess) e = launch_zero(lat->d_err, 1, nullptr);
-    if (e == hipSuccess && lat->d_flags) e = launch_zero(lat->d_flags, lat->plan.nwg, nullptr);
+    if (e == hipSuccess && lat->d_halo)  // tag 0 matches no pass
+        e = launch_zero(reinterpret_cast<uint32_t *>(lat->d_halo), 2ull * lat->plan.nwg * L, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         free_ising(lat);

@@ -25,6 +25,7 @@
 // end, so E = -sum over colour-1 sites of s h = -sum (4 - 2 m_after).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "rngx_internal.h"
@@ -173,27 +174,33 @@ struct StripArgs {
     uint32_t L, R, nwg, units;  // units per strip
     uint64_t T4, T8, n_sweeps;
     int32_t *trace;             // may be null
-    uint8_t *halo;              // 2 slots x nwg x 2 rows x L bytes
-    uint32_t *flags;            // nwg pass counters
-    uint32_t epoch0;
+    uint64_t *halo;             // 2 slots x nwg x 2 rows x L/4 tagged words
+    uint32_t epoch0;            // pass tags of this call are epoch0 + 1, epoch0 + 2, ...
     uint32_t *err;
 };
 
 constexpr uint32_t kSpinLimit = 1u << 20;
 
-// Wait (one wavefront, all lanes reading the same words) until both flags
-// reach `target`.  Gives up after kSpinLimit polls and records that in *err;
-// once *err is set every later wait returns at once, so a failed exchange
-// ends the kernel quickly (with an invalid lattice) instead of stalling it.
-__device__ __forceinline__ void wait_both(uint32_t *f0, uint32_t *f1, uint32_t target, uint32_t *err) {
-    for (uint32_t it = 0; it < kSpinLimit; ++it) {
-        const uint32_t v0 = __hip_atomic_load(f0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t v1 = __hip_atomic_load(f1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (static_cast<int32_t>(v0 - target) >= 0 && static_cast<int32_t>(v1 - target) >= 0) return;
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-        __builtin_amdgcn_s_sleep(2);
+// Halo words: 4 spins in the low half, the pass tag in the high half, both
+// written by one 64-bit agent-scope atomic store, so a word read with the
+// expected tag holds that pass's spins.  Polls one word until its tag is
+// `tag`; gives up after kSpinLimit polls and records that in *err (once set,
+// every later poll returns at once, so a failed exchange ends the kernel
+// quickly with an invalid lattice instead of stalling it).
+__device__ __forceinline__ uint32_t poll_word(const uint64_t *p, uint64_t v, uint32_t tag, uint32_t *err) {
+    for (uint32_t it = 0; static_cast<uint32_t>(v >> 32) != tag; ++it) {
+        if (it >= kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return static_cast<uint32_t>(v);
+}
+
+__device__ __forceinline__ void put_word(uint64_t *p, uint32_t spins, uint32_t tag) {
+    __hip_atomic_store(p, (static_cast<uint64_t>(tag) << 32) | spins, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // n bytes, n a multiple of 16 and both ends 16-byte aligned (rows are L
@@ -216,27 +223,6 @@ __device__ __forceinline__ void copy_rows(uint8_t *dst0, const uint8_t *src0, ui
     }
 }
 
-// s_waitcnt immediate that waits for vector memory counter 0 only (gfx9
-// encoding: vmcnt bits 3:0 and 15:14 zero, expcnt 7, lgkmcnt 15).
-constexpr unsigned kWaitVm0 = 0x0F70;
-
-// Make this pass's halo stores of every thread visible at agent scope, then
-// raise the strip's pass counter.  Each wave waits until its own stores have
-// reached this XCD's L2 (a workgroup barrier does not wait for them); after
-// the barrier wavefront 0 alone writes the L2 back (agent-scope release,
-// one write-back for the whole block) and waits for it before the counter
-// store.  A release fence in every wave would work too but costs one L2
-// write-back per wave.
-__device__ __forceinline__ void publish(uint32_t *flag, uint32_t target, uint32_t t) {
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    __syncthreads();
-    if (t < 64) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        if (t == 0) __hip_atomic_store(flag, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
 // Sum of v over the block (result valid in thread 0).
 __device__ __forceinline__ int block_sum(int v, int *scratch) {
 #pragma unroll
@@ -251,15 +237,69 @@ __device__ __forceinline__ int block_sum(int v, int *scratch) {
     return s;
 }
 
-// Unit k of the strip sits at byte offset `off` of LDS (row yl+1); bit 27:
+// ---------------------------------------------------------------- on-chip update
+// LDS holds the strip's rows (and one halo row above and below) at a pitch
+// of L + 2*kPad bytes with the spins at +kPad; the word just before a row's
+// spins is a copy of its last four spins and the word just after them a copy
+// of its first four ("ghost" words), so every run finds its left and right
+// neighbours at fixed offsets.
+constexpr uint32_t kPad = 16;
+__host__ __device__ constexpr uint32_t lds_pitch(uint32_t L) { return L + 2 * kPad; }
+// Rows: 0 and R+1 the rows above and below the strip (halo buffer 0),
+// 1..R the strip, R+2 and R+3 halo buffer 1; then 64 bytes of per-wave sums
+// and a zero word.
+__host__ __device__ constexpr uint64_t strip_lds_bytes(uint32_t L, uint32_t R) {
+    return static_cast<uint64_t>(R + 4) * lds_pitch(L) + 80;
+}
+
+// Acceptance in 32 bits.  With d = twice the number of a site's neighbours
+// that differ from it (0, 2, .., 8), the flip is taken if d >= lo, else iff
+// r < (d == 2 ? t4 : t8).  lo is 4 except when a threshold is 2^32 (every
+// draw accepts), which 32 bits cannot hold: lo = 2 when that is T4, lo = 0
+// when it is T8 (and then also T4, since T8 <= T4).
+struct Accept {
+    uint32_t t4, t8, lo;
+};
+__device__ __forceinline__ Accept make_accept(uint64_t T4, uint64_t T8) {
+    constexpr uint64_t kAll = 1ull << 32;
+    return Accept{T4 >= kAll ? 0xFFFFFFFFu : static_cast<uint32_t>(T4), T8 >= kAll ? 0xFFFFFFFFu : static_cast<uint32_t>(T8),
+                  T8 >= kAll ? 0u : T4 >= kAll ? 2u : 4u};
+}
+
+// Twice the number of differing neighbours of each byte of a 4-spin word w
+// (spins +-1 as int8: two differ iff bit 1 of their xor is set); l and r are
+// the words left and right of w, u and d the words above and below.
+__device__ __forceinline__ uint32_t mismatch2(uint32_t w, uint32_t l, uint32_t r, uint32_t u, uint32_t d) {
+    constexpr uint32_t kBit1 = 0x02020202u;
+    const uint32_t left = __builtin_amdgcn_alignbit(w, l, 24);  // byte i: spin i-1
+    const uint32_t right = __builtin_amdgcn_alignbit(r, w, 8);  // byte i: spin i+1
+    return ((w ^ u) & kBit1) + ((w ^ d) & kBit1) + ((w ^ left) & kBit1) + ((w ^ right) & kBit1);
+}
+
+// Metropolis decision for the byte at bit offset sh of a word with doubled
+// counts m2 and draw r: returns f (the flip mask of that byte) if accepted,
+// else 0.  With E, adds the byte's doubled count after the step to *esum.
+template <bool E>
+__device__ __forceinline__ uint32_t decide(uint32_t m2, uint32_t sh, uint32_t f, uint32_t r, const Accept &A,
+                                           uint32_t &esum) {
+    const uint32_t d = __builtin_amdgcn_ubfe(m2, sh, 8);
+    // three compares combined as lane masks (no select of the threshold)
+    const bool two = d == 2;
+    const bool acc = (d >= A.lo) | (two & (r < A.t4)) | (!two & (r < A.t8));
+    if constexpr (E) esum += acc ? 8 - d : d;
+    return acc ? f : 0u;
+}
+
+// Unit k of the strip starts at LDS offset `off` (its row yl+1); bit 27:
 // unit in the strip's top row, bit 28: in its bottom row, bit 29: run starts
-// at x = 0, bit 30: run ends at x = L-1, bit 31: (row0+yl) odd.
+// the row, bit 30: run ends the row, bit 31: (row0+yl) odd, i.e. its
+// colour-c sites are the odd bytes when c = 0.
 constexpr uint32_t kOffMask = (1u << 27) - 1;
 template <int NB>
 __device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint32_t R, uint64_t row0) {
     const uint32_t upr = L / NB;
     const uint32_t yl = k / upr, x0 = (k % upr) * NB;
-    uint32_t off = (yl + 1) * L + x0;
+    uint32_t off = (yl + 1) * lds_pitch(L) + kPad + x0;
     if (yl == 0) off |= 1u << 27;
     if (yl == R - 1) off |= 1u << 28;
     if (x0 == 0) off |= 1u << 29;
@@ -268,122 +308,244 @@ __device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint32_t 
     return off;
 }
 
-// All sweeps of strip r (R rows at row r*R) held in `lds` ((R+2)*L + 80
-// bytes: rows, block-sum scratch, a zero word) by the calling workgroup.
+// Colour-c update of the unit at `pl` (place word, made opaque per pass);
+// returns its new spins.  The rows above and below are read at off - P +
+// up_add and off + P + dn_add (non-zero only to reach halo buffer 1).  The
+// draws go to the colour-c bytes in increasing order.
+template <class Unit, bool E>
+__device__ __forceinline__ uint64_t update_unit(uint8_t *lds, uint32_t pl, uint32_t P, uint32_t up_add, uint32_t dn_add,
+                                                int c, Unit &u, const Accept &A, uint32_t &esum) {
+    constexpr int NB = Unit::kNB;
+    const uint32_t off = pl & kOffMask;
+    const uint32_t sh0 = ((pl >> 31) ^ static_cast<uint32_t>(c)) << 3;  // bit offset of the first colour-c byte
+    const uint32_t f0 = 0xFEu << sh0, f1 = f0 << 16;                     // flip masks (+1 <-> -1)
+    const uint32_t *l32 = reinterpret_cast<const uint32_t *>(lds + off);
+    uint32_t rr[NB / 2];
+    u.draw(rr);
+    if constexpr (NB == 4) {
+        const uint32_t w = l32[0];
+        const uint32_t m2 = mismatch2(w, l32[-1], l32[1], *reinterpret_cast<const uint32_t *>(lds + off - P + up_add),
+                                      *reinterpret_cast<const uint32_t *>(lds + off + P + dn_add));
+        const uint32_t g0 = decide<E>(m2, sh0, f0, rr[0], A, esum);
+        const uint32_t g1 = decide<E>(m2, sh0 + 16, f1, rr[1], A, esum);
+        const uint32_t nw = w ^ (g0 | g1);
+        *reinterpret_cast<uint32_t *>(lds + off) = nw;
+        return nw;
+    } else {
+        const uint2 w = *reinterpret_cast<const uint2 *>(lds + off);
+        const uint2 up = *reinterpret_cast<const uint2 *>(lds + off - P + up_add);
+        const uint2 dn = *reinterpret_cast<const uint2 *>(lds + off + P + dn_add);
+        const uint32_t m2a = mismatch2(w.x, l32[-1], w.y, up.x, dn.x);
+        const uint32_t m2b = mismatch2(w.y, w.x, l32[2], up.y, dn.y);
+        const uint32_t g0 = decide<E>(m2a, sh0, f0, rr[0], A, esum);
+        const uint32_t g1 = decide<E>(m2a, sh0 + 16, f1, rr[1], A, esum);
+        const uint32_t g2 = decide<E>(m2b, sh0, f0, rr[2], A, esum);
+        const uint32_t g3 = decide<E>(m2b, sh0 + 16, f1, rr[3], A, esum);
+        const uint2 nw = make_uint2(w.x ^ (g0 | g1), w.y ^ (g2 | g3));
+        *reinterpret_cast<uint2 *>(lds + off) = nw;
+        return (static_cast<uint64_t>(nw.y) << 32) | nw.x;
+    }
+}
+
+// Ghost words of LDS rows [y0, y1) from the same rows' spins.
+__device__ __forceinline__ void refresh_ghosts(uint8_t *lds, uint32_t L, uint32_t y0, uint32_t y1, uint32_t t,
+                                               uint32_t nt) {
+    const uint32_t P = lds_pitch(L);
+    for (uint32_t i = 2 * y0 + t; i < 2 * y1; i += nt) {
+        uint8_t *row = lds + (i >> 1) * P + kPad;
+        if (i & 1) *reinterpret_cast<uint32_t *>(row + L) = *reinterpret_cast<const uint32_t *>(row);
+        else *reinterpret_cast<uint32_t *>(row - 4) = *reinterpret_cast<const uint32_t *>(row + L - 4);
+    }
+}
+
+// R rows of L spins between global memory (L apart) and LDS (pitch apart).
+template <bool TO_LDS>
+__device__ __forceinline__ void copy_strip(uint8_t *lds_row1, int8_t *g, uint32_t L, uint32_t R, uint32_t t, uint32_t nt) {
+    const uint32_t n16 = L / 16, P = lds_pitch(L);
+    for (uint32_t i = t; i < R * n16; i += nt) {
+        const uint32_t y = i / n16, x = (i - y * n16) * 16;
+        uint4 *l = reinterpret_cast<uint4 *>(lds_row1 + y * P + x);
+        uint4 *m = reinterpret_cast<uint4 *>(g + static_cast<uint64_t>(y) * L + x);
+        if constexpr (TO_LDS) *l = *m;
+        else *m = *l;
+    }
+}
+
+// A unit whose run starts (bit 29) or ends (bit 30) its row also refreshes
+// the row's ghost word on that side (run: the run's first spin in LDS).
+// Other threads may read that ghost during the pass, but only its
+// other-colour byte, which this update does not change.
+template <int NB>
+__device__ __forceinline__ void edge_ghosts(uint8_t *run, uint32_t pl, uint32_t L, uint64_t nw) {
+    if ((pl >> 29) & 1) *reinterpret_cast<uint32_t *>(run + L) = static_cast<uint32_t>(nw);  // first 4 spins
+    if ((pl >> 30) & 1)                                                                      // last 4 spins
+        *reinterpret_cast<uint32_t *>(run + NB - L - 4) = static_cast<uint32_t>(nw >> (8 * (NB - 4)));
+}
+
+// All sweeps of strip r (R rows at row r*R) held in `lds`
+// (strip_lds_bytes(L, R)) by the calling workgroup.
 //
-// With several strips, each colour pass is scheduled around the exchange of
-// boundary rows with the strips above and below:
-//   1. update the slots holding the strip's top and bottom rows; each thread
-//      also stores its updated boundary runs into this pass's halo slot;
-//   2. publish: every wave fences its stores at agent scope, then after a
-//      barrier wavefront 0 raises the strip's pass counter;
-//   3. update the interior slots while the neighbours do the same;
-//   4. wavefront 0 waits for both neighbours' counters and acquires; after a
-//      barrier all threads pull the two neighbour rows into LDS.
-// Sites of one colour are independent within a pass, so the slot order does
-// not change any result.  When a row does not fit in one slot (wide lattices,
-// few threads) the publish moves after the last slot.
-template <class Unit, int SPT>
+// Pass q reads the halo rows of buffer q&1 and fills buffer (q+1)&1, so a
+// pass needs a single barrier (before it starts):
+//   - every unit updates its sites and, at a row end, the row's ghost word;
+//   - with one strip (periodic in y) the units of the top and bottom rows
+//     also write their new runs into the other side's row of the next
+//     buffer;
+//   - with several strips they store them as tagged words into pass q's
+//     halo slot in global memory, and every thread pulls its share of the
+//     neighbours' tagged words (loads issued some slots before the end,
+//     polled until the tags say pass q) into the next buffer.
+// Sites of one colour are independent within a pass, so the slot order changes
+// no result; the slots holding the top and bottom rows go first so that the
+// neighbours' words are ready when pulled.
+template <class Unit, int SPT, bool EARLY>
 __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8_t *lds) {
     constexpr int NB = Unit::kNB;
     const uint32_t L = a.L, R = a.R, nwg = a.nwg, t = threadIdx.x, nt = blockDim.x;
+    const uint32_t P = lds_pitch(L);
     const uint64_t row0 = static_cast<uint64_t>(r) * R;
-    const uint32_t strip_bytes = R * L;
-    const uint32_t upr = L / NB;               // units per row
-    const uint32_t last0 = a.units - upr;      // first unit of the bottom row
-    int *red = reinterpret_cast<int *>(lds + (R + 2) * L);
-    uint32_t *zero_word = reinterpret_cast<uint32_t *>(lds + (R + 2) * L + 64);
+    const uint32_t upr = L / NB;             // units per row
+    const uint32_t last0 = a.units - upr;    // first unit of the bottom row
+    const uint32_t W = L / 4;                // halo words per row
+    int *wave_e = reinterpret_cast<int *>(lds + (R + 4) * P);
+    uint32_t *zero_word = reinterpret_cast<uint32_t *>(lds + (R + 4) * P + 64);
     if (t == 0) *zero_word = 0;
+    // interiors of the halo rows (above, below) of buffers 0 and 1
+    const uint32_t h_up[2] = {kPad, (R + 2) * P + kPad}, h_dn[2] = {(R + 1) * P + kPad, (R + 3) * P + kPad};
 
-    // strip and initial halo rows from the lattice
-    const int8_t *gs = a.spins;
-    copy_bytes(lds + L, reinterpret_cast<const uint8_t *>(gs + row0 * L), strip_bytes, t, nt);
+    // strip and halo rows (buffer 0) from the lattice, then every ghost word
+    const uint8_t *gs = reinterpret_cast<const uint8_t *>(a.spins);
+    copy_strip<true>(lds + P + kPad, a.spins + row0 * L, L, R, t, nt);
     const uint64_t up_row = (row0 + L - 1) % L, dn_row = (row0 + R) % L;
-    copy_bytes(lds, reinterpret_cast<const uint8_t *>(gs + up_row * L), L, t, nt);
-    copy_bytes(lds + (R + 1) * L, reinterpret_cast<const uint8_t *>(gs + dn_row * L), L, t, nt);
+    copy_rows(lds + h_up[0], gs + up_row * L, lds + h_dn[0], gs + dn_row * L, L, t, nt);
+    __syncthreads();
+    refresh_ghosts(lds, L, 0, R + 2, t, nt);
 
     const uint64_t ubase = static_cast<uint64_t>(r) * a.units;
     Unit u[SPT];
     uint32_t place[SPT];
+    uint32_t my_units = 0;
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
         const uint32_t k = t + i * nt;
         if (k < a.units) {
             u[i].load(a.st, a.S, ubase + k);
             place[i] = unit_place<NB>(k, L, R, row0);
+            ++my_units;
         }
     }
-    __syncthreads();
+    const Accept A = make_accept(a.T4, a.T8);
 
     const uint32_t up_wg = (r + nwg - 1) % nwg, dn_wg = (r + 1) % nwg;
-    // top row entirely in slot 0 and bottom row entirely in slot SPT-1
-    const bool early = nwg > 1 && SPT > 2 && upr <= nt && last0 >= (SPT - 1) * nt;
+    // EARLY: top row entirely in slot 0 and bottom row entirely in slot
+    // SPT-1, so only those two slots hold boundary units (the host picks the
+    // instantiation with the same test).
+    constexpr bool early = EARLY;
+    constexpr int kPullAt = SPT >= 4 ? SPT * 5 / 8 : SPT - 1;  // neighbours' words requested after this slot
     uint32_t q = 0;  // pass counter
-    for (uint64_t sweep = 0; sweep < a.n_sweeps; ++sweep) {
-        for (int c = 0; c < 2; ++c, ++q) {
-            int sh = 0;
-            const uint32_t zero = *zero_word;
-            const uint32_t slot = q & 1;
-            uint8_t *mine = nwg > 1 ? a.halo + ((static_cast<uint64_t>(slot) * nwg + r) * 2) * L : nullptr;
-            const uint32_t target = a.epoch0 + q + 1;
+
+    // trace[sweep] from the wave sums of that sweep's colour-1 pass (read
+    // after the barrier that follows them), by the last wavefront.
+    auto flush_energy = [&](uint64_t sweep) {
+        if (a.trace && t >= nt - 64) {
+            const uint32_t lane = t & 63;
+            int v = lane < (nt >> 6) ? wave_e[lane] : 0;
 #pragma unroll
-            for (int j = 0; j < SPT; ++j) {
-                const int i = j == 0 ? SPT - 1 : j - 1;  // bottom-row slot, top-row slot, then the rest
-                const uint32_t k = t + i * nt;
-                if (k < a.units) {
-                    // `zero` is reloaded from LDS every pass, so the addresses
-                    // below cannot be hoisted out of the sweep loop and held
-                    // per unit in registers.
-                    const uint32_t pl = place[i] + zero;
-                    const uint32_t off = pl & kOffMask;
-                    uint64_t w = lds_run<NB>(lds + off);
-                    const uint64_t upw = lds_run<NB>(lds + off - L), dnw = lds_run<NB>(lds + off + L);
-                    const uint32_t lb = lds[(pl >> 29) & 1 ? off + L - 1 : off - 1];
-                    const uint32_t rb = lds[(pl >> 30) & 1 ? off + NB - L : off + NB];
-                    const uint64_t m = mismatches<NB>(w, upw, dnw, lb, rb);
-                    const int p = (c + (pl >> 31)) & 1;
-                    uint32_t rr[NB / 2];
-                    u[i].draw(rr);
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) {
+                if (nwg == 1) a.trace[sweep] = -v;  // the only contributor
+                else atomicAdd(a.trace + sweep, -v);
+            }
+        }
+    };
+
+    // One colour pass; E: accumulate the energy terms (colour 1 with a trace).
+    auto pass = [&](auto e_tag, int c, uint64_t sweep) {
+        constexpr bool E = decltype(e_tag)::value;
+        __syncthreads();  // pass q-1 done, buffer q&1 complete
+        if (c == 0 && sweep > 0) flush_energy(sweep - 1);  // colour 1 of the previous sweep
+        const uint32_t cur = q & 1, nxt = cur ^ 1;
+        const uint32_t tag = a.epoch0 + q + 1;
+        const uint32_t up_add = h_up[cur] - h_up[0], dn_add = h_dn[cur] - h_dn[0];
+        uint64_t *mine = nwg > 1 ? a.halo + (static_cast<uint64_t>(cur) * nwg + r) * 2 * W : nullptr;  // [top][bottom]
+        const uint64_t *from_up = nwg > 1 ? a.halo + ((static_cast<uint64_t>(cur) * nwg + up_wg) * 2 + 1) * W : nullptr;
+        const uint64_t *from_dn = nwg > 1 ? a.halo + (static_cast<uint64_t>(cur) * nwg + dn_wg) * 2 * W : nullptr;
+        // my pulled words: i = t + m nt (< 2W), i < W from the strip above
+        auto src_word = [&](uint32_t i) { return i < W ? from_up + i : from_dn + (i - W); };
+        uint64_t pre0 = 0, pre1 = 0;
+        auto request = [&]() {
+            if (t < 2 * W) pre0 = __hip_atomic_load(src_word(t), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t + nt < 2 * W) pre1 = __hip_atomic_load(src_word(t + nt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
+        uint32_t esum = 0;
+        const uint32_t zero = *zero_word;
 #pragma unroll
-                    for (int h = 0; h < NB / 2; ++h) sh += metropolis(w, m, p + 2 * h, rr[h], a.T4, a.T8);
-                    lds_put<NB>(lds + off, w);
+        for (int j = 0; j < SPT; ++j) {
+            const int i = j == 0 ? SPT - 1 : j - 1;  // bottom-row slot, top-row slot, then the rest
+            const uint32_t k = t + i * nt;
+            const bool bslot = !early || j <= 1;      // may hold top- or bottom-row units
+            if (k < a.units) {
+                // `zero` is reloaded from LDS every pass, so the addresses
+                // derived from `pl` cannot be hoisted out of the sweep loop
+                // and held per unit in registers.
+                const uint32_t pl = place[i] + zero;
+                const bool top = bslot && ((pl >> 27) & 1), bot = bslot && ((pl >> 28) & 1);
+                const uint64_t nw = update_unit<Unit, E>(lds, pl, P, top ? up_add : 0u, bot ? dn_add : 0u, c, u[i], A, esum);
+                const uint32_t off = pl & kOffMask;
+                const uint32_t yrow = top ? 1 : bot ? R : 0;   // only used for boundary units
+                const uint32_t x0 = off - kPad - yrow * P;
+                if ((pl >> 29) & 3) edge_ghosts<NB>(lds + off, pl, L, nw);
+                if (top || bot) {
                     if (nwg > 1) {
-                        if ((pl >> 27) & 1) lds_put<NB>(mine + off - L, w);                // my top row
-                        if ((pl >> 28) & 1) lds_put<NB>(mine + off + L - R * L, w);        // my bottom row
+                        uint64_t *dst = mine + (bot ? W : 0) + x0 / 4;
+                        put_word(dst, static_cast<uint32_t>(nw), tag);
+                        if constexpr (NB == 8) put_word(dst + 1, static_cast<uint32_t>(nw >> 32), tag);
+                    } else {
+                        // periodic in y: the top row is the row below the bottom row
+                        uint8_t *row = lds + (top ? h_dn[nxt] : h_up[nxt]);
+                        lds_put<NB>(row + x0, nw);
+                        if ((pl >> 29) & 3) edge_ghosts<NB>(row + x0, pl, L, nw);
                     }
                 }
-                // keep units apart: only the held states stay live across units
-                __builtin_amdgcn_sched_barrier(0);
-                if (j == 1 && early) publish(a.flags + r, target, t);
             }
-            if (nwg == 1) {
-                __syncthreads();
-                copy_bytes(lds, lds + R * L, L, t, nt);            // row above row 0 = last row
-                copy_bytes(lds + (R + 1) * L, lds + L, L, t, nt);  // row below the last = row 0
-            } else {
-                if (!early) publish(a.flags + r, target, t);
-                if (t < 64) {
-                    wait_both(a.flags + up_wg, a.flags + dn_wg, target, a.err);
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                }
-                __syncthreads();
-                const uint8_t *upn = a.halo + ((static_cast<uint64_t>(slot) * nwg + up_wg) * 2) * L + L;  // its bottom
-                const uint8_t *dnn = a.halo + ((static_cast<uint64_t>(slot) * nwg + dn_wg) * 2) * L;      // its top
-                copy_rows(lds, upn, lds + (R + 1) * L, dnn, L, t, nt);
-            }
-            if (c == 1 && a.trace) {
-                const int tot = block_sum(sh, red);
-                if (t == 0) {
-                    if (nwg == 1) a.trace[sweep] = -tot;  // the only contributor
-                    else atomicAdd(a.trace + sweep, -tot);
-                }
-            }
-            __syncthreads();
+            // keep units apart: only the held states stay live across units
+            __builtin_amdgcn_sched_barrier(0);
+            if (nwg > 1 && early && j == kPullAt) request();
         }
+        if (nwg > 1) {
+            if (!early) request();
+            // the neighbours' pass-q words into buffer nxt, with ghosts
+            for (uint32_t i = t, m = 0; i < 2 * W; i += nt, ++m) {
+                const uint64_t *sp = src_word(i);
+                const uint64_t v0 = m == 0 ? pre0 : m == 1 ? pre1 : __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t v = poll_word(sp, v0, tag, a.err);
+                const uint32_t wi = i < W ? i : i - W;
+                uint8_t *row = lds + (i < W ? h_up[nxt] : h_dn[nxt]);
+                *reinterpret_cast<uint32_t *>(row + 4 * wi) = v;
+                if (wi == 0) *reinterpret_cast<uint32_t *>(row + L) = v;
+                if (wi == W - 1) *reinterpret_cast<uint32_t *>(row - 4) = v;
+            }
+        }
+        if constexpr (E) {
+            // each colour-1 site adds s*h = 4 - (doubled count after the step)
+            int v = static_cast<int>(2 * NB * my_units) - static_cast<int>(esum);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if ((t & 63) == 0) wave_e[t >> 6] = v;
+        }
+        ++q;
+    };
+
+    for (uint64_t sweep = 0; sweep < a.n_sweeps; ++sweep) {
+        pass(std::false_type{}, 0, sweep);
+        if (a.trace) pass(std::true_type{}, 1, sweep);
+        else pass(std::false_type{}, 1, sweep);
     }
+    __syncthreads();
+    if (a.n_sweeps > 0) flush_energy(a.n_sweeps - 1);
 
     // write back spins and state
-    copy_bytes(reinterpret_cast<uint8_t *>(a.spins + row0 * L), lds + L, strip_bytes, t, nt);
+    copy_strip<false>(lds + P + kPad, a.spins + row0 * L, L, R, t, nt);
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
         const uint32_t k = t + i * nt;
@@ -391,14 +553,24 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
     }
 }
 
-template <class Unit, int SPT>
+// EARLY: the strip's top row lies in slot 0 and its bottom row in slot SPT-1.
+template <int SPT>
+__host__ __device__ constexpr bool early_slots(uint32_t upr, uint32_t units, uint32_t nt) {
+    return SPT > 2 && upr <= nt && units - upr >= (SPT - 1) * nt;
+}
+
+template <class Unit, int SPT, bool EARLY>
 __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     // Blocks b, b+8, b+16, ... share an XCD: give them consecutive strips so
     // that most neighbour exchanges stay inside one L2.
     const uint32_t b = blockIdx.x, nwg = a.nwg;
     const uint32_t r = (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
-    strip_body<Unit, SPT>(a, r, lds);
+    if (early_slots<SPT>(a.L / Unit::kNB, a.units, blockDim.x) != EARLY) {  // plan and kernel disagree
+        if (threadIdx.x == 0) __hip_atomic_fetch_or(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    strip_body<Unit, SPT, EARLY>(a, r, lds);
 }
 
 // ---------------------------------------------------------------- per pass
@@ -503,8 +675,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc
         const ReplicaDesc d = reps[order[idx]];
         if (d.on_chip) {
             const StripArgs a{d.spins, d.st, d.S, d.L, d.L, 1, static_cast<uint32_t>(static_cast<uint64_t>(d.L) * d.L / NB),
-                              d.T4, d.T8, d.n_sweeps, d.trace, nullptr, nullptr, 0, nullptr};
-            strip_body<Unit, batch_spt<Unit>()>(a, 0, lds);
+                              d.T4, d.T8, d.n_sweeps, d.trace, nullptr, 0, nullptr};
+            constexpr int spt = batch_spt<Unit>();
+            if (early_slots<spt>(d.L / NB, a.units, blockDim.x)) strip_body<Unit, spt, true>(a, 0, lds);
+            else strip_body<Unit, spt, false>(a, 0, lds);
         } else {
             replica_in_memory<Unit>(d, red_s);
         }
@@ -524,19 +698,29 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const int32_t *partial
 constexpr uint32_t kLdsMax = 160 * 1024;
 constexpr uint32_t kMaxThreads = 1024;
 
-template <class Unit, int SPT>
-const void *strip_kernel() { return reinterpret_cast<const void *>(&k_ising_strip<Unit, SPT>); }
+template <class Unit, int SPT, bool EARLY>
+const void *strip_kernel() { return reinterpret_cast<const void *>(&k_ising_strip<Unit, SPT, EARLY>); }
 
 template <class Unit>
-const void *strip_kernel_for(int spt) {
+const void *strip_kernel_for(int spt, bool early) {
     switch (spt) {
-    case 1: return strip_kernel<Unit, 1>();
-    case 2: return strip_kernel<Unit, 2>();
-    case 4: return strip_kernel<Unit, 4>();
-    case 8: return strip_kernel<Unit, 8>();
-    case 16: return strip_kernel<Unit, 16>();
+    case 1: return strip_kernel<Unit, 1, false>();
+    case 2: return strip_kernel<Unit, 2, false>();
+    case 4: return early ? strip_kernel<Unit, 4, true>() : strip_kernel<Unit, 4, false>();
+    case 8: return early ? strip_kernel<Unit, 8, true>() : strip_kernel<Unit, 8, false>();
+    case 16: return early ? strip_kernel<Unit, 16, true>() : strip_kernel<Unit, 16, false>();
     }
     return nullptr;
+}
+
+// Host twin of early_slots for a run-time SPT.
+inline bool plan_early(int spt, uint32_t upr, uint32_t units, uint32_t nt) {
+    switch (spt) {
+    case 4: return early_slots<4>(upr, units, nt);
+    case 8: return early_slots<8>(upr, units, nt);
+    case 16: return early_slots<16>(upr, units, nt);
+    }
+    return false;
 }
 
 template <class Unit>
@@ -564,15 +748,16 @@ hipError_t run_strips(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t 
         hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                            reinterpret_cast<uint32_t *>(tr), n);
     }
-    if (lat->epoch + 2 * n + 2 >= (1ull << 31)) {  // restart the pass counters before they wrap
-        hipLaunchKernelGGL(k_zero_u32, dim3((pl.nwg + kBlock - 1) / kBlock), dim3(kBlock), 0, st, lat->d_flags,
-                           static_cast<uint64_t>(pl.nwg));
+    if (pl.nwg > 1 && lat->epoch + 2 * n + 2 >= (1ull << 31)) {  // restart the pass tags before they wrap
+        const uint64_t words = 2ull * pl.nwg * lat->L;              // halo size in uint32
+        hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((words + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           reinterpret_cast<uint32_t *>(lat->d_halo), words);
         lat->epoch = 0;
     }
     StripArgs a{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, pl.R, pl.nwg, pl.units, T4, T8, n,
-                tr, lat->d_halo, lat->d_flags, static_cast<uint32_t>(lat->epoch), lat->d_err};
+                tr, lat->d_halo, static_cast<uint32_t>(lat->epoch), lat->d_err};
     void *args[] = {&a};
-    const void *fn = strip_kernel_for<Unit>(pl.spt);
+    const void *fn = strip_kernel_for<Unit>(pl.spt, pl.early);
     hipError_t e;
     if (pl.nwg == 1)
         e = hipLaunchKernel(fn, dim3(1), dim3(pl.threads), args, pl.lds, st);
@@ -589,7 +774,8 @@ bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out)
     constexpr uint32_t NB = Unit::kNB;
     if (nwg == 0 || L % nwg) return false;
     const uint32_t R = L / nwg;
-    const uint64_t lds = static_cast<uint64_t>(R + 2) * L + 80;
+    if (R < 2) return false;  // a strip's top and bottom rows are distinct
+    const uint64_t lds = strip_lds_bytes(L, R);
     if (lds > kLdsMax) return false;
     const uint64_t sites = static_cast<uint64_t>(R) * L;
     if (NB == 8 && sites % 128) return false;  // whole XS1024W instances per strip
@@ -599,7 +785,8 @@ bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out)
     if (spt > max_spt) return false;
     uint32_t threads = (units + spt - 1) / spt;
     threads = (threads + 63) / 64 * 64;
-    const void *fn = strip_kernel_for<Unit>(spt);
+    const bool early = plan_early(spt, L / NB, units, threads);
+    const void *fn = strip_kernel_for<Unit>(spt, early);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     (void)hipGetLastError();
     int occ = 0;
@@ -609,7 +796,7 @@ bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out)
         return false;
     }
     if (static_cast<uint64_t>(occ) * n_cu < nwg) return false;
-    *out = IsingPlan{true, R, nwg, units, static_cast<uint32_t>(spt), threads, static_cast<uint32_t>(lds)};
+    *out = IsingPlan{true, R, nwg, units, static_cast<uint32_t>(spt), threads, static_cast<uint32_t>(lds), early};
     return true;
 }
 
@@ -667,7 +854,7 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
     uint32_t lds = 80;
     for (uint32_t i = 0; i < n; ++i) {
         const Ising *l = lats[i];
-        const uint64_t L = l->L, units = L * L / nb, bytes = (L + 2) * L + 80;
+        const uint64_t L = l->L, units = L * L / nb, bytes = strip_lds_bytes(l->L, l->L);
         const uint64_t spt = nb == 8 ? 8 : 16;
         const bool on_chip = units <= spt * kBatchThreads && bytes <= kBatchLdsCap;
         reps[i] = ReplicaDesc{l->d_spins, l->gen->d_state, l->gen->S, l->L, on_chip ? 1u : 0u,

@@ -71,6 +71,7 @@ struct IsingPlan {
     uint32_t spt;      // units per thread
     uint32_t threads;  // threads per workgroup
     uint32_t lds;      // dynamic LDS bytes per workgroup
+    bool early;        // top and bottom rows in the first and last unit slots
 };
 
 struct Ising {
@@ -80,11 +81,10 @@ struct Ising {
     int8_t *d_spins;
     Gen *gen;
     IsingPlan plan;
-    uint8_t *d_halo;     // strips: 2 slots x nwg x 2 rows x L bytes
-    uint32_t *d_flags;   // strips: per-strip pass counters
+    uint64_t *d_halo;    // strips: 2 slots x nwg x 2 rows x L/4 tagged words (4 spins | pass tag << 32)
     uint32_t *d_err;     // strips: set if a neighbour wait gave up
     int32_t *d_partial;  // per-pass path: per-block energy partials
-    uint64_t epoch;      // pass counter value the flags have reached
+    uint64_t epoch;      // passes run since the halo tags were last cleared
     uint32_t batches;    // batches that hold this lattice
 };
 
