@@ -398,7 +398,14 @@ __device__ __forceinline__ void edge_ghosts(uint8_t *run, uint32_t pl, uint32_t 
 // Sites of one colour are independent within a pass, so the slot order changes
 // no result; the slots holding the top and bottom rows go first so that the
 // neighbours' words are ready when pulled.
-template <class Unit, int SPT, bool EARLY>
+// Place words in LDS (after the per-wave sums) instead of registers when a
+// thread's unit states are large: frees SPT registers for kinds that would
+// otherwise spill.  The batch kernel keeps them in registers (its LDS budget
+// is tighter).
+template <class Unit, int SPT>
+__host__ __device__ constexpr bool place_in_lds() { return SPT * (sizeof(Unit) / 4 + 1) >= 40; }
+
+template <class Unit, int SPT, bool EARLY, bool PLDS>
 __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8_t *lds) {
     constexpr int NB = Unit::kNB;
     const uint32_t L = a.L, R = a.R, nwg = a.nwg, t = threadIdx.x, nt = blockDim.x;
@@ -423,14 +430,17 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
 
     const uint64_t ubase = static_cast<uint64_t>(r) * a.units;
     Unit u[SPT];
-    uint32_t place[SPT];
+    uint32_t place[PLDS ? 1 : SPT];
+    uint32_t *place_lds = reinterpret_cast<uint32_t *>(lds + (R + 4) * P + 80);  // [slot][thread] when PLDS
     uint32_t my_units = 0;
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
         const uint32_t k = t + i * nt;
         if (k < a.units) {
             u[i].load(a.st, a.S, ubase + k);
-            place[i] = unit_place<NB>(k, L, R, row0);
+            const uint32_t pw = unit_place<NB>(k, L, R, row0);
+            if constexpr (PLDS) place_lds[i * nt + t] = pw;
+            else place[i] = pw;
             ++my_units;
         }
     }
@@ -459,7 +469,7 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
         }
     };
 
-    // One colour pass; E: accumulate the energy terms (colour 1 with a trace).
+    // One colour pass; E: accumulate the energy terms (colour 1).
     auto pass = [&](auto e_tag, int c, uint64_t sweep) {
         constexpr bool E = decltype(e_tag)::value;
         __syncthreads();  // pass q-1 done, buffer q&1 complete
@@ -488,7 +498,9 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
                 // `zero` is reloaded from LDS every pass, so the addresses
                 // derived from `pl` cannot be hoisted out of the sweep loop
                 // and held per unit in registers.
-                const uint32_t pl = place[i] + zero;
+                uint32_t pl;
+                if constexpr (PLDS) pl = place_lds[i * nt + t];
+                else pl = place[i] + zero;
                 const bool top = bslot && ((pl >> 27) & 1), bot = bslot && ((pl >> 28) & 1);
                 const uint64_t nw = update_unit<Unit, E>(lds, pl, P, top ? up_add : 0u, bot ? dn_add : 0u, c, u[i], A, esum);
                 const uint32_t off = pl & kOffMask;
@@ -536,10 +548,13 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
         ++q;
     };
 
+    // Colour 1 always accumulates the energy terms (they are only reduced
+    // when a trace is asked for): a single colour-1 body keeps the register
+    // assignment of the unit states the same on every path through the loop,
+    // which a traced/untraced branch here would not.
     for (uint64_t sweep = 0; sweep < a.n_sweeps; ++sweep) {
         pass(std::false_type{}, 0, sweep);
-        if (a.trace) pass(std::true_type{}, 1, sweep);
-        else pass(std::false_type{}, 1, sweep);
+        pass(std::true_type{}, 1, sweep);
     }
     __syncthreads();
     if (a.n_sweeps > 0) flush_energy(a.n_sweeps - 1);
@@ -570,7 +585,7 @@ __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
         if (threadIdx.x == 0) __hip_atomic_fetch_or(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    strip_body<Unit, SPT, EARLY>(a, r, lds);
+    strip_body<Unit, SPT, EARLY, place_in_lds<Unit, SPT>()>(a, r, lds);
 }
 
 // ---------------------------------------------------------------- per pass
@@ -677,8 +692,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc
             const StripArgs a{d.spins, d.st, d.S, d.L, d.L, 1, static_cast<uint32_t>(static_cast<uint64_t>(d.L) * d.L / NB),
                               d.T4, d.T8, d.n_sweeps, d.trace, nullptr, 0, nullptr};
             constexpr int spt = batch_spt<Unit>();
-            if (early_slots<spt>(d.L / NB, a.units, blockDim.x)) strip_body<Unit, spt, true>(a, 0, lds);
-            else strip_body<Unit, spt, false>(a, 0, lds);
+            if (early_slots<spt>(d.L / NB, a.units, blockDim.x)) strip_body<Unit, spt, true, false>(a, 0, lds);
+            else strip_body<Unit, spt, false, false>(a, 0, lds);
         } else {
             replica_in_memory<Unit>(d, red_s);
         }
@@ -711,6 +726,18 @@ const void *strip_kernel_for(int spt, bool early) {
     case 16: return early ? strip_kernel<Unit, 16, true>() : strip_kernel<Unit, 16, false>();
     }
     return nullptr;
+}
+
+template <class Unit>
+bool place_lds_for(int spt) {
+    switch (spt) {
+    case 1: return place_in_lds<Unit, 1>();
+    case 2: return place_in_lds<Unit, 2>();
+    case 4: return place_in_lds<Unit, 4>();
+    case 8: return place_in_lds<Unit, 8>();
+    case 16: return place_in_lds<Unit, 16>();
+    }
+    return false;
 }
 
 // Host twin of early_slots for a run-time SPT.
@@ -775,7 +802,7 @@ bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out)
     if (nwg == 0 || L % nwg) return false;
     const uint32_t R = L / nwg;
     if (R < 2) return false;  // a strip's top and bottom rows are distinct
-    const uint64_t lds = strip_lds_bytes(L, R);
+    uint64_t lds = strip_lds_bytes(L, R);
     if (lds > kLdsMax) return false;
     const uint64_t sites = static_cast<uint64_t>(R) * L;
     if (NB == 8 && sites % 128) return false;  // whole XS1024W instances per strip
@@ -786,6 +813,8 @@ bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out)
     uint32_t threads = (units + spt - 1) / spt;
     threads = (threads + 63) / 64 * 64;
     const bool early = plan_early(spt, L / NB, units, threads);
+    if (place_lds_for<Unit>(spt)) lds += 4ull * spt * threads;
+    if (lds > kLdsMax) return false;
     const void *fn = strip_kernel_for<Unit>(spt, early);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     (void)hipGetLastError();
