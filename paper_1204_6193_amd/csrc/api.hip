@@ -106,6 +106,16 @@ rngx_status alloc_gen(rngx_kind kind, uint64_t S, Gen **out) {
         (void)hipGetLastError();
         return fail(RNGX_E_NOMEM, std::string("hipMalloc of generator state failed: ") + hipGetErrorString(e));
     }
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess) n_cu = 0;
+    e = fill_setup(g, n_cu);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(g->d_state);
+        (void)hipFree(g->d_ring);
+        delete g;
+        return fail(RNGX_E_NOMEM, std::string("fill set-up failed: ") + hipGetErrorString(e));
+    }
     *out = g;
     return RNGX_OK;
 }
@@ -113,6 +123,7 @@ rngx_status alloc_gen(rngx_kind kind, uint64_t S, Gen **out) {
 void free_gen(Gen *g) {
     if (!g) return;
     (void)hipFree(g->d_state);
+    (void)hipFree(g->d_ring);
     g->magic = 0;
     delete g;
 }

@@ -6,6 +6,8 @@
 // span per step.  Small-state kinds run V consecutive streams per thread
 // (V = 4: one 16-byte store per step); XS1024W runs one instance per
 // 16-lane DPP row with two words per lane (one 8-byte store per step).
+#include <algorithm>
+
 #include "rngx_internal.h"
 
 namespace rngx {
@@ -14,7 +16,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kXsBlock = 1024;   // XS1024W fill block, see k_fill_xs
-constexpr uint64_t kXsSync = 16;  // rows between its barriers (a power of two)
+constexpr uint64_t kXsSync = 16;  // rows between its barriers when not paced (a power of two)
 
 // --------------------------------------------------------------------------
 // Seeding (definitions in rngx.h).
@@ -116,15 +118,24 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
 }
 
 // XS1024W: thread t runs lane j = t % 16 of instance g = t / 16.  The output
-// is written row by row across all streams; 1024-thread blocks that meet at a
-// barrier every kXsSync rows keep their 16 waves on the same few rows, which
-// narrows the span of HBM pages written at once (about 3% faster at 2^20
-// streams than free-running 256-thread blocks).  Rows past the last instance
-// stay in the loop with their loads and stores masked, since every wave of
-// the block has to reach each barrier; they are whole 16-lane rows, so no
-// active instance sees one of their words.
+// is written row by row across all streams.  How fast HBM takes these rows
+// depends on how many distinct rows the chip writes at once, i.e. on how far
+// the workgroups drift apart, so a paced launch (ring != null, whole grid
+// resident) keeps them together: rows go in bands of kBand, and before band b
+// a workgroup waits until every workgroup has finished band b - kSlack.
+// Completion is counted in a ring of kRing band entries of kPaceSlots
+// counters (workgroup w adds 1 to slot w % kPaceSlots), so that no counter is
+// hit by more than a few workgroups; an entry's target after its u-th use is
+// u times the workgroups of its slot.  Waits are bounded: a workgroup that
+// waited kPollLimit polls runs free for the rest of the launch.  Pacing only
+// decides when a row is written, never what is written.  Unpaced launches
+// meet at a block barrier every kXsSync rows instead.  Rows past the last
+// instance stay in the loop with their loads and stores masked, since every
+// wave of the block has to reach each barrier; they are whole 16-lane rows,
+// so no active instance sees one of their words.
 template <int MODE>
-__global__ __launch_bounds__(kXsBlock) void k_fill_xs(uint8_t *st, uint64_t S, uint64_t count, void *out) {
+__global__ __launch_bounds__(kXsBlock) void k_fill_xs(uint8_t *st, uint64_t S, uint64_t count, void *out,
+                                                      uint32_t *ring) {
     const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t G = S / 32, g = t >> 4;
     const bool live = g < G;
@@ -137,23 +148,71 @@ __global__ __launch_bounds__(kXsBlock) void k_fill_xs(uint8_t *st, uint64_t S, u
     const uint64_t n = live ? N[g] : 0;
     uint32_t y = y0 + static_cast<uint32_t>(n) * kWeylC;
     uint32_t acc0 = 0, acc1 = 0;
-    for (uint64_t k = 0; k < count; ++k) {
-        xs1024_step(a, b);
-        y += kWeylC;
-        const uint32_t m = weyl_mix(y);
-        const uint32_t u[2] = {a + m, b + m};
-        if constexpr (MODE == kOutXor) {
-            acc0 ^= u[0];
-            acc1 ^= u[1];
+    __shared__ uint32_t s_free;
+    bool paced = MODE != kOutXor && ring != nullptr;
+    const uint32_t nblk = gridDim.x;
+    for (uint64_t k0 = 0, band = 0; k0 < count; k0 += kBand, ++band) {
+        if (paced && band >= kSlack) {
+            if (threadIdx.x < 64) {
+                const uint64_t prev = band - kSlack;
+                const uint32_t *e = ring + (prev % kRing) * kPaceSlots;
+                const uint32_t use = static_cast<uint32_t>(prev / kRing) + 1;
+                uint32_t it = 0;
+                for (; it < kPollLimit; ++it) {
+                    bool ok = true;
+#pragma unroll
+                    for (uint32_t m = 0; m < kPaceSlots / 64; ++m) {
+                        const uint32_t j = m * 64 + threadIdx.x;
+                        const uint32_t want = (nblk / kPaceSlots + (j < nblk % kPaceSlots ? 1u : 0u)) * use;
+                        ok &= __hip_atomic_load(e + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
+                    }
+                    if (__all(ok)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (threadIdx.x == 0) s_free = it == kPollLimit;
+            }
+            __syncthreads();
+            if (s_free) paced = false;  // keep counting below, stop waiting
+        }
+        auto row = [&](uint64_t k) {
+            xs1024_step(a, b);
+            y += kWeylC;
+            const uint32_t m = weyl_mix(y);
+            const uint32_t u[2] = {a + m, b + m};
+            if constexpr (MODE == kOutXor) {
+                acc0 ^= u[0];
+                acc1 ^= u[1];
+            } else {
+                if (live) store_out<MODE, 2>(out, k * S + 2 * t, u);
+            }
+        };
+        const uint64_t k1 = k0 + kBand < count ? k0 + kBand : count;
+        if (k1 - k0 == kBand) {
+#pragma unroll
+            for (uint32_t kk = 0; kk < kBand; ++kk) row(k0 + kk);
         } else {
-            if (live) store_out<MODE, 2>(out, k * S + 2 * t, u);
-            if ((k & (kXsSync - 1)) == kXsSync - 1) __syncthreads();
+            for (uint64_t k = k0; k < k1; ++k) row(k);
+        }
+        if constexpr (MODE != kOutXor) {
+            if (ring) {  // counted even when running free, so nobody waits for it
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_fetch_add(ring + (band % kRing) * kPaceSlots + blockIdx.x % kPaceSlots, 1u,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if ((k1 & (kXsSync - 1)) == 0) {
+                __syncthreads();
+            }
         }
     }
     if (!live) return;
     W[t] = make_uint2(a, b);
     if ((t & 15) == 0) N[g] = n + count;
     if constexpr (MODE == kOutXor) reinterpret_cast<uint2 *>(out)[t] = make_uint2(acc0, acc1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_ring(uint32_t *ring) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < kRing * kPaceSlots) ring[i] = 0;
 }
 
 template <class G, int MODE>
@@ -182,7 +241,14 @@ hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
     case RNGX_XS1024W: {
         const uint64_t threads = g->S / 2;
         const unsigned blocks = static_cast<unsigned>((threads + kXsBlock - 1) / kXsBlock);
-        hipLaunchKernelGGL((k_fill_xs<MODE>), dim3(blocks), dim3(kXsBlock), 0, st, g->d_state, g->S, count, out);
+        // pace only large launches whose workgroups are all resident at once
+        const bool pace = MODE != kOutXor && g->d_ring && count >= 4 * kBand && blocks >= 128 &&
+                          blocks <= g->fill_resident;
+        if (pace)
+            hipLaunchKernelGGL(k_zero_ring, dim3((kRing * kPaceSlots + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                               g->d_ring);
+        hipLaunchKernelGGL((k_fill_xs<MODE>), dim3(blocks), dim3(kXsBlock), 0, st, g->d_state, g->S, count, out,
+                           pace ? g->d_ring : nullptr);
         return hipGetLastError();
     }
     }
@@ -201,6 +267,21 @@ hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st) {
         hipLaunchKernelGGL(k_seed_small, dim3(blocks), dim3(kBlock), 0, st, g->kind, g->d_state, g->S, seed);
     }
     return hipGetLastError();
+}
+
+hipError_t fill_setup(Gen *g, int n_cu) {
+    g->d_ring = nullptr;
+    g->fill_resident = 0;
+    if (g->kind != RNGX_XS1024W) return hipSuccess;
+    int occ_u = 0, occ_f = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ_u, reinterpret_cast<const void *>(&k_fill_xs<kOutU32>), kXsBlock, 0);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, reinterpret_cast<const void *>(&k_fill_xs<kOutF32>),
+                                                         kXsBlock, 0);
+    if (e != hipSuccess) return e;
+    g->fill_resident = static_cast<uint32_t>(std::min(occ_u, occ_f) * std::max(n_cu, 0));
+    return hipMalloc(&g->d_ring, 4ull * kRing * kPaceSlots);
 }
 
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st) {

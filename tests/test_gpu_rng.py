@@ -162,6 +162,36 @@ def _xor_fold(x):
     return x[0]
 
 
+def test_xs1024w_paced_fill_ragged_rows(rngx, orc):
+    """A fill large enough to be paced (2^18 streams: 128 workgroups of 2048
+    streams) with a row count that is not a multiple of the 8-row band, twice
+    in a row (the pacing counters are reused), then once as FP32: sampled
+    stream ranges equal the oracle and the whole output's XOR equals the
+    consume variant on a second handle."""
+    S, count = 1 << 18, 1003
+    print("case paced fill xs1024w", flush=True)
+    g = rngx.rng_create("xs1024w", S, 5)
+    g2 = rngx.rng_create("xs1024w", S, 5)
+    st = orc.seed("xs1024w", S, 5)
+    ranges = ((0, 256), (S // 2 - 128, S // 2 + 128), (S - 256, S))
+    acc = torch.empty(S, dtype=torch.int32, device="cuda")
+    for rep in range(3):
+        f32 = rep == 2
+        out = torch.empty(S * count, dtype=torch.float32 if f32 else torch.int32, device="cuda")
+        (rngx.rng_fill_f32 if f32 else rngx.rng_fill_u32)(g, out, count)
+        view = out.view(count, S)
+        for lo, hi in ranges:
+            want = orc.generate("xs1024w", S, st, count, lo=lo, hi=hi, mode=orc.OUT_F32 if f32 else orc.OUT_U32)
+            got = view[:, lo:hi].contiguous().cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (rep, lo, hi)
+        rngx.rng_consume(g2, acc, count)
+        if not f32:
+            assert torch.equal(acc, _xor_fold(view)), rep
+        del out, view
+    assert np.array_equal(rngx.rng_get_state(g), rngx.rng_get_state(g2))
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_full_size_sampled_parity(rngx, orc, kind):
     """2^20 streams x 4096 outputs (16 GiB) as the benchmark launches it:
