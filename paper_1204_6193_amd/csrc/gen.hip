@@ -17,6 +17,17 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kXsBlock = 1024;   // XS1024W fill block, see k_fill_xs
 constexpr uint64_t kXsSync = 16;  // rows between its barriers when not paced (a power of two)
+// Paced small-state fills: streams per thread and threads per workgroup
+// (measured at 2^20 streams x 4096: 512-thread workgroups suit the
+// one- and two-word states, XORWOW's six words prefer 1024).
+template <class G>
+struct PacedShape {
+    static constexpr int V = 4, BLK = 512;
+};
+template <>
+struct PacedShape<Xorwow> {
+    static constexpr int V = 4, BLK = 1024;
+};
 
 // --------------------------------------------------------------------------
 // Seeding (definitions in rngx.h).
@@ -117,6 +128,83 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
     }
 }
 
+// Pacing of a fill's workgroups in bands of kBand rows (see k_fill_xs).
+// before(b): wait (bounded) until every workgroup has finished band
+// b - kSlack; after(b): count this workgroup's band b.  A workgroup whose wait
+// times out stops waiting for the rest of the launch but keeps counting.
+// Every thread of the workgroup must call both (they contain barriers).
+struct Pacer {
+    uint32_t *ring;  // null: not paced
+    bool waiting;
+    __device__ void before(uint64_t band, uint32_t *s_free) {
+        if (!waiting || band < kSlack) return;
+        const uint32_t nblk = gridDim.x;
+        if (threadIdx.x < 64) {
+            const uint64_t prev = band - kSlack;
+            const uint32_t *e = ring + (prev % kRing) * kPaceSlots;
+            const uint32_t use = static_cast<uint32_t>(prev / kRing) + 1;
+            uint32_t it = 0;
+            for (; it < kPollLimit; ++it) {
+                bool ok = true;
+#pragma unroll
+                for (uint32_t m = 0; m < kPaceSlots / 64; ++m) {
+                    const uint32_t j = m * 64 + threadIdx.x;
+                    const uint32_t want = (nblk / kPaceSlots + (j < nblk % kPaceSlots ? 1u : 0u)) * use;
+                    ok &= __hip_atomic_load(e + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
+                }
+                if (__all(ok)) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (threadIdx.x == 0) *s_free = it == kPollLimit;
+        }
+        __syncthreads();
+        if (*s_free) waiting = false;
+    }
+    __device__ void after(uint64_t band) {
+        if (!ring) return;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(ring + (band % kRing) * kPaceSlots + blockIdx.x % kPaceSlots, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+// Small-state kinds, paced: V consecutive streams per thread, BLK threads
+// per workgroup (S % V == 0; threads past the last stream stay in the loop
+// with their stores masked, since they take part in the barriers).
+template <class G, int MODE, int V, int BLK>
+__global__ __launch_bounds__(BLK) void k_fill_paced(uint8_t *st, uint64_t S, uint64_t count, void *out,
+                                                    uint32_t *ring) {
+    const uint64_t s0 = (static_cast<uint64_t>(blockIdx.x) * BLK + threadIdx.x) * V;
+    const bool live = s0 < S;
+    G g[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        if (live) g[v].load(st, S, s0 + v);
+    __shared__ uint32_t s_free;
+    Pacer pc{ring, true};
+    for (uint64_t k0 = 0, band = 0; k0 < count; k0 += kBand, ++band) {
+        pc.before(band, &s_free);
+        auto row = [&](uint64_t k) {
+            uint32_t u[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) u[v] = g[v].next();
+            if (live) store_out<MODE, V>(out, k * S + s0, u);
+        };
+        const uint64_t k1 = k0 + kBand < count ? k0 + kBand : count;
+        if (k1 - k0 == kBand) {
+#pragma unroll
+            for (uint32_t kk = 0; kk < kBand; ++kk) row(k0 + kk);
+        } else {
+            for (uint64_t k = k0; k < k1; ++k) row(k);
+        }
+        pc.after(band);
+    }
+    if (!live) return;
+#pragma unroll
+    for (int v = 0; v < V; ++v) g[v].store(st, S, s0 + v);
+}
+
 // XS1024W: thread t runs lane j = t % 16 of instance g = t / 16.  The output
 // is written row by row across all streams.  How fast HBM takes these rows
 // depends on how many distinct rows the chip writes at once, i.e. on how far
@@ -126,9 +214,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
 // Completion is counted in a ring of kRing band entries of kPaceSlots
 // counters (workgroup w adds 1 to slot w % kPaceSlots), so that no counter is
 // hit by more than a few workgroups; an entry's target after its u-th use is
-// u times the workgroups of its slot.  Waits are bounded: a workgroup that
-// waited kPollLimit polls runs free for the rest of the launch.  Pacing only
-// decides when a row is written, never what is written.  Unpaced launches
+// u times the workgroups of its slot (Pacer).  Waits are bounded: a workgroup
+// that waited kPollLimit polls runs free for the rest of the launch.  Pacing
+// only decides when a row is written, never what is written.  Unpaced launches
 // meet at a block barrier every kXsSync rows instead.  Rows past the last
 // instance stay in the loop with their loads and stores masked, since every
 // wave of the block has to reach each barrier; they are whole 16-lane rows,
@@ -149,31 +237,10 @@ __global__ __launch_bounds__(kXsBlock) void k_fill_xs(uint8_t *st, uint64_t S, u
     uint32_t y = y0 + static_cast<uint32_t>(n) * kWeylC;
     uint32_t acc0 = 0, acc1 = 0;
     __shared__ uint32_t s_free;
-    bool paced = MODE != kOutXor && ring != nullptr;
-    const uint32_t nblk = gridDim.x;
+    Pacer pc{MODE != kOutXor ? ring : nullptr, true};
+    pc.waiting = pc.ring != nullptr;
     for (uint64_t k0 = 0, band = 0; k0 < count; k0 += kBand, ++band) {
-        if (paced && band >= kSlack) {
-            if (threadIdx.x < 64) {
-                const uint64_t prev = band - kSlack;
-                const uint32_t *e = ring + (prev % kRing) * kPaceSlots;
-                const uint32_t use = static_cast<uint32_t>(prev / kRing) + 1;
-                uint32_t it = 0;
-                for (; it < kPollLimit; ++it) {
-                    bool ok = true;
-#pragma unroll
-                    for (uint32_t m = 0; m < kPaceSlots / 64; ++m) {
-                        const uint32_t j = m * 64 + threadIdx.x;
-                        const uint32_t want = (nblk / kPaceSlots + (j < nblk % kPaceSlots ? 1u : 0u)) * use;
-                        ok &= __hip_atomic_load(e + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
-                    }
-                    if (__all(ok)) break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (threadIdx.x == 0) s_free = it == kPollLimit;
-            }
-            __syncthreads();
-            if (s_free) paced = false;  // keep counting below, stop waiting
-        }
+        if constexpr (MODE != kOutXor) pc.before(band, &s_free);
         auto row = [&](uint64_t k) {
             xs1024_step(a, b);
             y += kWeylC;
@@ -194,14 +261,8 @@ __global__ __launch_bounds__(kXsBlock) void k_fill_xs(uint8_t *st, uint64_t S, u
             for (uint64_t k = k0; k < k1; ++k) row(k);
         }
         if constexpr (MODE != kOutXor) {
-            if (ring) {  // counted even when running free, so nobody waits for it
-                __syncthreads();
-                if (threadIdx.x == 0)
-                    __hip_atomic_fetch_add(ring + (band % kRing) * kPaceSlots + blockIdx.x % kPaceSlots, 1u,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if ((k1 & (kXsSync - 1)) == 0) {
-                __syncthreads();
-            }
+            if (pc.ring) pc.after(band);
+            else if ((k1 & (kXsSync - 1)) == 0) __syncthreads();
         }
     }
     if (!live) return;
@@ -219,6 +280,17 @@ template <class G, int MODE>
 hipError_t fill_small(Gen *g, void *out, uint64_t count, hipStream_t st) {
     const uint64_t S = g->S;
     const bool vec4 = (S % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    if constexpr (MODE != kOutXor) {
+        constexpr int V = PacedShape<G>::V, BLK = PacedShape<G>::BLK;
+        const uint64_t pblocks = (S / V + BLK - 1) / BLK;
+        if (vec4 && g->d_ring && count >= 4 * kBand && pblocks >= 128 && pblocks <= g->fill_resident) {
+            hipLaunchKernelGGL(k_zero_ring, dim3((kRing * kPaceSlots + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                               g->d_ring);
+            hipLaunchKernelGGL((k_fill_paced<G, MODE, V, BLK>), dim3(static_cast<unsigned>(pblocks)), dim3(BLK), 0, st,
+                               g->d_state, S, count, out, g->d_ring);
+            return hipGetLastError();
+        }
+    }
     if (vec4) {
         const uint64_t threads = S / 4;
         const unsigned blocks = static_cast<unsigned>((threads + kBlock - 1) / kBlock);
@@ -269,18 +341,43 @@ hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <class G>
+hipError_t paced_occupancy(int *occ) {
+    constexpr int V = PacedShape<G>::V, BLK = PacedShape<G>::BLK;
+    int u = 0, f = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &u, reinterpret_cast<const void *>(&k_fill_paced<G, kOutU32, V, BLK>), BLK, 0);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &f, reinterpret_cast<const void *>(&k_fill_paced<G, kOutF32, V, BLK>), BLK, 0);
+    *occ = std::min(u, f);
+    return e;
+}
+
 hipError_t fill_setup(Gen *g, int n_cu) {
     g->d_ring = nullptr;
     g->fill_resident = 0;
-    if (g->kind != RNGX_XS1024W) return hipSuccess;
-    int occ_u = 0, occ_f = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ_u, reinterpret_cast<const void *>(&k_fill_xs<kOutU32>), kXsBlock, 0);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, reinterpret_cast<const void *>(&k_fill_xs<kOutF32>),
+    int occ = 0;
+    hipError_t e = hipSuccess;
+    switch (g->kind) {
+    case RNGX_LCG32: e = paced_occupancy<Lcg32>(&occ); break;
+    case RNGX_LCG64: e = paced_occupancy<Lcg64>(&occ); break;
+    case RNGX_MWC: e = paced_occupancy<Mwc>(&occ); break;
+    case RNGX_XORWOW: e = paced_occupancy<Xorwow>(&occ); break;
+    case RNGX_PHILOX4X32_10: e = paced_occupancy<Philox>(&occ); break;
+    case RNGX_XS1024W: {
+        int u = 0, f = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&u, reinterpret_cast<const void *>(&k_fill_xs<kOutU32>),
                                                          kXsBlock, 0);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void *>(&k_fill_xs<kOutF32>),
+                                                             kXsBlock, 0);
+        occ = std::min(u, f);
+        break;
+    }
+    }
     if (e != hipSuccess) return e;
-    g->fill_resident = static_cast<uint32_t>(std::min(occ_u, occ_f) * std::max(n_cu, 0));
+    g->fill_resident = static_cast<uint32_t>(occ * std::max(n_cu, 0));
     return hipMalloc(&g->d_ring, 4ull * kRing * kPaceSlots);
 }
 

@@ -39,11 +39,11 @@ struct Gen {
     size_t state_bytes;
     const void *owner;  // the lattice that owns this generator, if any
     uint32_t plans;     // ragged plans that hold this generator
-    uint32_t *d_ring;   // XS1024W fill pacing counters (kRing x kPaceSlots), or null
-    uint32_t fill_resident;  // XS1024W fill workgroups that fit on the device at once
+    uint32_t *d_ring;        // fill pacing counters (kRing x kPaceSlots)
+    uint32_t fill_resident;  // paced fill workgroups that fit on the device at once
 };
 
-// XS1024W fill pacing (see k_fill_xs).
+// Fill pacing (see k_fill_xs).
 constexpr uint32_t kBand = 8;         // rows per band
 constexpr uint32_t kSlack = 3;        // bands a workgroup may run ahead of the slowest
 constexpr uint32_t kRing = 32;        // band entries in the counter ring
@@ -131,7 +131,7 @@ void clear_error();
 
 // Launchers (stream-ordered, no host synchronisation).
 hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st);
-hipError_t fill_setup(Gen *g, int n_cu);  // pacing counters and residency of the XS1024W fill
+hipError_t fill_setup(Gen *g, int n_cu);  // pacing counters and residency of the paced fill
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st);
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
 
