@@ -267,7 +267,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--parts", default="all", help="all | none: per-kind parts and Ising")
     ap.add_argument("--ising-sweeps", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
@@ -277,6 +277,9 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3: the headline fill `steps` times, then a plain 4 GiB device-to-device "
                          "copy `steps` times as the reference for scaling HBM byte counters; prints no JSON")
+    ap.add_argument("--profile-ising", action="store_true",
+                    help="for rocprofv3: `steps` XS1024W Ising calls of 200 sweeps each at L=4096, beta=0.4 "
+                         "(energy trace on); prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -287,6 +290,14 @@ def main():
     import paper_1204_6193_amd as rx
     rx.load()
     torch.cuda.set_device(0)
+    if args.profile_ising:
+        lat = rx.ising_create(4096, "xs1024w", 1)
+        tr = torch.zeros(200, dtype=torch.int32, device="cuda")
+        for _ in range(args.steps):
+            rx.ising_sweep(lat, 0.4, 200, tr)
+        torch.cuda.synchronize()
+        print(f"profile pass done: {args.steps} calls of 200 sweeps at L=4096", flush=True)
+        return
     out = torch.empty(S_FULL * COUNT_FULL, dtype=torch.int32, device="cuda")
     if args.profile_pass:
         g = rx.rng_create("xs1024w", S_FULL, 1)
