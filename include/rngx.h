@@ -101,6 +101,16 @@ typedef struct {
     uint64_t seed;           /* master seed of every client generator and Ising job              */
 } rngx_server_config;
 
+/* A fill configuration (see rng_fill_configs): paced (1) or free-running (0)
+ * workgroups, streams per thread (XS1024W: 2, one lane pair of an instance),
+ * threads per workgroup.  All configurations of a kind produce the same
+ * values; they differ only in speed. */
+typedef struct rngx_fill_config {
+    int32_t paced;
+    int32_t streams_per_thread;
+    int32_t block;
+} rngx_fill_config;
+
 typedef struct {
     int32_t status;    /* RNGX_OK once done                                                       */
     void *d_output;    /* device memory owned by the server until srv_release (see srv_submit_*) */
@@ -147,6 +157,30 @@ rngx_status rng_consume(rngx_gen g, uint32_t *d_xor, uint64_t count_per_stream, 
  * term, Philox by its counter.  The result equals producing and discarding
  * n outputs. */
 rngx_status rng_skip(rngx_gen g, uint64_t n, void *stream);
+
+/* Fill configurations and their autotuner.  The block size, streams per
+ * thread and pacing of rng_fill_u32/_f32 are chosen per handle from a fixed
+ * list per kind (the defaults were measured at 2^20 streams x 4096; other
+ * sizes or devices may prefer others).  Pacing keeps the workgroups of a
+ * large fill within a few bands of rows of each other, which HBM rewards for
+ * the interleaved layout; it needs every workgroup resident and is skipped
+ * otherwise.  rng_consume and rng_fill_ragged_u32 do not use these.
+ *
+ * rng_fill_configs: the list for `kind` in index order; out (n entries) may
+ * be NULL to ask for *n only.
+ * rng_set_fill_config: use entry `index` for this handle (-1: the kind's
+ * default); rng_get_fill_config: the entry in use (the default resolved).
+ * rng_autotune_fill: times every entry on this handle's fills of `count`
+ * outputs per stream into d_out (S*count u32 elements, overwritten), one
+ * warm-up and `reps` (>= 1) timed launches each, selects the fastest and
+ * leaves the stream state as it was (it is saved to device memory that the
+ * call allocates and frees).  ms_out (may be NULL) receives the mean launch
+ * time of each entry in index order.  Synchronizes the stream. */
+rngx_status rng_fill_configs(rngx_kind kind, rngx_fill_config *out, int32_t *n);
+rngx_status rng_set_fill_config(rngx_gen g, int32_t index);
+rngx_status rng_get_fill_config(rngx_gen g, int32_t *index);
+rngx_status rng_autotune_fill(rngx_gen g, uint32_t *d_out, uint64_t count_per_stream, int32_t reps, float *ms_out,
+                              void *stream);
 
 /* Uneven per-stream requests (streams of very different length served in one
  * pass, the batched form of rng_fill_u32).  `offsets` (host memory, copied)

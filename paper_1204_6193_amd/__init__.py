@@ -33,6 +33,10 @@ SIGNATURES = {
     "rng_fill_f32": (_i32, [_vp, _vp, _u64, _vp]),
     "rng_consume": (_i32, [_vp, _vp, _u64, _vp]),
     "rng_skip": (_i32, [_vp, _u64, _vp]),
+    "rng_fill_configs": (_i32, [_i32, _vp, ctypes.POINTER(_i32)]),
+    "rng_set_fill_config": (_i32, [_vp, _i32]),
+    "rng_get_fill_config": (_i32, [_vp, ctypes.POINTER(_i32)]),
+    "rng_autotune_fill": (_i32, [_vp, _vp, _u64, _i32, _vp, _vp]),
     "rng_ragged_create": (_i32, [_vp, _vp, _u64, ctypes.POINTER(_vp)]),
     "rng_fill_ragged_u32": (_i32, [_vp, _vp, _vp]),
     "rng_ragged_destroy": (_i32, [_vp]),
@@ -177,6 +181,40 @@ def rng_consume(g: Gen, out_xor, count_per_stream: int, stream=None):
 
 def rng_skip(g: Gen, n: int, stream=None):
     _check(load().rng_skip(g.handle, n, _stream(stream)))
+
+
+class FillConfig(ctypes.Structure):
+    """rngx_fill_config: paced, streams per thread, threads per workgroup."""
+    _fields_ = [("paced", ctypes.c_int32), ("streams_per_thread", ctypes.c_int32), ("block", ctypes.c_int32)]
+
+
+def rng_fill_configs(kind) -> list[tuple[int, int, int]]:
+    """The fill configurations of `kind` in index order, as (paced, streams_per_thread, block)."""
+    n = ctypes.c_int()
+    _check(load().rng_fill_configs(_kind(kind), None, ctypes.byref(n)))
+    arr = (FillConfig * n.value)()
+    _check(load().rng_fill_configs(_kind(kind), ctypes.cast(arr, _vp), ctypes.byref(n)))
+    return [(c.paced, c.streams_per_thread, c.block) for c in arr]
+
+
+def rng_set_fill_config(g: Gen, index: int):
+    _check(load().rng_set_fill_config(g.handle, index))
+
+
+def rng_get_fill_config(g: Gen) -> int:
+    i = ctypes.c_int()
+    _check(load().rng_get_fill_config(g.handle, ctypes.byref(i)))
+    return i.value
+
+
+def rng_autotune_fill(g: Gen, out, count_per_stream: int, reps: int = 3, stream=None) -> list[float]:
+    """Time every fill configuration on `out` (S*count u32, overwritten), keep the fastest for `g`
+    and leave g's stream state unchanged; returns the mean launch time (ms) of each configuration."""
+    n = len(rng_fill_configs(g.kind))
+    ms = (ctypes.c_float * n)()
+    _check(load().rng_autotune_fill(g.handle, _dptr(out, g.n_streams * count_per_stream, 4), count_per_stream, reps,
+                                    ctypes.cast(ms, _vp), _stream(stream)))
+    return list(ms)
 
 
 class Ragged:

@@ -245,6 +245,95 @@ rngx_status rng_consume(rngx_gen g, uint32_t *d_xor, uint64_t count, void *strea
     return fill_common(g, d_xor, count, kOutXor, stream);
 }
 
+rngx_status rng_fill_configs(rngx_kind kind, rngx_fill_config *out, int32_t *n) {
+    if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind " + std::to_string(kind));
+    if (!n) return fail(RNGX_E_INVALID, "n is NULL");
+    const rngx_fill_config *list;
+    const int k = fill_configs(kind, &list);
+    if (out)
+        for (int i = 0; i < k; ++i) out[i] = list[i];
+    *n = k;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_set_fill_config(rngx_gen h, int32_t index) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    const rngx_fill_config *list;
+    const int k = fill_configs(g->kind, &list);
+    if (index < -1 || index >= k) return fail(RNGX_E_INVALID, "fill configuration index out of range");
+    g->fill_cfg = index;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_get_fill_config(rngx_gen h, int32_t *index) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (!index) return fail(RNGX_E_INVALID, "index is NULL");
+    *index = g->fill_cfg >= 0 ? g->fill_cfg : fill_default(g->kind);
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_autotune_fill(rngx_gen h, uint32_t *d_out, uint64_t count, int32_t reps, float *ms_out, void *stream) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (!d_out) return fail(RNGX_E_INVALID, "output pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(d_out) % 16) return fail(RNGX_E_ALIGN, "output pointer must be 16-byte aligned");
+    if (count == 0 || reps < 1) return fail(RNGX_E_INVALID, "count and reps must be positive");
+    uint64_t n, bytes;
+    if (mul_overflows(g->S, count, &n) || mul_overflows(n, 4, &bytes))
+        return fail(RNGX_E_OVERFLOW, "n_streams * count * 4 overflows 64 bits");
+    DeviceScope ds(g->device);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const rngx_fill_config *list;
+    const int k = fill_configs(g->kind, &list);
+    void *saved = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&saved, g->state_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RNGX_E_NOMEM, "device memory for the saved state");
+    }
+    e = hipMemcpyAsync(saved, g->d_state, g->state_bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best = -1;
+    float best_ms = 0;
+    for (int i = 0; i < k && e == hipSuccess; ++i) {
+        g->fill_cfg = i;
+        e = hipMemcpyAsync(g->d_state, saved, g->state_bytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = launch_fill(g, d_out, count, kOutU32, st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_fill(g, d_out, count, kOutU32, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        ms /= static_cast<float>(reps);
+        if (ms_out) ms_out[i] = ms;
+        if (e == hipSuccess && (best < 0 || ms < best_ms)) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    // the stream state as it was before the call
+    if (e == hipSuccess) e = hipMemcpyAsync(g->d_state, saved, g->state_bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    g->fill_cfg = best;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(saved);
+    if (e != hipSuccess) {
+        g->fill_cfg = -1;
+        return hip_fail(e, "fill autotuning");
+    }
+    clear_error();
+    return RNGX_OK;
+}
+
 rngx_status rng_skip(rngx_gen h, uint64_t n, void *stream) {
     Gen *g;
     if (rngx_status s = check_gen(h, &g)) return s;

@@ -15,20 +15,7 @@ namespace rngx {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kXsBlock = 1024;   // XS1024W fill block, see k_fill_xs
 constexpr uint64_t kXsSync = 16;  // rows between its barriers when not paced (a power of two)
-// Paced small-state fills: streams per thread and threads per workgroup
-// (measured at 2^20 streams x 4096: 512-thread workgroups suit the
-// one- and two-word states, XORWOW's six words prefer 1024).
-template <class G>
-struct PacedShape {
-    static constexpr int V = 4, BLK = 512;
-};
-template <>
-struct PacedShape<Xorwow> {
-    static constexpr int V = 4, BLK = 1024;
-};
-
 // --------------------------------------------------------------------------
 // Seeding (definitions in rngx.h).
 __global__ __launch_bounds__(kBlock) void k_seed_small(rngx_kind kind, uint8_t *st, uint64_t S, uint64_t seed) {
@@ -134,10 +121,11 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
 // times out stops waiting for the rest of the launch but keeps counting.
 // Every thread of the workgroup must call both (they contain barriers).
 struct Pacer {
-    uint32_t *ring;  // null: not paced
-    bool waiting;
+    uint32_t *ring;  // null: not paced (before() and after() do nothing)
+    bool waiting;    // false once a wait timed out, and always without a ring
+    __device__ explicit Pacer(uint32_t *r) : ring(r), waiting(r != nullptr) {}
     __device__ void before(uint64_t band, uint32_t *s_free) {
-        if (!waiting || band < kSlack) return;
+        if (!ring || !waiting || band < kSlack) return;
         const uint32_t nblk = gridDim.x;
         if (threadIdx.x < 64) {
             const uint64_t prev = band - kSlack;
@@ -182,7 +170,7 @@ __global__ __launch_bounds__(BLK) void k_fill_paced(uint8_t *st, uint64_t S, uin
     for (int v = 0; v < V; ++v)
         if (live) g[v].load(st, S, s0 + v);
     __shared__ uint32_t s_free;
-    Pacer pc{ring, true};
+    Pacer pc(ring);
     for (uint64_t k0 = 0, band = 0; k0 < count; k0 += kBand, ++band) {
         pc.before(band, &s_free);
         auto row = [&](uint64_t k) {
@@ -221,9 +209,9 @@ __global__ __launch_bounds__(BLK) void k_fill_paced(uint8_t *st, uint64_t S, uin
 // instance stay in the loop with their loads and stores masked, since every
 // wave of the block has to reach each barrier; they are whole 16-lane rows,
 // so no active instance sees one of their words.
-template <int MODE>
-__global__ __launch_bounds__(kXsBlock) void k_fill_xs(uint8_t *st, uint64_t S, uint64_t count, void *out,
-                                                      uint32_t *ring) {
+template <int MODE, int BLK>
+__global__ __launch_bounds__(BLK) void k_fill_xs(uint8_t *st, uint64_t S, uint64_t count, void *out,
+                                                 uint32_t *ring) {
     const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t G = S / 32, g = t >> 4;
     const bool live = g < G;
@@ -237,8 +225,7 @@ __global__ __launch_bounds__(kXsBlock) void k_fill_xs(uint8_t *st, uint64_t S, u
     uint32_t y = y0 + static_cast<uint32_t>(n) * kWeylC;
     uint32_t acc0 = 0, acc1 = 0;
     __shared__ uint32_t s_free;
-    Pacer pc{MODE != kOutXor ? ring : nullptr, true};
-    pc.waiting = pc.ring != nullptr;
+    Pacer pc(MODE != kOutXor ? ring : nullptr);
     for (uint64_t k0 = 0, band = 0; k0 < count; k0 += kBand, ++band) {
         if constexpr (MODE != kOutXor) pc.before(band, &s_free);
         auto row = [&](uint64_t k) {
@@ -276,19 +263,99 @@ __global__ __launch_bounds__(kBlock) void k_zero_ring(uint32_t *ring) {
     if (i < kRing * kPaceSlots) ring[i] = 0;
 }
 
+// ---------------------------------------------------------------- configurations
+// The fill configurations the autotuner chooses from; every one of them
+// produces the same values.  Small-state kinds: paced or not, streams per
+// thread, threads per workgroup (the unpaced one is k_fill_small).
+// XS1024W: always one lane pair per thread; paced or not, threads per
+// workgroup.  The first entry of each list is the default (XORWOW: the
+// second), as measured at 2^20 streams x 4096.
+constexpr rngx_fill_config kSmallConfigs[] = {{1, 4, 512}, {1, 4, 1024}, {1, 4, 256}, {1, 2, 1024},
+                                              {1, 2, 512}, {1, 2, 256},  {0, 4, 256}};
+constexpr rngx_fill_config kXsConfigs[] = {{1, 2, 1024}, {1, 2, 512}, {0, 2, 1024}, {0, 2, 256}};
+constexpr int kNumSmall = sizeof(kSmallConfigs) / sizeof(kSmallConfigs[0]);
+constexpr int kNumXs = sizeof(kXsConfigs) / sizeof(kXsConfigs[0]);
+static_assert(kNumSmall <= kMaxFillConfigs && kNumXs <= kMaxFillConfigs, "Gen::resident too small");
+
+int default_config(rngx_kind kind) { return kind == RNGX_XORWOW ? 1 : 0; }
+
+// Kernel of a configuration (U32 or F32), for launches and occupancy.
+template <class G, int MODE>
+const void *paced_kernel(int v, int blk) {
+    if (v == 4 && blk == 256) return reinterpret_cast<const void *>(&k_fill_paced<G, MODE, 4, 256>);
+    if (v == 4 && blk == 512) return reinterpret_cast<const void *>(&k_fill_paced<G, MODE, 4, 512>);
+    if (v == 4 && blk == 1024) return reinterpret_cast<const void *>(&k_fill_paced<G, MODE, 4, 1024>);
+    if (v == 2 && blk == 256) return reinterpret_cast<const void *>(&k_fill_paced<G, MODE, 2, 256>);
+    if (v == 2 && blk == 512) return reinterpret_cast<const void *>(&k_fill_paced<G, MODE, 2, 512>);
+    if (v == 2 && blk == 1024) return reinterpret_cast<const void *>(&k_fill_paced<G, MODE, 2, 1024>);
+    return nullptr;
+}
+template <int MODE>
+const void *xs_kernel(int blk) {
+    if (blk == 256) return reinterpret_cast<const void *>(&k_fill_xs<MODE, 256>);
+    if (blk == 512) return reinterpret_cast<const void *>(&k_fill_xs<MODE, 512>);
+    if (blk == 1024) return reinterpret_cast<const void *>(&k_fill_xs<MODE, 1024>);
+    return nullptr;
+}
+template <class G>
+const void *config_kernel(int mode, const rngx_fill_config &c) {
+    return mode == kOutU32 ? paced_kernel<G, kOutU32>(c.streams_per_thread, c.block)
+                           : paced_kernel<G, kOutF32>(c.streams_per_thread, c.block);
+}
+const void *config_kernel(rngx_kind kind, int mode, const rngx_fill_config &c) {
+    switch (kind) {
+    case RNGX_LCG32: return config_kernel<Lcg32>(mode, c);
+    case RNGX_LCG64: return config_kernel<Lcg64>(mode, c);
+    case RNGX_MWC: return config_kernel<Mwc>(mode, c);
+    case RNGX_XORWOW: return config_kernel<Xorwow>(mode, c);
+    case RNGX_PHILOX4X32_10: return config_kernel<Philox>(mode, c);
+    case RNGX_XS1024W: return mode == kOutU32 ? xs_kernel<kOutU32>(c.block) : xs_kernel<kOutF32>(c.block);
+    }
+    return nullptr;
+}
+
+// Workgroups of configuration i that fit on the device at once (cached).
+uint32_t resident(Gen *g, int i, const rngx_fill_config &c) {
+    if (g->resident[i] >= 0) return static_cast<uint32_t>(g->resident[i]);
+    int u = 0, f = 0;
+    const void *ku = config_kernel(g->kind, kOutU32, c), *kf = config_kernel(g->kind, kOutF32, c);
+    if (!ku || !kf || hipOccupancyMaxActiveBlocksPerMultiprocessor(&u, ku, c.block, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, kf, c.block, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        u = f = 0;
+    }
+    g->resident[i] = std::min(u, f) * std::max(g->n_cu, 0);
+    return static_cast<uint32_t>(g->resident[i]);
+}
+
+// Pace a launch of `blocks` workgroups of configuration i: large enough and
+// every workgroup resident at once.
+bool pace_ok(Gen *g, int i, const rngx_fill_config &c, uint64_t blocks, uint64_t count) {
+    return g->d_ring && count >= 4 * kBand && blocks >= 128 && blocks <= resident(g, i, c);
+}
+
+void clear_ring(Gen *g, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_ring, dim3((kRing * kPaceSlots + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g->d_ring);
+}
+
 template <class G, int MODE>
 hipError_t fill_small(Gen *g, void *out, uint64_t count, hipStream_t st) {
     const uint64_t S = g->S;
-    const bool vec4 = (S % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(out);
+    const bool vec4 = (S % 4 == 0) && (addr % 16 == 0);
     if constexpr (MODE != kOutXor) {
-        constexpr int V = PacedShape<G>::V, BLK = PacedShape<G>::BLK;
-        const uint64_t pblocks = (S / V + BLK - 1) / BLK;
-        if (vec4 && g->d_ring && count >= 4 * kBand && pblocks >= 128 && pblocks <= g->fill_resident) {
-            hipLaunchKernelGGL(k_zero_ring, dim3((kRing * kPaceSlots + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                               g->d_ring);
-            hipLaunchKernelGGL((k_fill_paced<G, MODE, V, BLK>), dim3(static_cast<unsigned>(pblocks)), dim3(BLK), 0, st,
-                               g->d_state, S, count, out, g->d_ring);
-            return hipGetLastError();
+        const int i = g->fill_cfg >= 0 ? g->fill_cfg : default_config(g->kind);
+        const rngx_fill_config c = kSmallConfigs[i];
+        const int V = c.streams_per_thread;
+        if (c.paced && S % V == 0 && addr % (4 * V) == 0) {
+            const uint64_t blocks = (S / V + c.block - 1) / c.block;
+            const bool pace = pace_ok(g, i, c, blocks, count);
+            if (pace) clear_ring(g, st);
+            uint32_t *ring = pace ? g->d_ring : nullptr;
+            void *args[] = {&g->d_state, const_cast<uint64_t *>(&S), &count, &out, &ring};
+            const hipError_t e = hipLaunchKernel(config_kernel<G>(MODE, c), dim3(static_cast<unsigned>(blocks)),
+                                                 dim3(c.block), args, 0, st);
+            return e != hipSuccess ? e : hipGetLastError();
         }
     }
     if (vec4) {
@@ -303,6 +370,20 @@ hipError_t fill_small(Gen *g, void *out, uint64_t count, hipStream_t st) {
 }
 
 template <int MODE>
+hipError_t fill_xs(Gen *g, void *out, uint64_t count, hipStream_t st) {
+    const int i = MODE == kOutXor ? 2 : (g->fill_cfg >= 0 ? g->fill_cfg : default_config(g->kind));
+    const rngx_fill_config c = kXsConfigs[i];
+    const uint64_t blocks = (g->S / 2 + c.block - 1) / c.block;
+    const bool pace = MODE != kOutXor && c.paced && pace_ok(g, i, c, blocks, count);
+    if (pace) clear_ring(g, st);
+    uint32_t *ring = pace ? g->d_ring : nullptr;
+    const void *fn = MODE == kOutXor ? reinterpret_cast<const void *>(&k_fill_xs<kOutXor, 1024>) : xs_kernel<MODE>(c.block);
+    void *args[] = {&g->d_state, &g->S, &count, &out, &ring};
+    const hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(blocks)), dim3(c.block), args, 0, st);
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+template <int MODE>
 hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
     switch (g->kind) {
     case RNGX_LCG32: return fill_small<Lcg32, MODE>(g, out, count, st);
@@ -310,19 +391,7 @@ hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
     case RNGX_MWC: return fill_small<Mwc, MODE>(g, out, count, st);
     case RNGX_XORWOW: return fill_small<Xorwow, MODE>(g, out, count, st);
     case RNGX_PHILOX4X32_10: return fill_small<Philox, MODE>(g, out, count, st);
-    case RNGX_XS1024W: {
-        const uint64_t threads = g->S / 2;
-        const unsigned blocks = static_cast<unsigned>((threads + kXsBlock - 1) / kXsBlock);
-        // pace only large launches whose workgroups are all resident at once
-        const bool pace = MODE != kOutXor && g->d_ring && count >= 4 * kBand && blocks >= 128 &&
-                          blocks <= g->fill_resident;
-        if (pace)
-            hipLaunchKernelGGL(k_zero_ring, dim3((kRing * kPaceSlots + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                               g->d_ring);
-        hipLaunchKernelGGL((k_fill_xs<MODE>), dim3(blocks), dim3(kXsBlock), 0, st, g->d_state, g->S, count, out,
-                           pace ? g->d_ring : nullptr);
-        return hipGetLastError();
-    }
+    case RNGX_XS1024W: return fill_xs<MODE>(g, out, count, st);
     }
     return hipErrorInvalidValue;
 }
@@ -341,45 +410,20 @@ hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <class G>
-hipError_t paced_occupancy(int *occ) {
-    constexpr int V = PacedShape<G>::V, BLK = PacedShape<G>::BLK;
-    int u = 0, f = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &u, reinterpret_cast<const void *>(&k_fill_paced<G, kOutU32, V, BLK>), BLK, 0);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &f, reinterpret_cast<const void *>(&k_fill_paced<G, kOutF32, V, BLK>), BLK, 0);
-    *occ = std::min(u, f);
-    return e;
-}
-
 hipError_t fill_setup(Gen *g, int n_cu) {
     g->d_ring = nullptr;
-    g->fill_resident = 0;
-    int occ = 0;
-    hipError_t e = hipSuccess;
-    switch (g->kind) {
-    case RNGX_LCG32: e = paced_occupancy<Lcg32>(&occ); break;
-    case RNGX_LCG64: e = paced_occupancy<Lcg64>(&occ); break;
-    case RNGX_MWC: e = paced_occupancy<Mwc>(&occ); break;
-    case RNGX_XORWOW: e = paced_occupancy<Xorwow>(&occ); break;
-    case RNGX_PHILOX4X32_10: e = paced_occupancy<Philox>(&occ); break;
-    case RNGX_XS1024W: {
-        int u = 0, f = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&u, reinterpret_cast<const void *>(&k_fill_xs<kOutU32>),
-                                                         kXsBlock, 0);
-        if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, reinterpret_cast<const void *>(&k_fill_xs<kOutF32>),
-                                                             kXsBlock, 0);
-        occ = std::min(u, f);
-        break;
-    }
-    }
-    if (e != hipSuccess) return e;
-    g->fill_resident = static_cast<uint32_t>(occ * std::max(n_cu, 0));
+    g->n_cu = n_cu;
+    g->fill_cfg = -1;
+    for (int i = 0; i < kMaxFillConfigs; ++i) g->resident[i] = -1;
     return hipMalloc(&g->d_ring, 4ull * kRing * kPaceSlots);
 }
+
+int fill_configs(rngx_kind kind, const rngx_fill_config **list) {
+    *list = kind == RNGX_XS1024W ? kXsConfigs : kSmallConfigs;
+    return kind == RNGX_XS1024W ? kNumXs : kNumSmall;
+}
+
+int fill_default(rngx_kind kind) { return default_config(kind); }
 
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st) {
     if (mode == kOutU32) return fill_mode<kOutU32>(g, d_out, count, st);

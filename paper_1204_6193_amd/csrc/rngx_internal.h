@@ -39,9 +39,12 @@ struct Gen {
     size_t state_bytes;
     const void *owner;  // the lattice that owns this generator, if any
     uint32_t plans;     // ragged plans that hold this generator
-    uint32_t *d_ring;        // fill pacing counters (kRing x kPaceSlots)
-    uint32_t fill_resident;  // paced fill workgroups that fit on the device at once
+    uint32_t *d_ring;   // fill pacing counters (kRing x kPaceSlots)
+    int n_cu;           // compute units of the device
+    int fill_cfg;       // fill configuration (index into the kind's list), -1: default
+    int resident[8];    // per configuration: workgroups that fit at once, -1: not known yet
 };
+constexpr int kMaxFillConfigs = 8;
 
 // Fill pacing (see k_fill_xs).
 constexpr uint32_t kBand = 8;         // rows per band
@@ -131,7 +134,9 @@ void clear_error();
 
 // Launchers (stream-ordered, no host synchronisation).
 hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st);
-hipError_t fill_setup(Gen *g, int n_cu);  // pacing counters and residency of the paced fill
+hipError_t fill_setup(Gen *g, int n_cu);  // pacing counters, default configuration
+int fill_configs(rngx_kind kind, const rngx_fill_config **list);  // autotuner candidates of a kind
+int fill_default(rngx_kind kind);
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st);
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
 

@@ -72,6 +72,27 @@ def test_unknown_handles_are_rejected(rngx):
     assert "unknown" in _err(lib)
 
 
+def test_fill_configuration_lists(rngx):
+    """The autotuner's candidates: every small-state kind has the same list
+    (its first entry the default, XORWOW's the second); XS1024W threads
+    always hold one lane pair."""
+    lib = rngx.load()
+    small = rngx.rng_fill_configs("lcg32")
+    assert len(small) == 7 and small[0] == (1, 4, 512) and (0, 4, 256) in small
+    for kind in ("lcg64", "mwc", "xorwow", "philox4x32_10"):
+        assert rngx.rng_fill_configs(kind) == small
+    xs = rngx.rng_fill_configs("xs1024w")
+    assert len(xs) == 4 and all(v == 2 for _, v, _ in xs) and xs[0] == (1, 2, 1024)
+    for paced, v, block in small + xs:
+        assert paced in (0, 1) and v in (2, 4) and block in (256, 512, 1024)
+    n = ctypes.c_int()
+    assert lib.rng_fill_configs(9, None, ctypes.byref(n)) == -1
+    assert lib.rng_fill_configs(1, None, None) == -1
+    bogus = ctypes.c_void_p(0x1234560)
+    assert lib.rng_set_fill_config(bogus, 0) == -1
+    assert lib.rng_autotune_fill(bogus, ctypes.c_void_p(0x1000), 4, 1, None, None) == -1
+
+
 def test_last_error_is_per_thread(rngx):
     import threading
     lib = rngx.load()

@@ -192,6 +192,64 @@ def test_xs1024w_paced_fill_ragged_rows(rngx, orc):
     torch.cuda.empty_cache()
 
 
+def _sampled_fill_check(rngx, orc, kind, S, count, seed, index):
+    """Fill of a fresh handle with configuration `index`: sampled stream
+    ranges equal the oracle, the whole output's XOR equals rng_consume on a
+    twin handle, and both end in the same state."""
+    g = rngx.rng_create(kind, S, seed)
+    twin = rngx.rng_create(kind, S, seed)
+    if index is not None:
+        rngx.rng_set_fill_config(g, index)
+        assert rngx.rng_get_fill_config(g) == index
+    st = orc.seed(kind, S, seed)
+    out = torch.empty(S * count, dtype=torch.int32, device="cuda")
+    rngx.rng_fill_u32(g, out, count)
+    view = out.view(count, S)
+    for lo, hi in ((0, 256), (S // 2 - 128, S // 2 + 128), (S - 256, S)):
+        want = orc.generate(kind, S, st, count, lo=lo, hi=hi)
+        assert np.array_equal(view[:, lo:hi].contiguous().cpu().numpy().view(np.uint32), want), (kind, index, lo)
+    acc = torch.empty(S, dtype=torch.int32, device="cuda")
+    rngx.rng_consume(twin, acc, count)
+    assert torch.equal(acc, _xor_fold(view)), (kind, index)
+    assert np.array_equal(rngx.rng_get_state(g), rngx.rng_get_state(twin)), (kind, index)
+    return g
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_every_fill_configuration(rngx, orc, kind):
+    """Each autotuner candidate at 2^19 streams x 37 (large enough that the
+    paced candidates run paced) gives the same numbers."""
+    S, count = 1 << 19, 37
+    for index in range(len(rngx.rng_fill_configs(kind))):
+        print(f"case fill config {kind} #{index}", flush=True)
+        _sampled_fill_check(rngx, orc, kind, S, count, 3, index)
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "xorwow"])
+def test_autotune_fill(rngx, orc, kind):
+    """The autotuner times every candidate, keeps the fastest and leaves the
+    stream state as it was; fills after it stay exact."""
+    S, count = 1 << 19, 64
+    print(f"case autotune {kind}", flush=True)
+    g = rngx.rng_create(kind, S, 9)
+    before = rngx.rng_get_state(g)
+    out = torch.empty(S * count, dtype=torch.int32, device="cuda")
+    ms = rngx.rng_autotune_fill(g, out, count, reps=2)
+    assert len(ms) == len(rngx.rng_fill_configs(kind)) and all(m > 0 for m in ms)
+    assert rngx.rng_get_fill_config(g) == int(np.argmin(ms))
+    assert np.array_equal(rngx.rng_get_state(g), before)
+    st = orc.seed(kind, S, 9)
+    rngx.rng_fill_u32(g, out, count)
+    view = out.view(count, S)
+    want = orc.generate(kind, S, st, count, lo=S - 256, hi=S)
+    assert np.array_equal(view[:, S - 256:].contiguous().cpu().numpy().view(np.uint32), want)
+    with pytest.raises(rngx.RngxError):
+        rngx.rng_set_fill_config(g, 99)
+    del out, view
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_full_size_sampled_parity(rngx, orc, kind):
     """2^20 streams x 4096 outputs (16 GiB) as the benchmark launches it:
