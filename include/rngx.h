@@ -182,6 +182,22 @@ rngx_status rng_get_fill_config(rngx_gen g, int32_t *index);
 rngx_status rng_autotune_fill(rngx_gen g, uint32_t *d_out, uint64_t count_per_stream, int32_t reps, float *ms_out,
                               void *stream);
 
+/* Ising plans and their autotuner.  A lattice runs either as strips held on
+ * chip by cooperating workgroups (one per strip; the strip count is the
+ * sub-lattice tiling) or, if no strip plan fits, one launch per colour pass.
+ * Every plan gives the same spins, energies and stream states.
+ * ising_plans: the strip counts that fit this lattice, most strips first,
+ * then 0 (the per-pass path); strips_out (n entries) may be NULL to ask for
+ * *n only.  ising_set_plan: use `strips` strips (0: per pass); synchronizes
+ * the device.  ising_autotune: times every plan on `reps` (>= 1) calls of
+ * n_sweeps sweeps at beta after one warm-up call, keeps the fastest and
+ * restores the spins and stream states it started from (saved to device
+ * memory the call allocates and frees); ms_out (may be NULL) receives the
+ * mean call time of each plan in ising_plans order.  Synchronizes the device. */
+rngx_status ising_plans(rngx_ising lat, uint32_t *strips_out, int32_t *n);
+rngx_status ising_set_plan(rngx_ising lat, uint32_t strips);
+rngx_status ising_autotune(rngx_ising lat, double beta, uint64_t n_sweeps, int32_t reps, float *ms_out, void *stream);
+
 /* Uneven per-stream requests (streams of very different length served in one
  * pass, the batched form of rng_fill_u32).  `offsets` (host memory, copied)
  * holds n_units + 1 non-decreasing element indices, n_units = S, or S/32

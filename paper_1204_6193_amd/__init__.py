@@ -37,6 +37,9 @@ SIGNATURES = {
     "rng_set_fill_config": (_i32, [_vp, _i32]),
     "rng_get_fill_config": (_i32, [_vp, ctypes.POINTER(_i32)]),
     "rng_autotune_fill": (_i32, [_vp, _vp, _u64, _i32, _vp, _vp]),
+    "ising_plans": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
+    "ising_set_plan": (_i32, [_vp, ctypes.c_uint32]),
+    "ising_autotune": (_i32, [_vp, ctypes.c_double, _u64, _i32, _vp, _vp]),
     "rng_ragged_create": (_i32, [_vp, _vp, _u64, ctypes.POINTER(_vp)]),
     "rng_fill_ragged_u32": (_i32, [_vp, _vp, _vp]),
     "rng_ragged_destroy": (_i32, [_vp]),
@@ -305,6 +308,27 @@ def ising_info(lat: Ising) -> dict:
     n = ctypes.c_uint32()
     _check(load().ising_info(lat.handle, ctypes.byref(L), ctypes.byref(k), ctypes.byref(n)))
     return {"L": L.value, "kind": KIND_NAMES[k.value], "strips": n.value}
+
+
+def ising_plans(lat: Ising) -> list[int]:
+    """Strip counts that fit this lattice, most strips first, then 0 (one launch per colour pass)."""
+    n = ctypes.c_int()
+    _check(load().ising_plans(lat.handle, None, ctypes.byref(n)))
+    arr = (ctypes.c_uint32 * n.value)()
+    _check(load().ising_plans(lat.handle, ctypes.cast(arr, _vp), ctypes.byref(n)))
+    return list(arr)
+
+
+def ising_set_plan(lat: Ising, strips: int):
+    _check(load().ising_set_plan(lat.handle, strips))
+
+
+def ising_autotune(lat: Ising, beta: float, n_sweeps: int, reps: int = 2, stream=None) -> list[float]:
+    """Time every plan (ising_plans order), keep the fastest, restore spins and streams; returns ms per call."""
+    n = len(ising_plans(lat))
+    ms = (ctypes.c_float * n)()
+    _check(load().ising_autotune(lat.handle, beta, n_sweeps, reps, ctypes.cast(ms, _vp), _stream(stream)))
+    return list(ms)
 
 
 def ising_spins(lat: Ising) -> int:

@@ -480,6 +480,7 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
     if (e == hipSuccess) e = hipMalloc(&lat->d_err, 4);
     if (e == hipSuccess && lat->plan.strips && lat->plan.nwg > 1) {
         e = hipMalloc(&lat->d_halo, static_cast<size_t>(8) * lat->plan.nwg * L);
+        lat->halo_nwg = lat->plan.nwg;
     }
     if (e == hipSuccess && !lat->plan.strips) e = hipMalloc(&lat->d_partial, 4 * ising_partials(L));
     if (e != hipSuccess) {
@@ -513,6 +514,134 @@ rngx_status ising_sweep(rngx_ising h, double beta, uint64_t n_sweeps, int32_t *d
     DeviceScope ds(lat->device);
     hipError_t e = launch_ising(lat, beta, n_sweeps, d_trace, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "Ising kernel launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+namespace {
+
+constexpr int kMaxPlans = 15;
+
+int plan_candidates(const Ising *lat, IsingPlan *list) {
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, lat->device) != hipSuccess) n_cu = 0;
+    return ising_plan_list(lat->L, lat->gen->kind, n_cu, list, kMaxPlans);
+}
+
+// Switch the lattice to plan p (strips, or the per-pass path when
+// !p.strips): waits for the device, sizes the buffers the plan needs and
+// clears the halo tags.
+hipError_t apply_plan(Ising *lat, const IsingPlan &p) {
+    hipError_t e = hipDeviceSynchronize();
+    const uint64_t L = lat->L;
+    if (e == hipSuccess && p.strips && p.nwg > 1 && p.nwg > lat->halo_nwg) {
+        (void)hipFree(lat->d_halo);
+        lat->d_halo = nullptr;
+        lat->halo_nwg = 0;
+        e = hipMalloc(&lat->d_halo, 8ull * p.nwg * L);
+        if (e == hipSuccess) lat->halo_nwg = p.nwg;
+    }
+    if (e == hipSuccess && !p.strips && !lat->d_partial) e = hipMalloc(&lat->d_partial, 4 * ising_partials(lat->L));
+    if (e == hipSuccess && lat->d_halo)
+        e = launch_zero(reinterpret_cast<uint32_t *>(lat->d_halo), 2ull * lat->halo_nwg * L, nullptr);
+    if (e == hipSuccess) e = launch_zero(lat->d_err, 1, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return e;
+    lat->plan = p;
+    lat->epoch = 0;
+    return hipSuccess;
+}
+
+}  // namespace
+
+rngx_status ising_plans(rngx_ising h, uint32_t *strips_out, int32_t *n) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (!n) return fail(RNGX_E_INVALID, "n is NULL");
+    DeviceScope ds(lat->device);
+    IsingPlan list[kMaxPlans];
+    const int k = plan_candidates(lat, list);
+    if (strips_out) {
+        for (int i = 0; i < k; ++i) strips_out[i] = list[i].nwg;
+        strips_out[k] = 0;
+    }
+    *n = k + 1;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_set_plan(rngx_ising h, uint32_t strips) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    DeviceScope ds(lat->device);
+    IsingPlan p{};
+    if (strips) {
+        IsingPlan list[kMaxPlans];
+        const int k = plan_candidates(lat, list);
+        int i = 0;
+        while (i < k && list[i].nwg != strips) ++i;
+        if (i == k) return fail(RNGX_E_INVALID, "no strip plan with that many strips fits this lattice");
+        p = list[i];
+    }
+    if (hipError_t e = apply_plan(lat, p)) return hip_fail(e, "switching the lattice's plan");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_autotune(rngx_ising h, double beta, uint64_t n_sweeps, int32_t reps, float *ms_out, void *stream) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (!std::isfinite(beta) || beta < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");
+    if (n_sweeps == 0 || reps < 1) return fail(RNGX_E_INVALID, "n_sweeps and reps must be positive");
+    DeviceScope ds(lat->device);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    IsingPlan list[kMaxPlans + 1];
+    const int k = plan_candidates(lat, list);
+    list[k] = IsingPlan{};  // the per-pass path
+    const size_t sbytes = static_cast<size_t>(lat->L) * lat->L, gbytes = lat->gen->state_bytes;
+    void *saved_spins = nullptr, *saved_state = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&saved_spins, sbytes);
+    if (e == hipSuccess) e = hipMalloc(&saved_state, gbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(saved_spins);
+        return fail(RNGX_E_NOMEM, "device memory for the saved lattice");
+    }
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(saved_spins, lat->d_spins, sbytes, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(saved_state, lat->gen->d_state, gbytes, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best = -1;
+    float best_ms = 0;
+    for (int i = 0; i <= k && e == hipSuccess; ++i) {
+        e = apply_plan(lat, list[i]);
+        if (e == hipSuccess) e = hipMemcpyAsync(lat->d_spins, saved_spins, sbytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(lat->gen->d_state, saved_state, gbytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = launch_ising(lat, beta, n_sweeps, nullptr, st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_ising(lat, beta, n_sweeps, nullptr, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        ms /= static_cast<float>(reps);
+        if (ms_out) ms_out[i] = ms;
+        if (e == hipSuccess && (best < 0 || ms < best_ms)) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    // the best plan, and the lattice and its streams as they were
+    if (e == hipSuccess) e = apply_plan(lat, list[best]);
+    if (e == hipSuccess) e = hipMemcpy(lat->d_spins, saved_spins, sbytes, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(lat->gen->d_state, saved_state, gbytes, hipMemcpyDeviceToDevice);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(saved_spins);
+    (void)hipFree(saved_state);
+    if (e != hipSuccess) return hip_fail(e, "Ising autotuning");
     clear_error();
     return RNGX_OK;
 }

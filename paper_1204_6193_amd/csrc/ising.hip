@@ -928,6 +928,35 @@ hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
     return hipGetLastError();
 }
 
+namespace {
+// Every strip count the planner accepts for side L, most strips first (at
+// most `max`): the autotuner's candidates besides the per-pass path.
+template <class Unit>
+int list_plans(uint32_t L, int max_spt, int n_cu, IsingPlan *out, int max) {
+    int n = 0;
+    const uint32_t top = std::min<uint32_t>(L, static_cast<uint32_t>(std::max(n_cu, 1)));
+    for (uint32_t nwg = top; nwg >= 1 && n < max; --nwg) {
+        if (L % nwg) continue;
+        if (nwg > 1 && static_cast<uint64_t>(L / nwg) * L < 2048) continue;
+        IsingPlan p;
+        if (try_strips<Unit>(L, nwg, max_spt, n_cu, &p)) out[n++] = p;
+    }
+    return n;
+}
+}  // namespace
+
+int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int max) {
+    switch (kind) {
+    case RNGX_LCG32: return list_plans<SmallUnit<Lcg32>>(L, 16, n_cu, out, max);
+    case RNGX_LCG64: return list_plans<SmallUnit<Lcg64>>(L, 16, n_cu, out, max);
+    case RNGX_MWC: return list_plans<SmallUnit<Mwc>>(L, 16, n_cu, out, max);
+    case RNGX_XORWOW: return list_plans<SmallUnit<Xorwow>>(L, 16, n_cu, out, max);
+    case RNGX_PHILOX4X32_10: return list_plans<PhiloxUnit>(L, 16, n_cu, out, max);
+    case RNGX_XS1024W: return list_plans<XsUnit>(L, 16, n_cu, out, max);
+    }
+    return 0;
+}
+
 bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
     switch (kind) {
     case RNGX_LCG32: return plan_strips<SmallUnit<Lcg32>>(L, 16, n_cu, out);

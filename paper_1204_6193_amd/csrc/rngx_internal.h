@@ -94,6 +94,7 @@ struct Ising {
     Gen *gen;
     IsingPlan plan;
     uint64_t *d_halo;    // strips: 2 slots x nwg x 2 rows x L/4 tagged words (4 spins | pass tag << 32)
+    uint32_t halo_nwg;   // strips the halo allocation is sized for
     uint32_t *d_err;     // strips: set if a neighbour wait gave up
     int32_t *d_partial;  // per-pass path: per-block energy partials
     uint64_t epoch;      // passes run since the halo tags were last cleared
@@ -151,6 +152,7 @@ hipError_t launch_hot_start(Ising *lat, uint64_t seed, hipStream_t st);
 hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st);
 hipError_t launch_zero(uint32_t *p, uint64_t n, hipStream_t st);
 bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out);
+int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int max);  // strip candidates
 hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas, const uint64_t *n_sweeps,
                          int32_t *const *traces, int n_cu);
 hipError_t launch_batch(IsingBatch *b, hipStream_t st);

@@ -17,8 +17,11 @@ KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w"]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _run_both(rx, orc, L, kind, beta, sweeps, seed=1, chunks=(None,)):
+def _run_both(rx, orc, L, kind, beta, sweeps, seed=1, chunks=(None,), plan=None):
     lat = rx.ising_create(L, kind, seed)
+    if plan is not None:
+        rx.ising_set_plan(lat, plan)
+        assert rx.ising_info(lat)["strips"] == plan
     sp, st = orc.ising_create(L, kind, seed)
     assert np.array_equal(rx.ising_get_spins(lat).ravel(), sp)
     for n in chunks:
@@ -112,6 +115,43 @@ def test_per_pass_path_parity(rngx, orc, kind):
     print(f"case ising per-pass {kind} L=8192", flush=True)
     lat = _run_both(rngx, orc, 8192, kind, 0.4, 1)
     assert rngx.ising_info(lat)["strips"] == 0
+
+
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "philox4x32_10"])
+@pytest.mark.parametrize("L", [512, 2048])
+def test_every_plan_gives_the_same_lattice(rngx, orc, kind, L):
+    """Each autotuner candidate (every strip count that fits, and the
+    per-pass path) gives the oracle's spins, energies and streams."""
+    plans = rngx.ising_plans(rngx.ising_create(L, kind, 1))
+    assert plans[-1] == 0 and len(plans) >= 2 and plans[:-1] == sorted(plans[:-1], reverse=True)
+    for strips in plans:
+        print(f"case ising plan {kind} L={L} strips={strips}", flush=True)
+        _run_both(rngx, orc, L, kind, 0.4, 3, chunks=(2, 1), plan=strips)
+
+
+def test_autotune_restores_the_lattice(rngx, orc):
+    L, kind = 1024, "xs1024w"
+    print("case ising autotune", flush=True)
+    lat = rngx.ising_create(L, kind, 4)
+    rngx.ising_sweep(lat, 0.4, 2)
+    spins = rngx.ising_get_spins(lat)
+    state = rngx.rng_get_state(rngx.ising_rng(lat))
+    ms = rngx.ising_autotune(lat, 0.4, 3, reps=1)
+    plans = rngx.ising_plans(lat)
+    assert len(ms) == len(plans) and all(m > 0 for m in ms)
+    assert rngx.ising_info(lat)["strips"] == plans[int(np.argmin(ms))]
+    assert np.array_equal(rngx.ising_get_spins(lat), spins)
+    assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lat)), state)
+    # and it still computes the oracle's lattice
+    sp, st = orc.ising_create(L, kind, 4)
+    orc.ising_sweeps(L, kind, 0.4, st, sp, 2)
+    tr = torch.zeros(3, dtype=torch.int32, device="cuda")
+    rngx.ising_sweep(lat, 0.4, 3, tr)
+    want = orc.ising_sweeps(L, kind, 0.4, st, sp, 3)
+    assert np.array_equal(tr.cpu().numpy(), want)
+    assert np.array_equal(rngx.ising_get_spins(lat).ravel(), sp.ravel())
+    with pytest.raises(rngx.RngxError):
+        rngx.ising_set_plan(lat, 7)
 
 
 def test_small_lattices_use_one_workgroup(rngx):
