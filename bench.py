@@ -59,9 +59,17 @@ def time_launches(fn, steps, warmup):
     return [a.elapsed_time(b) for a, b in evs], wall
 
 
-def bench_fill(rx, kind, mode, out, steps, warmup):
+def bench_fill(rx, kind, mode, out, steps, warmup, tune=True):
+    """Timed fills of one handle; with `tune` the fill autotuner first picks
+    the handle's configuration (untimed; it leaves the streams unchanged)."""
     import torch
     g = rx.rng_create(kind, S_FULL, 1)
+    tuned = None
+    if tune and mode != "consume":
+        tune_ms = rx.rng_autotune_fill(g, out, COUNT_FULL, reps=4)
+        cfg = rx.rng_fill_configs(kind)[rx.rng_get_fill_config(g)]
+        tuned = {"config": {"paced": cfg[0], "streams_per_thread": cfg[1], "block": cfg[2]},
+                 "candidates_ms": [round(m, 4) for m in tune_ms]}
     if mode == "u32":
         fn = lambda: rx.rng_fill_u32(g, out, COUNT_FULL)
     elif mode == "f32":
@@ -75,9 +83,12 @@ def bench_fill(rx, kind, mode, out, steps, warmup):
     samples = S_FULL * COUNT_FULL
     out_bytes = samples * 4 if mode != "consume" else S_FULL * 4
     alg_bytes = out_bytes + 2 * STATE_BYTES[kind] * S_FULL
-    return {"ms": round(ms, 4), "gsamples_s": round(samples / ms / 1e6, 2),
-            "gbs": round(alg_bytes / ms / 1e6, 1), "hbm_frac": round(alg_bytes / ms / 1e6 / HBM_PEAK_GBS, 4),
-            "ms_min": round(min(durs), 4)}
+    rec = {"ms": round(ms, 4), "gsamples_s": round(samples / ms / 1e6, 2),
+           "gbs": round(alg_bytes / ms / 1e6, 1), "hbm_frac": round(alg_bytes / ms / 1e6 / HBM_PEAK_GBS, 4),
+           "ms_min": round(min(durs), 4)}
+    if tuned:
+        rec["autotune"] = tuned
+    return rec
 
 
 def bench_write_ceiling(out, steps, warmup):
@@ -93,13 +104,19 @@ def bench_skip(rx, kind, reps=5):
 
 
 def bench_ising(rx, kind, L, sweeps, beta=0.4):
+    """One call of `sweeps` sweeps (energy trace on), after the plan
+    autotuner (untimed; it restores spins and streams) and 5 warm-up sweeps."""
     import torch
     lat = rx.ising_create(L, kind, 1)
+    plans = rx.ising_plans(lat)
+    tune_ms = rx.ising_autotune(lat, beta, 20, reps=1)
     rx.ising_sweep(lat, beta, 5)
     tr = torch.zeros(sweeps, dtype=torch.int32, device="cuda")
     durs, _ = time_launches(lambda: rx.ising_sweep(lat, beta, sweeps, tr), 1, 0)
     ms = durs[0]
-    return {"sweeps": sweeps, "ms": round(ms, 3), "flips_per_ns": round(L * L * sweeps / (ms * 1e6), 2)}
+    return {"sweeps": sweeps, "ms": round(ms, 3), "flips_per_ns": round(L * L * sweeps / (ms * 1e6), 2),
+            "strips": rx.ising_info(lat)["strips"],
+            "autotune": {"plans": plans, "ms_per_20_sweeps": [round(m, 3) for m in tune_ms]}}
 
 
 def bench_ising_batch(rx, n=512, sweeps=10000, base_sweeps=1000, seed=1):
@@ -360,7 +377,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "xs1024w bulk fill, uint32, interleaved out[k*S+s]", "n_streams": S_FULL,
-                   "outputs_per_stream": COUNT_FULL, "seed": 1, "generator": "XORShift-1024 + Weyl (paper's)"},
+                   "outputs_per_stream": COUNT_FULL, "seed": 1, "generator": "XORShift-1024 + Weyl (paper's)",
+                   "fill_config": head.get("autotune", {}).get("config")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile()},
         "kernel_hash": kernel_hash(),
