@@ -81,8 +81,9 @@ void free_ragged(Ragged *r) {
 
 void free_batch(IsingBatch *b) {
     (void)hipFree(b->d_reps);
-    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_items);
     (void)hipFree(b->d_next);
+    (void)hipFree(b->d_halo);
     delete[] b->lats;
     b->magic = 0;
     delete b;

@@ -158,13 +158,21 @@ __device__ __forceinline__ void lds_put(uint8_t *p, uint64_t w) {
 }
 
 // ---------------------------------------------------------------- strips
+// A batch replica runs in one of three modes: in memory by one workgroup
+// (kReplicaMemory), on chip by one workgroup (kReplicaOnChip, R = L), or as
+// a gang of nwg strip workgroups of R rows each (kReplicaStrips) that
+// exchange tagged halo words like the strips of one lattice.
+constexpr uint32_t kReplicaMemory = 0, kReplicaOnChip = 1, kReplicaStrips = 2;
 struct ReplicaDesc {
     int8_t *spins;
     uint8_t *st;
     uint64_t S;
-    uint32_t L, on_chip;
+    uint32_t L, mode;
     uint64_t T4, T8, n_sweeps;
-    int32_t *trace;  // may be null
+    int32_t *trace;   // may be null
+    uint32_t R, nwg, units;  // strips: rows and units per strip, strip count
+    uint64_t *halo;   // strips: 2 slots x nwg x 2 rows x L/4 tagged words
+    uint32_t *err;    // the lattice's error word (a strip gave up waiting)
 };
 
 struct StripArgs {
@@ -674,10 +682,16 @@ template <class Unit>
 constexpr int batch_spt() { return Unit::kNB == 8 ? 8 : 16; }
 constexpr uint32_t kBatchThreads = 1024;
 
+// Work items are (replica, strip) pairs; a gang's strips are consecutive in
+// the list, which the workgroups take in order from a counter.  Every
+// workgroup of the launch is resident, so when a strip waits for a neighbour
+// that neighbour is either running or will be taken by the next workgroup to
+// finish its (independent) item; gangs are far smaller than the grid.
 template <class Unit>
-__global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc *reps, const uint32_t *order, uint32_t n,
-                                                              uint32_t *next) {
+__global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc *reps, const uint2 *items,
+                                                              uint32_t n_items, uint32_t *next) {
     constexpr int NB = Unit::kNB;
+    constexpr int spt = batch_spt<Unit>();
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t idx_s;
     __shared__ int red_s[16];
@@ -686,18 +700,32 @@ __global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc
         if (threadIdx.x == 0) idx_s = atomicAdd(next, 1u);
         __syncthreads();
         const uint32_t idx = idx_s;
-        if (idx >= n) break;  // every workgroup leaves once the list is drained
-        const ReplicaDesc d = reps[order[idx]];
-        if (d.on_chip) {
-            const StripArgs a{d.spins, d.st, d.S, d.L, d.L, 1, static_cast<uint32_t>(static_cast<uint64_t>(d.L) * d.L / NB),
-                              d.T4, d.T8, d.n_sweeps, d.trace, nullptr, 0, nullptr};
-            constexpr int spt = batch_spt<Unit>();
-            if (early_slots<spt>(d.L / NB, a.units, blockDim.x)) strip_body<Unit, spt, true, false>(a, 0, lds);
-            else strip_body<Unit, spt, false, false>(a, 0, lds);
-        } else {
+        if (idx >= n_items) break;  // every workgroup leaves once the list is drained
+        const uint2 item = items[idx];
+        const ReplicaDesc d = reps[item.x];
+        if (d.mode == kReplicaMemory) {
             replica_in_memory<Unit>(d, red_s);
+            continue;
         }
+        const StripArgs a{d.spins, d.st, d.S, d.L, d.R, d.nwg, d.units, d.T4, d.T8, d.n_sweeps, d.trace,
+                          d.halo, 0, d.err};
+        if (early_slots<spt>(d.L / NB, d.units, blockDim.x)) strip_body<Unit, spt, true, false>(a, item.y, lds);
+        else strip_body<Unit, spt, false, false>(a, item.y, lds);
     }
+}
+
+// Before each batch run: the work counter, and for every gang its halo
+// tags (so that the pass tags can restart at 1 on every run, also on graph
+// replays) and its energy trace (strips add their parts).  Block i: replica i.
+__global__ __launch_bounds__(kBlock) void k_batch_prologue(const ReplicaDesc *reps, uint32_t *next) {
+    const ReplicaDesc d = reps[blockIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *next = 0;
+    if (d.mode != kReplicaStrips) return;
+    uint32_t *h = reinterpret_cast<uint32_t *>(d.halo);
+    const uint64_t words = 2ull * d.nwg * d.L;
+    for (uint64_t i = threadIdx.x; i < words; i += kBlock) h[i] = 0;
+    if (d.trace)
+        for (uint64_t i = threadIdx.x; i < d.n_sweeps; i += kBlock) d.trace[i] = 0;
 }
 
 // trace[t] = -(sum of n partials); one block, deterministic order.
@@ -853,6 +881,7 @@ hipError_t run(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hi
 }
 
 constexpr uint32_t kBatchLdsCap = 80 * 1024;  // keeps two batch workgroups per CU
+constexpr uint32_t kMaxGang = 32;             // most strips of one batch replica
 
 template <class Unit>
 const void *batch_kernel() { return reinterpret_cast<const void *>(&k_ising_batch<Unit>); }
@@ -879,23 +908,43 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
                          int32_t *const *traces, int n_cu) {
     const uint32_t n = b->n;
     const uint32_t nb = b->kind == RNGX_XS1024W ? 8 : 4;
+    const uint64_t spt = nb == 8 ? 8 : 16, max_units = spt * kBatchThreads;
     std::vector<ReplicaDesc> reps(n);
     uint32_t lds = 80;
+    uint64_t halo_bytes = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const Ising *l = lats[i];
-        const uint64_t L = l->L, units = L * L / nb, bytes = strip_lds_bytes(l->L, l->L);
-        const uint64_t spt = nb == 8 ? 8 : 16;
-        const bool on_chip = units <= spt * kBatchThreads && bytes <= kBatchLdsCap;
-        reps[i] = ReplicaDesc{l->d_spins, l->gen->d_state, l->gen->S, l->L, on_chip ? 1u : 0u,
-                              threshold(betas[i], 4), threshold(betas[i], 8), n_sweeps[i], traces ? traces[i] : nullptr};
-        if (on_chip) lds = std::max<uint32_t>(lds, static_cast<uint32_t>(bytes));
+        const uint32_t L = l->L;
+        ReplicaDesc d{l->d_spins, l->gen->d_state, l->gen->S, L, kReplicaMemory, threshold(betas[i], 4),
+                      threshold(betas[i], 8), n_sweeps[i], traces ? traces[i] : nullptr, 0, 0, 0, nullptr, l->d_err};
+        // fewest strips (one if possible) whose strip fits the workgroup's LDS and unit slots
+        for (uint32_t R = L; R >= 2; --R) {
+            if (L % R) continue;
+            const uint64_t units = static_cast<uint64_t>(R) * L / nb;
+            if (units > max_units || strip_lds_bytes(L, R) > kBatchLdsCap) continue;
+            if (nb == 8 && (static_cast<uint64_t>(R) * L) % 128) continue;
+            const uint32_t nwg = L / R;
+            if (nwg > kMaxGang) break;
+            d.mode = nwg == 1 ? kReplicaOnChip : kReplicaStrips;
+            d.R = R;
+            d.nwg = nwg;
+            d.units = static_cast<uint32_t>(units);
+            lds = std::max<uint32_t>(lds, static_cast<uint32_t>(strip_lds_bytes(L, R)));
+            if (nwg > 1) halo_bytes += 8ull * nwg * L;
+            break;
+        }
+        reps[i] = d;
     }
+    // items: replicas by decreasing work per item, each gang's strips together
     std::vector<uint32_t> order(n);
     for (uint32_t i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-        return static_cast<double>(reps[x].L) * reps[x].L * reps[x].n_sweeps >
-               static_cast<double>(reps[y].L) * reps[y].L * reps[y].n_sweeps;
-    });
+    auto work = [&](uint32_t x) {
+        return static_cast<double>(reps[x].L) * reps[x].L * reps[x].n_sweeps / std::max<uint32_t>(reps[x].nwg, 1);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return work(x) > work(y); });
+    std::vector<uint2> items;
+    for (uint32_t x : order)
+        for (uint32_t j = 0; j < std::max<uint32_t>(reps[x].nwg, 1); ++j) items.push_back(make_uint2(x, j));
     const void *fn = batch_kernel_for(b->kind);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     (void)hipGetLastError();
@@ -903,27 +952,47 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBatchThreads, lds);
     if (e != hipSuccess) return e;
     if (occ < 1) return hipErrorOutOfMemory;
+    const uint32_t resident = static_cast<uint32_t>(occ * std::max(n_cu, 1));
+    if (resident < 2 * kMaxGang) {  // too few workgroups to run gangs safely: strips go to memory
+        halo_bytes = 0;
+        for (auto &d : reps)
+            if (d.mode == kReplicaStrips) d = ReplicaDesc{d.spins, d.st, d.S, d.L, kReplicaMemory, d.T4, d.T8,
+                                                          d.n_sweeps, d.trace, 0, 0, 0, nullptr, d.err};
+        items.clear();
+        for (uint32_t x : order) items.push_back(make_uint2(x, 0));
+    }
     b->lds = lds;
-    b->grid = std::min<uint32_t>(n, static_cast<uint32_t>(occ * std::max(n_cu, 1)));
+    b->n_items = static_cast<uint32_t>(items.size());
+    b->grid = std::min<uint32_t>(b->n_items, resident);
+    if (halo_bytes) {
+        if ((e = hipMalloc(&b->d_halo, halo_bytes)) != hipSuccess) return e;
+        uint64_t off = 0;
+        for (auto &d : reps)
+            if (d.mode == kReplicaStrips) {
+                d.halo = reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(b->d_halo) + off);
+                off += 8ull * d.nwg * d.L;
+            }
+    }
     if ((e = hipMalloc(&b->d_reps, sizeof(ReplicaDesc) * n)) != hipSuccess) return e;
-    if ((e = hipMalloc(&b->d_order, 4ull * n)) != hipSuccess) return e;
+    if ((e = hipMalloc(&b->d_items, sizeof(uint2) * items.size())) != hipSuccess) return e;
     if ((e = hipMalloc(&b->d_next, 4)) != hipSuccess) return e;
     if ((e = hipMemcpy(b->d_reps, reps.data(), sizeof(ReplicaDesc) * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    return hipMemcpy(b->d_order, order.data(), 4ull * n, hipMemcpyHostToDevice);
+    return hipMemcpy(b->d_items, items.data(), sizeof(uint2) * items.size(), hipMemcpyHostToDevice);
 }
 
 hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
     if (b->n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBlock), 0, st, b->d_next, static_cast<uint64_t>(1));
-    const dim3 grid(b->grid), block(kBatchThreads);
     const auto *reps = static_cast<const ReplicaDesc *>(b->d_reps);
+    const auto *items = static_cast<const uint2 *>(b->d_items);
+    hipLaunchKernelGGL(k_batch_prologue, dim3(b->n), dim3(kBlock), 0, st, reps, b->d_next);
+    const dim3 grid(b->grid), block(kBatchThreads);
     switch (b->kind) {
-    case RNGX_LCG32: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg32>>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
-    case RNGX_LCG64: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg64>>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
-    case RNGX_MWC: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Mwc>>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
-    case RNGX_XORWOW: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Xorwow>>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
-    case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ising_batch<PhiloxUnit>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
-    case RNGX_XS1024W: hipLaunchKernelGGL(k_ising_batch<XsUnit>, grid, block, b->lds, st, reps, b->d_order, b->n, b->d_next); break;
+    case RNGX_LCG32: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg32>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
+    case RNGX_LCG64: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg64>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
+    case RNGX_MWC: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Mwc>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
+    case RNGX_XORWOW: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Xorwow>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
+    case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ising_batch<PhiloxUnit>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
+    case RNGX_XS1024W: hipLaunchKernelGGL(k_ising_batch<XsUnit>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     }
     return hipGetLastError();
 }

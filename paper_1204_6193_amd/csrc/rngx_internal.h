@@ -108,8 +108,10 @@ struct IsingBatch {
     rngx_kind kind;
     uint32_t n;
     void *d_reps;        // replica descriptors (device)
-    uint32_t *d_order;   // replicas in decreasing order of work
+    void *d_items;       // (replica, strip) work items, gangs consecutive, decreasing work
+    uint32_t n_items;
     uint32_t *d_next;    // work counter
+    void *d_halo;        // tagged halo words of the gang replicas
     uint32_t lds, grid;  // launch shape
     Ising **lats;        // host copy of the members
 };

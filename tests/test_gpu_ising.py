@@ -215,6 +215,28 @@ def test_batch_equals_individual_sweeps(rngx, kind):
                                   rngx.rng_get_state(rngx.ising_rng(tw))), (rep, i)
 
 
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
+def test_batch_gangs_and_memory_replicas(rngx, kind):
+    """Large replicas run as gangs of strip workgroups (L = 1024: 16 strips;
+    1008, 784: odd strip counts; 272: two) or, beyond the largest gang, in
+    memory (L = 2048); each equals ising_sweep on the lattice alone."""
+    print(f"case batch gangs {kind}", flush=True)
+    Ls, betas, sweeps = [1024, 1008, 784, 272, 2048, 48], [0.4, 0.35, 0.5, 0.44, 0.41, 0.3], [3, 2, 4, 3, 2, 5]
+    lats = [rngx.ising_create(L, kind, 300 + i) for i, L in enumerate(Ls)]
+    twins = [rngx.ising_create(L, kind, 300 + i) for i, L in enumerate(Ls)]
+    traces = [torch.full((s,), 7, dtype=torch.int32, device="cuda") for s in sweeps]
+    batch = rngx.ising_batch_create(lats, betas, sweeps, traces)
+    for rep in range(2):
+        rngx.ising_batch_run(batch)
+        for i, tw in enumerate(twins):
+            tt = torch.zeros(sweeps[i], dtype=torch.int32, device="cuda")
+            rngx.ising_sweep(tw, betas[i], sweeps[i], tt)
+            assert torch.equal(traces[i], tt), (rep, i, Ls[i])
+            assert np.array_equal(rngx.ising_get_spins(lats[i]), rngx.ising_get_spins(tw)), (rep, i, Ls[i])
+            assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[i])),
+                                  rngx.rng_get_state(rngx.ising_rng(tw))), (rep, i)
+
+
 def test_batch_small_replicas_match_oracle(rngx, orc):
     kind = "xs1024w"
     Ls, betas, sweeps = [16, 48, 96], [0.31, 0.44, 0.58], [3, 5, 2]

@@ -144,6 +144,32 @@ def test_results_do_not_depend_on_the_stream(rngx):
     assert torch.equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
+def test_paced_fill_graph_replays(rngx, kind):
+    """A paced fill (counters cleared by a kernel, not a memset) captured in a
+    HIP graph: every replay equals the same fill run eagerly on a twin
+    handle, with eager work in between."""
+    S, count = 1 << 19, 40
+    print(f"case graph paced fill {kind}", flush=True)
+    ga, gb = rngx.rng_create(kind, S, 6), rngx.rng_create(kind, S, 6)
+    oa = torch.empty(S * count, dtype=torch.int32, device="cuda")
+    ob = torch.empty(S * count, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        rngx.rng_fill_u32(ga, oa, count, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        rngx.rng_fill_u32(gb, ob, count)
+        torch.cuda.synchronize()
+        assert torch.equal(oa, ob), (kind, rep)
+        assert np.array_equal(rngx.rng_get_state(ga), rngx.rng_get_state(gb)), (kind, rep)
+    del oa, ob
+    torch.cuda.empty_cache()
+
+
 def test_xs1024w_config_4096_streams_x_1024(rngx, orc):
     """The paper's generator: 4096 streams seeded from master seed 1, 1024
     outputs each (4,194,304 values), the whole array bit-exact."""
