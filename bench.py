@@ -30,7 +30,7 @@ KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10"]
 # state bytes read + written once per launch, per stream
 STATE_BYTES = {"lcg32": 4, "lcg64": 8, "mwc": 8, "xorwow": 24, "philox4x32_10": 16, "xs1024w": 4 + 8 / 32}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "xs1024w_fill_u32_2p20x4096_hbm_traffic.md")
-KERNEL_SOURCES = ["paper_1204_6193_amd/csrc/gen.hip", "paper_1204_6193_amd/csrc/rngx_internal.h"]
+KERNEL_SOURCES = ["paper_1204_6193_amd/csrc/gen.hip", "paper_1204_6193_amd/csrc/rngx_device.h"]
 
 
 def kernel_hash() -> str:
