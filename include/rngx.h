@@ -214,7 +214,7 @@ rngx_status ising_autotune(rngx_ising lat, double beta, uint64_t n_sweeps, int32
  * must be 4-byte aligned and hold offsets[n_units] elements.  The generator
  * must outlive the plan (rng_destroy returns RNGX_E_BUSY meanwhile).
  * Errors: RNGX_E_INVALID (wrong count, decreasing offsets, NULL),
- * RNGX_E_OVERFLOW, RNGX_E_NOMEM. */
+ * RNGX_E_OVERFLOW (output size, or 2^32 or more chunks), RNGX_E_NOMEM. */
 rngx_status rng_ragged_create(rngx_gen g, const uint64_t *offsets, uint64_t n_offsets, rngx_ragged *out);
 rngx_status rng_fill_ragged_u32(rngx_ragged r, uint32_t *d_out, void *stream);
 rngx_status rng_ragged_destroy(rngx_ragged r);

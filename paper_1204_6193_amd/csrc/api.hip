@@ -75,6 +75,7 @@ void free_ragged(Ragged *r) {
     (void)hipFree(r->d_scratch);
     (void)hipFree(r->d_t64);
     (void)hipFree(r->d_t32);
+    (void)hipFree(r->d_slots);
     r->magic = 0;
     delete r;
 }
@@ -357,21 +358,27 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
         if (offsets[u + 1] < offsets[u]) return fail(RNGX_E_INVALID, "offsets decrease at " + std::to_string(u));
     uint64_t bytes;
     if (mul_overflows(offsets[units], 4, &bytes)) return fail(RNGX_E_OVERFLOW, "output size overflows");
-    std::vector<RaggedItem> items;
-    uint64_t max_chunks = 1;
-    ragged_plan(g->kind, offsets, units, &items, &max_chunks);
+    RaggedPlan plan;
+    ragged_plan(g->kind, offsets, units, g->n_cu, &plan);
+    const std::vector<RaggedItem> &items = plan.items;
+    if (items.size() > 0xFFFFFFFFull) return fail(RNGX_E_OVERFLOW, "too many chunks in one ragged plan");
     std::vector<uint64_t> t64;
     std::vector<uint32_t> t32;
-    jump_table(g->kind, ragged_chunk(g->kind), max_chunks, &t64, &t32);
+    jump_table(g->kind, plan.step, plan.max_j + 1, &t64, &t32);
     DeviceScope ds(g->device);
     Ragged *r = new Ragged{};
     r->magic = kRaggedMagic;
     r->gen = g;
     r->n_items = items.size();
     r->total = offsets[units];
+    r->step = plan.step;
+    r->n_slots = plan.slots.empty() ? 0 : static_cast<uint32_t>(plan.slots.size() - 1);
     hipError_t e = hipSuccess;
     if (!items.empty()) {
         e = hipMalloc(&r->d_items, sizeof(RaggedItem) * items.size());
+        if (e == hipSuccess && !plan.slots.empty()) e = hipMalloc(&r->d_slots, 4 * plan.slots.size());
+        if (e == hipSuccess && !plan.slots.empty())
+            e = hipMemcpy(r->d_slots, plan.slots.data(), 4 * plan.slots.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMalloc(&r->d_scratch, ragged_scratch_bytes(g->kind, items.size()));
         if (e == hipSuccess && !t64.empty()) e = hipMalloc(&r->d_t64, 8 * t64.size());
         if (e == hipSuccess && !t32.empty()) e = hipMalloc(&r->d_t32, 4 * t32.size());

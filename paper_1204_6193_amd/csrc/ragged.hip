@@ -6,13 +6,17 @@
 // order (step k, lane i -> out[off_g + 32 k + i]), taking ceil(len_g / 32)
 // steps and dropping the lanes of a last partial step.
 //
-// A request is cut into chunks of C outputs (XS1024W: C instance steps) so
-// that long requests spread over many threads.  The first kernel puts the
-// start state of every chunk j into scratch by jumping the stream's state by
-// j*C (precomputed powers of the C-step map: affine pairs, a^(jC) mod p, or
-// GF(2) polynomials x^(jC) mod P applied by Horner's rule); the second
-// kernel generates every chunk from its start state, and the last chunk of a
-// stream writes the stream's final state back.
+// A request is cut into chunks so that long requests spread over many
+// threads.  The first kernel puts the start state of every chunk j into
+// scratch by jumping the stream's state by j*C (precomputed powers of the
+// C-step map: affine pairs, a^(jC) mod p, or GF(2) polynomials x^(jC) mod P
+// applied by Horner's rule); the second kernel generates every chunk from its
+// start state, and the last chunk of a stream writes the stream's final state
+// back.  Small-state kinds take one chunk of C outputs per lane.  XS1024W
+// balances rows instead: the instances' steps, concatenated, are cut into
+// about equal slots (cuts inside an instance on multiples of C), and one
+// 16-lane row generates all chunks of its slot in turn, so no row waits on a
+// longer one and the only jumps are those at the cuts.
 #include <algorithm>
 #include <vector>
 
@@ -25,8 +29,12 @@ namespace {
 constexpr int kBlock = 256;
 
 // Each lane owns one chunk.  Rounds of 32 outputs go through a per-wave LDS
-// tile so that the wave writes two lanes' 32 consecutive values with one
-// store (two contiguous 128-byte pieces) instead of 64 scattered words.
+// tile so that the wave writes two lanes' segments with one store.  Rounds
+// are aligned to 32-word (128-byte) lines of the output: round r of a chunk
+// covers the line-aligned window [base + 32 r, base + 32 r + 32) and only the
+// chunk's first and last windows are partial, so every cache line but those
+// at chunk ends is written whole by one store.  Each lane puts the window's
+// address and its column range [lo, hi) in LDS for the store loop.
 constexpr int kSeg = 32;
 
 template <class G>
@@ -34,6 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_ragged_gen_small(const RaggedItem *i
                                                               const uint8_t *scratch, uint8_t *st, uint64_t S,
                                                               uint32_t *out) {
     __shared__ uint32_t tile[kBlock / 64][64][kSeg + 1];
+    __shared__ uint64_t desc[kBlock / 64][64][2];  // window address; lo | hi << 32
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6, half = lane >> 5, col = lane & 31;
     const bool mine = i < n_items;
@@ -44,20 +53,41 @@ __global__ __launch_bounds__(kBlock) void k_ragged_gen_small(const RaggedItem *i
         g.load(scratch, n_items, i);
     }
     const uint32_t len = mine ? it.len : 0;
-    uint32_t rounds = (len + kSeg - 1) / kSeg;  // rounds needed by the longest chunk of the wave
+    const uint32_t mis = static_cast<uint32_t>(it.out) & (kSeg - 1);
+    const uint64_t base = it.out - mis;
+    uint32_t rounds = len ? (mis + len + kSeg - 1) / kSeg : 0;  // rounds needed by the longest chunk of the wave
     for (int off = 32; off > 0; off >>= 1) rounds = max(rounds, static_cast<uint32_t>(__shfl_xor(static_cast<int>(rounds), off)));
     for (uint32_t rd = 0; rd < rounds; ++rd) {
-        const uint32_t base = rd * kSeg;
-        const uint32_t cnt = len > base ? min(static_cast<uint32_t>(kSeg), len - base) : 0;
-        for (uint32_t k = 0; k < cnt; ++k) tile[w][lane][k] = g.next();
+        const int64_t rem = static_cast<int64_t>(mis) + len - static_cast<int64_t>(rd) * kSeg;
+        const uint32_t lo = rd == 0 ? mis : 0;
+        const uint32_t hi = rem <= 0 ? 0 : static_cast<uint32_t>(min(rem, static_cast<int64_t>(kSeg)));
+        if (lo == 0 && hi == kSeg) {
+#pragma unroll
+            for (int c = 0; c < kSeg; ++c) tile[w][lane][c] = g.next();
+        } else {
+            for (uint32_t c = lo; c < hi; ++c) tile[w][lane][c] = g.next();
+        }
+        const uint64_t a = base + static_cast<uint64_t>(rd) * kSeg;
+        desc[w][lane][0] = a;
+        desc[w][lane][1] = lo | static_cast<uint64_t>(hi) << 32;
         __builtin_amdgcn_wave_barrier();
-        // lanes 0-31 write lane j's segment, lanes 32-63 lane j+1's
-        for (uint32_t j = 0; j < 64; j += 2) {
-            const uint32_t src = j + half;
-            const uint32_t len_j = static_cast<uint32_t>(__shfl(static_cast<int>(len), src));
-            const uint64_t out_j = static_cast<uint64_t>(__shfl(static_cast<long long>(it.out), src));
-            const uint32_t cnt_j = len_j > base ? min(static_cast<uint32_t>(kSeg), len_j - base) : 0;
-            if (col < cnt_j) out[out_j + base + col] = tile[w][src][col];
+        // lanes 0-31 write lane j's window, lanes 32-63 lane j+1's.  When
+        // every window of the wave is whole (all rounds but a chunk's first
+        // and last) the stores need no test.
+        if (__all((lo == 0) & (hi == kSeg))) {
+#pragma unroll 8
+            for (uint32_t j = 0; j < 64; j += 2) {
+                const uint32_t src = j + half;
+                out[desc[w][src][0] + col] = tile[w][src][col];
+            }
+        } else {
+#pragma unroll 4
+            for (uint32_t j = 0; j < 64; j += 2) {
+                const uint32_t src = j + half;
+                const uint64_t dr = desc[w][src][1];
+                if ((col >= static_cast<uint32_t>(dr)) & (col < static_cast<uint32_t>(dr >> 32)))
+                    out[desc[w][src][0] + col] = tile[w][src][col];
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -132,31 +162,66 @@ __global__ __launch_bounds__(kBlock) void k_ragged_start_xs(const RaggedItem *it
             reinterpret_cast<const uint64_t *>(st + 4 * S)[it.unit] + it.j * chunk;
 }
 
+// One 16-lane row per slot: the row runs its slot's chunks (consecutive
+// items slots[r] .. slots[r+1]-1) back to back in one flat loop, loading the
+// next chunk's start state from scratch when a chunk ends, and writes the
+// instance's final state after the instance's last chunk.  Control flow
+// depends on the row only, so the DPP moves of a step never see a lane of the
+// row switched off.
 __global__ __launch_bounds__(kBlock) void k_ragged_gen_xs(const RaggedItem *items, uint64_t n_items,
+                                                           const uint32_t *slots, uint32_t n_slots,
                                                            const uint8_t *scratch, uint8_t *st, uint64_t S,
                                                            uint32_t *out) {
     const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint64_t i = t >> 4, lane = t & 15;
-    if (i >= n_items) return;  // whole rows
-    const RaggedItem it = items[i];
-    const uint2 w = reinterpret_cast<const uint2 *>(scratch)[t];
-    uint32_t a = w.x, b = w.y;
-    const uint64_t n = reinterpret_cast<const uint64_t *>(scratch + 128 * n_items)[i];
+    const uint64_t r = t >> 4, lane = t & 15;
+    if (r >= n_slots) return;  // whole rows
+    uint32_t q = slots[r];
+    const uint32_t q_end = slots[r + 1];
+    if (q >= q_end) return;
+    const uint2 *starts = reinterpret_cast<const uint2 *>(scratch);
+    const uint64_t *counters = reinterpret_cast<const uint64_t *>(scratch + 128 * n_items);
     const uint32_t y0 = *reinterpret_cast<const uint32_t *>(st + 4 * S + 8 * (S / 32));
+    RaggedItem it = items[q];
+    uint2 w = starts[16ull * q + lane];
+    uint32_t a = w.x, b = w.y;
+    uint64_t n = counters[q];
     uint32_t y = y0 + static_cast<uint32_t>(n) * kWeylC;
-    uint32_t *o = out + it.out;
-    const uint64_t v0 = 2 * lane;
-    for (uint32_t k = 0; k < it.len; ++k) {
+    uint32_t *o = out + it.out + 2 * lane;
+    uint32_t k = 0;
+    // Loads of a chunk's data complete where they are issued (vmcnt(0)).
+    // Otherwise the wait lands at the loop head, and since stores share the
+    // counter, every step would wait for the previous step's stores.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    while (true) {
+        if (k == it.len) {
+            if (it.last) {
+                reinterpret_cast<uint2 *>(st)[16 * it.unit + lane] = make_uint2(a, b);
+                if (lane == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[it.unit] = n + it.len;
+            }
+            if (++q == q_end) break;
+            it = items[q];
+            w = starts[16ull * q + lane];
+            a = w.x;
+            b = w.y;
+            n = counters[q];
+            y = y0 + static_cast<uint32_t>(n) * kWeylC;
+            o = out + it.out + 2 * lane;
+            k = 0;
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
         xs1024_step(a, b);
         y += kWeylC;
         const uint32_t m = weyl_mix(y);
-        const uint64_t v = 32ull * k + v0;
-        if (v < it.nvals) o[v] = a + m;
-        if (v + 1 < it.nvals) o[v + 1] = b + m;
-    }
-    if (it.last) {
-        reinterpret_cast<uint2 *>(st)[16 * it.unit + lane] = make_uint2(a, b);
-        if (lane == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[it.unit] = n + it.len;
+        if (k + 1 < it.len) {
+            o[0] = a + m;
+            o[1] = b + m;
+        } else {  // the chunk's last step may be partial
+            const uint64_t v = 32ull * k + 2 * lane;
+            if (v < it.nvals) o[0] = a + m;
+            if (v + 1 < it.nvals) o[1] = b + m;
+        }
+        o += 32;
+        ++k;
     }
 }
 
@@ -266,35 +331,87 @@ hipError_t launch_stream_fill(rngx_kind kind, const uint8_t *st_in, uint8_t *st_
     return hipGetLastError();
 }
 
-uint64_t ragged_chunk(rngx_kind kind) { return kind == RNGX_XS1024W ? 8192 : 4096; }
+uint64_t ragged_chunk(rngx_kind) { return 4096; }
 
-void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, std::vector<RaggedItem> *items,
-                 uint64_t *max_chunks) {
-    const uint64_t C = ragged_chunk(kind);
-    const bool xs = kind == RNGX_XS1024W;
-    items->clear();
-    *max_chunks = 1;
-    for (uint64_t u = 0; u < n_units; ++u) {
-        const uint64_t total = off[u + 1] - off[u];
-        const uint64_t steps = xs ? (total + 31) / 32 : total;
-        const uint64_t nch = (steps + C - 1) / C;
-        *max_chunks = std::max(*max_chunks, nch);
-        for (uint64_t j = 0; j < nch; ++j) {
-            RaggedItem it{};
-            it.unit = u;
-            it.j = j;
-            it.len = static_cast<uint32_t>(std::min(C, steps - j * C));
-            it.last = j + 1 == nch;
-            if (xs) {
-                it.out = off[u] + 32 * j * C;
-                it.nvals = std::min<uint64_t>(32ull * it.len, total - 32 * j * C);
-            } else {
+void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan) {
+    std::vector<RaggedItem> &items = plan->items;
+    items.clear();
+    plan->slots.clear();
+    plan->max_j = 0;
+    if (kind != RNGX_XS1024W) {
+        const uint64_t C = ragged_chunk(kind);
+        plan->step = C;
+        for (uint64_t u = 0; u < n_units; ++u) {
+            const uint64_t total = off[u + 1] - off[u];
+            const uint64_t nch = (total + C - 1) / C;
+            if (nch) plan->max_j = std::max(plan->max_j, nch - 1);
+            for (uint64_t j = 0; j < nch; ++j) {
+                RaggedItem it{};
+                it.unit = u;
+                it.j = j;
+                it.len = static_cast<uint32_t>(std::min(C, total - j * C));
+                it.last = j + 1 == nch;
                 it.out = off[u] + j * C;
                 it.nvals = it.len;
+                items.push_back(it);
             }
-            items->push_back(it);
+        }
+        return;
+    }
+    // XS1024W: concatenate the instances' steps and cut them into R slots of
+    // about Q steps; a cut inside an instance is rounded to a multiple of J
+    // steps (the jump table step), chosen so that the table stays small.
+    uint64_t T = 0, max_steps = 0;
+    for (uint64_t u = 0; u < n_units; ++u) {
+        const uint64_t steps = (off[u + 1] - off[u] + 31) / 32;
+        T += steps;
+        max_steps = std::max(max_steps, steps);
+    }
+    uint64_t J = 128;
+    while ((max_steps + J - 1) / J > 16384) J *= 2;
+    plan->step = J;
+    if (T == 0) return;
+    const uint64_t R = std::max<uint64_t>(
+        1, std::min<uint64_t>(static_cast<uint64_t>(kXsRowsPerCu) * std::max(n_cu, 1), (T + kXsMinSlotSteps - 1) / kXsMinSlotSteps));
+    const uint64_t Q = (T + R - 1) / R;
+    // Slot r should end at (r + 1) Q placed steps; G (steps placed) stays
+    // below the open slot's target between pieces.
+    uint64_t G = 0, r = 0;
+    plan->slots.push_back(0);
+    for (uint64_t u = 0; u < n_units; ++u) {
+        const uint64_t total = off[u + 1] - off[u], steps = (total + 31) / 32;
+        uint64_t p = 0;  // always 0 or a multiple of J
+        while (p < steps) {
+            const uint64_t target = (r + 1) * Q;
+            uint64_t end = steps;
+            bool close = false;
+            if (G + (steps - p) >= target) {  // the slot ends in this instance
+                close = true;
+                const uint64_t want = p + (target - G);
+                if (want < steps) {
+                    uint64_t cut = (want + J / 2) / J * J;
+                    if (cut <= p) cut = p + J;
+                    if (cut < steps) end = cut;
+                }
+            }
+            RaggedItem it{};
+            it.unit = u;
+            it.j = p / J;
+            it.len = static_cast<uint32_t>(end - p);
+            it.last = end == steps;
+            it.out = off[u] + 32 * p;
+            it.nvals = std::min<uint64_t>(32 * (end - p), total - 32 * p);
+            plan->max_j = std::max(plan->max_j, it.j);
+            items.push_back(it);
+            G += end - p;
+            p = end;
+            if (close) {
+                plan->slots.push_back(static_cast<uint32_t>(items.size()));
+                r = std::max(r + 1, G / Q);
+            }
         }
     }
+    if (plan->slots.back() != items.size()) plan->slots.push_back(static_cast<uint32_t>(items.size()));
 }
 
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items) {
@@ -305,12 +422,12 @@ hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st) {
     Gen *g = r->gen;
     const uint64_t n = r->n_items;
     if (n == 0) return hipSuccess;
-    const uint64_t C = ragged_chunk(g->kind);
+    const uint64_t C = r->step;
     if (g->kind == RNGX_XS1024W) {
         hipLaunchKernelGGL(k_ragged_start_xs, dim3(blocks_for(16 * n)), dim3(kBlock), 0, st, r->d_items, n,
                            g->d_state, g->S, r->d_scratch, r->d_t32, C);
-        hipLaunchKernelGGL(k_ragged_gen_xs, dim3(blocks_for(16 * n)), dim3(kBlock), 0, st, r->d_items, n,
-                           r->d_scratch, g->d_state, g->S, d_out);
+        hipLaunchKernelGGL(k_ragged_gen_xs, dim3(blocks_for(16ull * r->n_slots)), dim3(kBlock), 0, st, r->d_items,
+                           n, r->d_slots, r->n_slots, r->d_scratch, g->d_state, g->S, d_out);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_ragged_start_small, dim3(blocks_for(n)), dim3(kBlock), 0, st, g->kind, r->d_items, n,

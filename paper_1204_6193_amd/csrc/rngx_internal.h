@@ -52,6 +52,9 @@ struct Ragged {
     uint8_t *d_scratch;  // chunk start states
     uint64_t *d_t64;     // jump tables (see jump_table)
     uint32_t *d_t32;
+    uint64_t step;       // jump table step: chunk j starts j*step outputs (steps) in
+    uint32_t n_slots;    // XS1024W: rows of the generation kernel
+    uint32_t *d_slots;   // XS1024W: first item of each row, n_slots + 1 entries
 };
 
 // How a lattice is swept: as strips held on chip by co-resident
@@ -139,9 +142,20 @@ int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int ma
 hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas, const uint64_t *n_sweeps,
                          int32_t *const *traces, int n_cu);
 hipError_t launch_batch(IsingBatch *b, hipStream_t st);
+// Work items of a ragged fill.  Small-state kinds: chunks of ragged_chunk
+// outputs, one per lane.  XS1024W: the steps of all instances, concatenated,
+// are cut into about equal slots, one per generating row (up to
+// kXsRowsPerCu per compute unit); cuts inside an instance fall on multiples
+// of *step.  *max_j is the largest chunk index (jump table size - 1).
+struct RaggedPlan {
+    std::vector<RaggedItem> items;
+    std::vector<uint32_t> slots;  // XS1024W only
+    uint64_t step = 1, max_j = 0;
+};
+constexpr uint32_t kXsRowsPerCu = 128;      // 8 waves per SIMD x 4 SIMDs x 4 rows
+constexpr uint64_t kXsMinSlotSteps = 2048;  // slots are not cut finer than this
 uint64_t ragged_chunk(rngx_kind kind);
-void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, std::vector<RaggedItem> *items,
-                 uint64_t *max_chunks);
+void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan);
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items);
 hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st);
 uint64_t stream_fill_chunk(rngx_kind kind);

@@ -87,3 +87,62 @@ def test_ragged_argument_errors(rngx):
     p = rngx.rng_ragged_create(g, list(range(0, 18, 2)))
     assert rngx.load().rng_destroy(g.handle) == -7     # held by the plan
     p.destroy()
+
+
+def _runs(seed, target):
+    """Requests in runs of equal length (the oracle's jump-ahead then covers a
+    whole run in one call): run lengths log-uniform in [2^10, 2^22], 1..120
+    requests per run, about `target` values in all; one run of empty
+    requests and one of single values."""
+    rng = np.random.default_rng(seed)
+    runs, total = [(3, 0), (2, 1)], 0
+    while total < target:
+        ln, m = int(2.0 ** (10 + 12 * rng.random())), int(rng.integers(1, 121))
+        runs.append((m, ln))
+        total += m * ln
+    order = rng.permutation(len(runs))
+    return [runs[i] for i in order]
+
+
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
+def test_ragged_bench_shape_sampled(rngx, orc, kind):
+    """About 2.2e9 values in requests of 2^10 .. 2^22 values: large enough
+    that the XS1024W plan uses its full row count, with cuts inside many
+    instances.  Sampled requests are compared with the oracle value by value,
+    every stream's final state with the oracle's jump-ahead, and one word past
+    the end stays untouched."""
+    print(f"case ragged bench shape {kind}", flush=True)
+    runs = _runs(5, 2.2e9)
+    lens = np.concatenate([np.full(m, ln, dtype=np.int64) for m, ln in runs])
+    n = len(lens)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    total = int(off[-1])
+    width = 32 if kind == "xs1024w" else 1
+    S = width * n
+    g = rngx.rng_create(kind, S, 21)
+    plan = rngx.rng_ragged_create(g, off)
+    out = torch.empty(total + 1, dtype=torch.int32, device="cuda")
+    out[total] = -1
+    rngx.rng_fill_ragged_u32(plan, out)
+    torch.cuda.synchronize()
+    st0 = orc.seed(kind, S, 21)
+    rng = np.random.default_rng(6)
+    sample = sorted({0, int(np.argmax(lens)), int(np.argmin(lens)), n - 1,
+                     *(int(u) for u in rng.choice(n, size=10, replace=False))})
+    for u in sample:
+        ln = int(lens[u])
+        st = st0.copy()
+        steps = (ln + 31) // 32 if kind == "xs1024w" else ln
+        want = orc.generate(kind, S, st, steps, lo=width * u, hi=width * u + width).ravel()[:ln]
+        got = out[int(off[u]): int(off[u]) + ln].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, want), (kind, u, ln)
+    assert int(out[total].item()) == -1
+    st, u = st0.copy(), 0
+    for m, ln in runs:
+        steps = (ln + 31) // 32 if kind == "xs1024w" else ln
+        if steps:
+            orc.jump(kind, S, st, steps, lo=width * u, hi=width * (u + m))
+        u += m
+    assert np.array_equal(rngx.rng_get_state(g), st), kind
+    del out
+    torch.cuda.empty_cache()
