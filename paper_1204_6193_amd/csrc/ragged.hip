@@ -144,85 +144,115 @@ __global__ __launch_bounds__(kBlock) void k_ragged_start_small(rngx_kind kind, c
     }
 }
 
-// XS1024W: 16 lanes (one DPP row) per chunk.  Scratch holds, per item, the
-// 32 words (as 16 lane pairs) and the step counter.
-__global__ __launch_bounds__(kBlock) void k_ragged_start_xs(const RaggedItem *items, uint64_t n_items,
-                                                             const uint8_t *st, uint64_t S, uint8_t *scratch,
-                                                             const uint32_t *t32, uint64_t chunk) {
+// XS1024W: one 16-lane row per slot.  The row runs its slot's chunks
+// (items slots[r] .. slots[r+1]-1) in turn: it takes the instance's state,
+// jumps it by j*C if the chunk starts inside the instance (only a slot's
+// first chunk can), and generates the chunk.  The states are only read here;
+// after an instance's last chunk the row puts the final state in scratch
+// (per item: 16 lane pairs, then the step counters at 128 * n_items) and a
+// second kernel copies it back, so no row can read a state another row has
+// already advanced.
+//
+// Stores are aligned to 32-word (128-byte) output lines: step k's 32 words
+// go into a 64-word LDS ring and lane i writes the word pair at positions
+// 2i, 2i+1 of line k of the chunk's aligned span, which holds the last `mis`
+// words of step k-1 and the first 32-mis of step k (mis: the chunk's start
+// modulo 32 words).  Inside a chunk every store is one whole line per row;
+// only the first and last lines of a chunk are partial.
+__global__ __launch_bounds__(kBlock) void k_ragged_xs(const RaggedItem *items, uint64_t n_items,
+                                                       const uint32_t *slots, uint32_t n_slots, const uint8_t *st,
+                                                       uint64_t S, const uint32_t *t32, uint64_t chunk,
+                                                       uint8_t *scratch, uint32_t *out) {
+    __shared__ uint32_t ring[kBlock / 16][64];
     const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint64_t i = t >> 4, lane = t & 15;
-    if (i >= n_items) return;  // whole rows
-    const RaggedItem it = items[i];
-    const uint2 w = reinterpret_cast<const uint2 *>(st)[16 * it.unit + lane];
-    uint32_t a = w.x, b = w.y;
-    if (it.j) xs1024_apply_poly(t32 + 32 * it.j, a, b);
-    reinterpret_cast<uint2 *>(scratch)[t] = make_uint2(a, b);
-    if (lane == 0)
-        reinterpret_cast<uint64_t *>(scratch + 128 * n_items)[i] =
-            reinterpret_cast<const uint64_t *>(st + 4 * S)[it.unit] + it.j * chunk;
-}
-
-// One 16-lane row per slot: the row runs its slot's chunks (consecutive
-// items slots[r] .. slots[r+1]-1) back to back in one flat loop, loading the
-// next chunk's start state from scratch when a chunk ends, and writes the
-// instance's final state after the instance's last chunk.  Control flow
-// depends on the row only, so the DPP moves of a step never see a lane of the
-// row switched off.
-__global__ __launch_bounds__(kBlock) void k_ragged_gen_xs(const RaggedItem *items, uint64_t n_items,
-                                                           const uint32_t *slots, uint32_t n_slots,
-                                                           const uint8_t *scratch, uint8_t *st, uint64_t S,
-                                                           uint32_t *out) {
-    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint64_t r = t >> 4, lane = t & 15;
+    const uint64_t r = t >> 4;
+    const uint32_t lane = static_cast<uint32_t>(t & 15), rl = threadIdx.x >> 4;
     if (r >= n_slots) return;  // whole rows
-    uint32_t q = slots[r];
     const uint32_t q_end = slots[r + 1];
-    if (q >= q_end) return;
-    const uint2 *starts = reinterpret_cast<const uint2 *>(scratch);
-    const uint64_t *counters = reinterpret_cast<const uint64_t *>(scratch + 128 * n_items);
     const uint32_t y0 = *reinterpret_cast<const uint32_t *>(st + 4 * S + 8 * (S / 32));
-    RaggedItem it = items[q];
-    uint2 w = starts[16ull * q + lane];
-    uint32_t a = w.x, b = w.y;
-    uint64_t n = counters[q];
-    uint32_t y = y0 + static_cast<uint32_t>(n) * kWeylC;
-    uint32_t *o = out + it.out + 2 * lane;
-    uint32_t k = 0;
-    // Loads of a chunk's data complete where they are issued (vmcnt(0)).
-    // Otherwise the wait lands at the loop head, and since stores share the
-    // counter, every step would wait for the previous step's stores.
-    __builtin_amdgcn_s_waitcnt(0x0F70);
+    const uint64_t out_word = reinterpret_cast<uintptr_t>(out) >> 2;  // out is 4-byte aligned
+    uint32_t *rg = ring[rl];
+    // The row's chunks run in one flat loop (not a loop per chunk): the rows
+    // of a wave switch chunks at different steps, and with a loop per chunk
+    // the wave would run every chunk index as long as its longest row.
+    uint32_t q = slots[r];
+    RaggedItem it;
+    uint32_t a, b, y, mis, len, kf, k;
+    uint64_t n;
+    int64_t nvals;
+    uint32_t *o;
+    auto begin = [&]() {  // load chunk q
+        it = items[q];
+        const uint2 w = reinterpret_cast<const uint2 *>(st)[16 * it.unit + lane];
+        a = w.x;
+        b = w.y;
+        n = reinterpret_cast<const uint64_t *>(st + 4 * S)[it.unit];
+        if (it.j) {
+            xs1024_apply_poly(t32 + 32 * it.j, a, b);
+            n += it.j * chunk;
+        }
+        y = y0 + static_cast<uint32_t>(n) * kWeylC;
+        mis = static_cast<uint32_t>(out_word + it.out) & 31;
+        o = out + (it.out - mis) + 2 * lane;  // lane's pair in line 0 (positions < mis unused)
+        len = it.len;
+        nvals = static_cast<int64_t>(it.nvals);
+        // lines 1 .. kf are whole: 32 k - mis >= 0 and 32 k + 32 - mis <= nvals
+        const int64_t kf_ = (nvals + mis - 32) / 32;
+        kf = kf_ <= 0 ? 0 : static_cast<uint32_t>(min(kf_, static_cast<int64_t>(len) - 1));
+        k = 0;
+        // Loads complete here: stores share the memory counter, so a wait
+        // left to the step loop would also wait for the stores.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+    };
+    begin();
     while (true) {
-        if (k == it.len) {
+        if (k == len) {
+            {  // line len: the last mis words of step len-1
+                const uint32_t x = 32 * len + 2 * lane - mis;
+                const uint32_t f0 = rg[x & 63], f1 = rg[(x + 1) & 63];
+                __builtin_amdgcn_wave_barrier();
+                const int64_t v0 = 32 * static_cast<int64_t>(len) + 2 * lane - mis;
+                if (v0 < nvals) o[0] = f0;
+                if (v0 + 1 < nvals) o[1] = f1;
+            }
             if (it.last) {
-                reinterpret_cast<uint2 *>(st)[16 * it.unit + lane] = make_uint2(a, b);
-                if (lane == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[it.unit] = n + it.len;
+                reinterpret_cast<uint2 *>(scratch)[16ull * q + lane] = make_uint2(a, b);
+                if (lane == 0) reinterpret_cast<uint64_t *>(scratch + 128 * n_items)[q] = n + len;
             }
             if (++q == q_end) break;
-            it = items[q];
-            w = starts[16ull * q + lane];
-            a = w.x;
-            b = w.y;
-            n = counters[q];
-            y = y0 + static_cast<uint32_t>(n) * kWeylC;
-            o = out + it.out + 2 * lane;
-            k = 0;
-            __builtin_amdgcn_s_waitcnt(0x0F70);
+            begin();
         }
+        // step k into the ring, then the lane's pair of line k
         xs1024_step(a, b);
         y += kWeylC;
         const uint32_t m = weyl_mix(y);
-        if (k + 1 < it.len) {
-            o[0] = a + m;
-            o[1] = b + m;
-        } else {  // the chunk's last step may be partial
-            const uint64_t v = 32ull * k + 2 * lane;
-            if (v < it.nvals) o[0] = a + m;
-            if (v + 1 < it.nvals) o[1] = b + m;
+        *reinterpret_cast<uint2 *>(rg + ((32 * k + 2 * lane) & 63)) = make_uint2(a + m, b + m);
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t x = 32 * k + 2 * lane - mis;
+        const uint32_t w0 = rg[x & 63], w1 = rg[(x + 1) & 63];
+        __builtin_amdgcn_wave_barrier();
+        if (k - 1 < kf) {  // 1 <= k <= kf: a whole line
+            __builtin_nontemporal_store(w0 | static_cast<uint64_t>(w1) << 32, reinterpret_cast<uint64_t *>(o));
+        } else {
+            const int64_t v0 = 32 * static_cast<int64_t>(k) + 2 * lane - mis;
+            if (v0 >= 0 && v0 < nvals) o[0] = w0;
+            if (v0 + 1 >= 0 && v0 + 1 < nvals) o[1] = w1;
         }
         o += 32;
         ++k;
     }
+}
+
+// Final states of the instances, from the items that end them.
+__global__ __launch_bounds__(kBlock) void k_ragged_commit_xs(const RaggedItem *items, uint64_t n_items,
+                                                              const uint8_t *scratch, uint8_t *st, uint64_t S) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t i = t >> 4, lane = t & 15;
+    if (i >= n_items || !items[i].last) return;
+    const uint64_t u = items[i].unit;
+    reinterpret_cast<uint2 *>(st)[16 * u + lane] = reinterpret_cast<const uint2 *>(scratch)[t];
+    if (lane == 0)
+        reinterpret_cast<uint64_t *>(st + 4 * S)[u] = reinterpret_cast<const uint64_t *>(scratch + 128 * n_items)[i];
 }
 
 unsigned blocks_for(uint64_t threads) { return static_cast<unsigned>((threads + kBlock - 1) / kBlock); }
@@ -424,10 +454,10 @@ hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const uint64_t C = r->step;
     if (g->kind == RNGX_XS1024W) {
-        hipLaunchKernelGGL(k_ragged_start_xs, dim3(blocks_for(16 * n)), dim3(kBlock), 0, st, r->d_items, n,
-                           g->d_state, g->S, r->d_scratch, r->d_t32, C);
-        hipLaunchKernelGGL(k_ragged_gen_xs, dim3(blocks_for(16ull * r->n_slots)), dim3(kBlock), 0, st, r->d_items,
-                           n, r->d_slots, r->n_slots, r->d_scratch, g->d_state, g->S, d_out);
+        hipLaunchKernelGGL(k_ragged_xs, dim3(blocks_for(16ull * r->n_slots)), dim3(kBlock), 0, st, r->d_items, n,
+                           r->d_slots, r->n_slots, g->d_state, g->S, r->d_t32, C, r->d_scratch, d_out);
+        hipLaunchKernelGGL(k_ragged_commit_xs, dim3(blocks_for(16 * n)), dim3(kBlock), 0, st, r->d_items, n,
+                           r->d_scratch, g->d_state, g->S);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_ragged_start_small, dim3(blocks_for(n)), dim3(kBlock), 0, st, g->kind, r->d_items, n,
