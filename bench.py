@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import math
 import json
 import os
 import sys
@@ -335,11 +336,15 @@ def main():
     parts = {}
     if not args.only_headline and args.parts == "all":
         parts["write_ceiling"] = bench_write_ceiling(out, max(5, args.steps // 2), 2)
+        ceiling = parts["write_ceiling"]["gbs"]
+        head["ceiling_frac"] = round(head["gbs"] / ceiling, 4)
         print(f"# write ceiling {parts['write_ceiling']}", file=sys.stderr, flush=True)
         for kind in KINDS:
             rec = {}
             for mode in ("u32", "f32", "consume"):
                 rec[mode] = bench_fill(rx, kind, mode, out, max(5, args.steps // 2), 2)
+                if mode != "consume":
+                    rec[mode]["ceiling_frac"] = round(rec[mode]["gbs"] / ceiling, 4)
             rec["skip_2p40_ms"] = bench_skip(rx, kind)
             parts[kind] = rec
             print(f"# {kind}: {rec}", file=sys.stderr, flush=True)
@@ -351,10 +356,13 @@ def main():
             ising[kind] = bench_ising(rx, kind, 4096, sweeps)
             print(f"# ising L=4096 {kind}: {ising[kind]}", file=sys.stderr, flush=True)
         parts["ising_L4096_beta0.4"] = ising
+        beta_c = math.log(1 + math.sqrt(2)) / 2
+        parts["ising_L4096_betac"] = {"xs1024w": bench_ising(rx, "xs1024w", 4096, args.ising_sweeps, beta_c)}
+        print(f"# ising L=4096 xs1024w beta_c: {parts['ising_L4096_betac']}", file=sys.stderr, flush=True)
         if not args.skip_batched:
             parts["ising_batch"] = bench_ising_batch(rx)
             print(f"# ising batch: {parts['ising_batch']}", file=sys.stderr, flush=True)
-            parts["ragged"] = [bench_ragged(rx, k) for k in ("xs1024w", "lcg32")]
+            parts["ragged"] = [bench_ragged(rx, k) for k in KINDS]
             print(f"# ragged: {parts['ragged']}", file=sys.stderr, flush=True)
         if not args.skip_serve:
             parts["serve"] = {"continuous": bench_serve(rx), "fifo_one_at_a_time": bench_serve(rx, slots=1, inflight=1)}
