@@ -67,6 +67,8 @@ def lib():
         L.orc_ising_energy.argtypes = [ctypes.c_uint32, vp]
         L.orc_ising_sweeps.restype = i32
         L.orc_ising_sweeps.argtypes = [ctypes.c_uint32, i32, ctypes.c_double, vp, vp, u64, vp]
+        L.orc_ising_sweeps_hits.restype = i32
+        L.orc_ising_sweeps_hits.argtypes = [ctypes.c_uint32, i32, ctypes.c_double, vp, vp, u64, ctypes.c_uint32, vp]
         _lib = L
     return _lib
 
@@ -154,11 +156,12 @@ def ising_energy(L: int, spins: np.ndarray) -> int:
 
 
 def ising_sweeps(L: int, kind: str, beta: float, st: np.ndarray, spins: np.ndarray, n_sweeps: int,
-                 trace: bool = True):
-    """Run n_sweeps checkerboard sweeps in place; returns the energy trace (int32) or None."""
+                 trace: bool = True, hits: int = 1):
+    """Run n_sweeps checkerboard sweeps in place, `hits` Metropolis updates
+    per visited site; returns the energy trace (int32) or None."""
     tr = np.zeros(max(n_sweeps, 1), dtype=np.int32) if trace else None
-    _check(lib().orc_ising_sweeps(L, _CODE[kind], beta, _ptr(st), _ptr(spins), n_sweeps,
-                                  _ptr(tr) if trace else None), "ising sweeps")
+    _check(lib().orc_ising_sweeps_hits(L, _CODE[kind], beta, _ptr(st), _ptr(spins), n_sweeps, hits,
+                                       _ptr(tr) if trace else None), "ising sweeps")
     return tr[:n_sweeps] if trace else None
 
 

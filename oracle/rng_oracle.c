@@ -578,28 +578,37 @@ int32_t orc_ising_energy(uint32_t L, const int8_t *sp)
     return (int32_t)e;
 }
 
-int orc_ising_sweeps(uint32_t L, int kind, double beta, void *st, int8_t *sp, uint64_t n_sweeps, int32_t *e_trace)
+/* Multi-hit form (k = hits >= 1): every visited site gets `hits` Metropolis
+ * updates in a row, its neighbours fixed, each drawing the stream's next
+ * output; the stream's first site takes draws 0 .. hits-1 of the pass, its
+ * second site draws hits .. 2*hits-1.  hits = 1 is the plain sweep above.
+ * (The paper's k counts updates of a tile per load of the generator states:
+ * k = 1 uses two numbers per state load and save, k = 100 two hundred.) */
+int orc_ising_sweeps_hits(uint32_t L, int kind, double beta, void *st, int8_t *sp, uint64_t n_sweeps,
+                          uint32_t hits, int32_t *e_trace)
 {
-    if (L < 16 || L % 16) return -1;
+    if (L < 16 || L % 16 || hits < 1) return -1;
     uint64_t S = (uint64_t)L * L / 4, spr = L / 4;
     if (!kind_ok(kind, S)) return -1;
     uint64_t T4 = orc_ising_threshold(beta, 4), T8 = orc_ising_threshold(beta, 8);
-    uint32_t *r = (uint32_t *)malloc(2 * S * sizeof(uint32_t));
+    uint32_t *r = (uint32_t *)malloc(2 * (uint64_t)hits * S * sizeof(uint32_t));
     if (!r) return -3;
     for (uint64_t t = 0; t < n_sweeps; t++) {
         for (int c = 0; c < 2; c++) {
-            orc_generate(kind, S, st, 0, S, 2, ORC_OUT_U32, r); /* r[h*S + s] */
+            orc_generate(kind, S, st, 0, S, 2 * (uint64_t)hits, ORC_OUT_U32, r); /* r[j*S + s] */
             for (uint64_t s = 0; s < S; s++) {
                 uint64_t y = s / spr, x0 = 4 * (s % spr);
                 for (int h = 0; h < 2; h++) {
                     uint64_t x = x0 + 2 * h + ((c + y) & 1);
-                    int si = sp[y * L + x];
                     int nb = sp[y * L + (x + 1) % L] + sp[y * L + (x + L - 1) % L] +
                              sp[((y + 1) % L) * L + x] + sp[((y + L - 1) % L) * L + x];
-                    int dE = 2 * si * nb;
-                    uint64_t u = r[h * S + s];
-                    int acc = (dE <= 0) || (dE == 4 && u < T4) || (dE == 8 && u < T8);
-                    if (acc) sp[y * L + x] = (int8_t)(-si);
+                    for (uint32_t i = 0; i < hits; i++) {
+                        int si = sp[y * L + x];
+                        int dE = 2 * si * nb;
+                        uint64_t u = r[((uint64_t)h * hits + i) * S + s];
+                        int acc = (dE <= 0) || (dE == 4 && u < T4) || (dE == 8 && u < T8);
+                        if (acc) sp[y * L + x] = (int8_t)(-si);
+                    }
                 }
             }
         }
@@ -607,4 +616,9 @@ int orc_ising_sweeps(uint32_t L, int kind, double beta, void *st, int8_t *sp, ui
     }
     free(r);
     return 0;
+}
+
+int orc_ising_sweeps(uint32_t L, int kind, double beta, void *st, int8_t *sp, uint64_t n_sweeps, int32_t *e_trace)
+{
+    return orc_ising_sweeps_hits(L, kind, beta, st, sp, n_sweeps, 1, e_trace);
 }

@@ -123,3 +123,70 @@ def test_colour_zero_goes_first(orc):
     st = orc.seed("lcg32", L * L // 4, 1)
     orc.ising_sweeps(L, "lcg32", 1e9, st, sp, 1, trace=False)
     assert np.all(sp == -1)
+
+
+# ---------------------------------------------------------------- multi-hit
+# k Metropolis updates per visited site, neighbours fixed (the paper's k of
+# updates per load of the generator states, read as single-site hits).
+
+@pytest.mark.parametrize("hits", [2, 3])
+def test_multihit_infinite_temperature(orc, hits):
+    # every hit is taken: a sweep flips every spin `hits` times
+    L, kind = 16, "xs1024w"
+    sp, st = orc.ising_create(L, kind, 5)
+    sp0 = sp.copy()
+    tr = orc.ising_sweeps(L, kind, 0.0, st, sp, 3, hits=hits)
+    assert np.array_equal(sp, sp0 if hits % 2 == 0 else -sp0)
+    assert np.all(tr == orc.ising_energy(L, sp0))
+
+
+@pytest.mark.parametrize("hits", [2, 5])
+def test_multihit_draw_count(orc, hits):
+    # after t sweeps every stream has produced 4 k t outputs
+    L, kind = 16, "lcg64"
+    sp, st = orc.ising_create(L, kind, 4)
+    st2 = st.copy()
+    orc.ising_sweeps(L, kind, 0.4, st, sp, 3, trace=False, hits=hits)
+    orc.step_n(kind, L * L // 4, st2, 12 * hits)
+    assert np.array_equal(st, st2)
+
+
+@pytest.mark.parametrize("hits", [1, 2, 3])
+def test_multihit_neel_zero_temperature(orc, hits):
+    # Neel state: a colour-0 site has dE = -8, flips on its first hit and then
+    # sees dE = +8, so it flips exactly once whatever k is; colour 1 then sees
+    # dE = +8.  One sweep ends all -1 for every k (a hit loop that kept the
+    # first hit's dE would flip colour 0 k times).
+    L = 16
+    y, x = np.mgrid[0:L, 0:L]
+    sp = np.where((x + y) % 2 == 0, 1, -1).astype(np.int8).ravel()
+    st = orc.seed("mwc", L * L // 4, 1)
+    orc.ising_sweeps(L, "mwc", 1e9, st, sp, 1, trace=False, hits=hits)
+    assert np.all(sp == -1)
+
+
+def test_multihit_zero_temperature_ignores_the_generator(orc):
+    L = 32
+    for hits in (2, 3):
+        ref = None
+        for kind in orc.KINDS:
+            sp, st = orc.ising_create(L, kind, 9)
+            tr = orc.ising_sweeps(L, kind, 1e9, st, sp, 6, hits=hits)
+            assert np.all(np.diff(tr) <= 0)
+            if ref is None:
+                ref = sp.copy()
+            assert np.array_equal(sp, ref), (kind, hits)
+
+
+@pytest.mark.parametrize("beta", [0.4, ex.BETA_C])
+def test_multihit_statistics_match_exact_L16(orc, beta):
+    # every hit is a Metropolis step with the environment fixed, so the
+    # equilibrium is unchanged
+    L, n_eq, n_meas, kind = 16, 2000, 40000, "xs1024w"
+    sp, st = orc.ising_create(L, kind, 1)
+    orc.ising_sweeps(L, kind, beta, st, sp, n_eq, trace=False, hits=2)
+    tr = orc.ising_sweeps(L, kind, beta, st, sp, n_meas, hits=2)
+    e, se, c, sc = isingstats.estimates(tr, L * L, beta)
+    ee, ce = _exact(L, beta)
+    assert abs(e - ee) < 4 * se, (e, se, ee)
+    assert abs(c - ce) < 4 * sc, (c, sc, ce)
