@@ -250,6 +250,17 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
 rngx_status ising_sweep(rngx_ising lat, double beta, uint64_t n_sweeps, int32_t *d_energy_trace,
                         void *stream);
 
+/* Multi-hit sweeps (Sec. 2 and the Philox discussion: k updates per load of
+ * the generator states, here read as k Metropolis updates of each visited
+ * site in a row, its neighbours fixed).  In pass c stream s gives site
+ * x0 + ((c+y)&1) its next `hits` outputs, one per update, and site
+ * x0 + 2 + ((c+y)&1) the `hits` after those; each update flips the site
+ * under the rule above, so a sweep draws 4*hits outputs per stream.
+ * hits = 1 is ising_sweep.  Errors as ising_sweep, and RNGX_E_INVALID
+ * unless 1 <= hits <= 2^20. */
+rngx_status ising_sweep_hits(rngx_ising lat, double beta, uint64_t n_sweeps, uint32_t hits,
+                             int32_t *d_energy_trace, void *stream);
+
 /* How the lattice is swept: *strips receives the number of workgroups that
  * hold the lattice on chip as horizontal strips for a whole ising_sweep call
  * (1 = a single workgroup), or 0 when every colour pass is a separate launch

@@ -47,6 +47,7 @@ SIGNATURES = {
     "rng_set_state": (_i32, [_vp, _vp, _sz, _vp]),
     "ising_create": (_i32, [ctypes.c_uint32, _i32, _u64, ctypes.POINTER(_vp)]),
     "ising_sweep": (_i32, [_vp, ctypes.c_double, _u64, _vp, _vp]),
+    "ising_sweep_hits": (_i32, [_vp, ctypes.c_double, _u64, ctypes.c_uint32, _vp, _vp]),
     "ising_info": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_uint32)]),
     "ising_spins": (_i32, [_vp, ctypes.POINTER(_vp)]),
     "ising_get_spins": (_i32, [_vp, _vp, _vp]),
@@ -299,6 +300,12 @@ def ising_create(L: int, kind, seed: int) -> Ising:
 
 def ising_sweep(lat: Ising, beta: float, n_sweeps: int, energy_trace=None, stream=None):
     _check(load().ising_sweep(lat.handle, beta, n_sweeps, _dptr(energy_trace, n_sweeps, 4), _stream(stream)))
+
+
+def ising_sweep_hits(lat: Ising, beta: float, n_sweeps: int, hits: int, energy_trace=None, stream=None):
+    """Multi-hit sweeps: `hits` Metropolis updates per visited site."""
+    _check(load().ising_sweep_hits(lat.handle, beta, n_sweeps, hits, _dptr(energy_trace, n_sweeps, 4),
+                                   _stream(stream)))
 
 
 def ising_info(lat: Ising) -> dict:

@@ -513,17 +513,23 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
     return RNGX_OK;
 }
 
-rngx_status ising_sweep(rngx_ising h, double beta, uint64_t n_sweeps, int32_t *d_trace, void *stream) {
+rngx_status ising_sweep_hits(rngx_ising h, double beta, uint64_t n_sweeps, uint32_t hits, int32_t *d_trace,
+                             void *stream) {
     Ising *lat;
     if (rngx_status s = check_ising(h, &lat)) return s;
     if (!std::isfinite(beta) || beta < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");
+    if (hits < 1 || hits > (1u << 20)) return fail(RNGX_E_INVALID, "hits must be in 1 .. 2^20");
     if (d_trace && reinterpret_cast<uintptr_t>(d_trace) % 4) return fail(RNGX_E_ALIGN, "trace must be 4-byte aligned");
     if (n_sweeps == 0) { clear_error(); return RNGX_OK; }
     DeviceScope ds(lat->device);
-    hipError_t e = launch_ising(lat, beta, n_sweeps, d_trace, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_ising(lat, beta, n_sweeps, d_trace, static_cast<hipStream_t>(stream), hits);
     if (e != hipSuccess) return hip_fail(e, "Ising kernel launch");
     clear_error();
     return RNGX_OK;
+}
+
+rngx_status ising_sweep(rngx_ising h, double beta, uint64_t n_sweeps, int32_t *d_trace, void *stream) {
+    return ising_sweep_hits(h, beta, n_sweeps, 1, d_trace, stream);
 }
 
 namespace {

@@ -79,6 +79,16 @@ __device__ __forceinline__ int metropolis(uint64_t &w, uint64_t m, int i, uint32
     return acc ? e : -e;
 }
 
+// One Metropolis update of a site with mi (0..4) differing neighbours and
+// draw r (multi-hit updates: the site's neighbours stay fixed between its
+// hits); a taken flip turns mi into 4 - mi and toggles `flip`.
+__device__ __forceinline__ void hit_mem(uint32_t &mi, uint32_t &flip, uint32_t r, uint64_t T4, uint64_t T8) {
+    const uint64_t thr = mi == 1 ? T4 : T8;
+    const bool acc = (mi >= 2) | (static_cast<uint64_t>(r) < thr);
+    mi = acc ? 4 - mi : mi;
+    flip ^= acc ? 1u : 0u;
+}
+
 // ---------------------------------------------------------------- units
 // A unit is what one thread updates with one set of draws: a stream (4
 // sites) for the small-state kinds, a lane pair of an XS1024W instance (8
@@ -91,6 +101,11 @@ struct SmallUnit {
     __device__ void load(const uint8_t *st, uint64_t S, uint64_t u) { g.load(st, S, u); }
     __device__ void store(uint8_t *st, uint64_t S, uint64_t u, uint64_t) const { g.store(st, S, u); }
     __device__ void draw(uint32_t (&r)[2]) { r[0] = g.next(); r[1] = g.next(); }
+    // n draws in order, each handed to f (multi-hit updates)
+    template <class F>
+    __device__ void draws(uint32_t n, F &&f) {
+        for (uint32_t i = 0; i < n; ++i) f(g.next());
+    }
 };
 
 // Philox with only key and position held: the two draws of a pass come from
@@ -115,6 +130,16 @@ struct PhiloxUnit {
         if (j == 3) philox_block(k0, k1, (pos >> 2) + 1, b0, b1, b2, b3);
         r[1] = j == 0 ? b1 : j == 1 ? b2 : j == 2 ? b3 : b0;
         pos += 2;
+    }
+    template <class F>
+    __device__ void draws(uint32_t n, F &&f) {
+        uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t j = static_cast<uint32_t>(pos) & 3;
+            if (i == 0 || j == 0) philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);
+            f(j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3);
+            ++pos;
+        }
     }
 };
 
@@ -143,6 +168,14 @@ struct XsUnit {
         y += kWeylC;
         m = weyl_mix(y);
         r[1] = a + m; r[3] = b + m;
+    }
+    // one instance step: the next draw of stream 2u (ra) and of 2u+1 (rb)
+    __device__ void pair(uint32_t &ra, uint32_t &rb) {
+        xs1024_step(a, b);
+        y += kWeylC;
+        const uint32_t m = weyl_mix(y);
+        ra = a + m;
+        rb = b + m;
     }
 };
 
@@ -185,6 +218,7 @@ struct StripArgs {
     uint64_t *halo;             // 2 slots x nwg x 2 rows x L/4 tagged words
     uint32_t epoch0;            // pass tags of this call are epoch0 + 1, epoch0 + 2, ...
     uint32_t *err;
+    uint32_t hits;              // Metropolis updates per visited site (multi-hit kernels)
 };
 
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -298,6 +332,15 @@ __device__ __forceinline__ uint32_t decide(uint32_t m2, uint32_t sh, uint32_t f,
     return acc ? f : 0u;
 }
 
+// One update of a multi-hit site with doubled count d and draw r; a taken
+// flip turns d into 8 - d and toggles `flip`.
+__device__ __forceinline__ void hit_lds(uint32_t &d, uint32_t &flip, uint32_t r, const Accept &A) {
+    const bool two = d == 2;
+    const bool acc = (d >= A.lo) | (two & (r < A.t4)) | (!two & (r < A.t8));
+    d = acc ? 8 - d : d;
+    flip ^= acc ? 1u : 0u;
+}
+
 // Unit k of the strip starts at LDS offset `off` (its row yl+1); bit 27:
 // unit in the strip's top row, bit 28: in its bottom row, bit 29: run starts
 // the row, bit 30: run ends the row, bit 31: (row0+yl) odd, i.e. its
@@ -319,15 +362,58 @@ __device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint32_t 
 // Colour-c update of the unit at `pl` (place word, made opaque per pass);
 // returns its new spins.  The rows above and below are read at off - P +
 // up_add and off + P + dn_add (non-zero only to reach halo buffer 1).  The
-// draws go to the colour-c bytes in increasing order.
-template <class Unit, bool E>
+// draws go to the colour-c bytes in increasing order.  MH: `hits` updates
+// per site in a row, each stream's first site taking its first `hits`
+// draws of the pass (XS1024W: instance steps 1..hits serve the first site
+// of both streams of the lane pair, steps hits+1..2 hits the second).
+template <class Unit, bool E, bool MH>
 __device__ __forceinline__ uint64_t update_unit(uint8_t *lds, uint32_t pl, uint32_t P, uint32_t up_add, uint32_t dn_add,
-                                                int c, Unit &u, const Accept &A, uint32_t &esum) {
+                                                int c, Unit &u, const Accept &A, uint32_t &esum, uint32_t hits) {
     constexpr int NB = Unit::kNB;
     const uint32_t off = pl & kOffMask;
     const uint32_t sh0 = ((pl >> 31) ^ static_cast<uint32_t>(c)) << 3;  // bit offset of the first colour-c byte
     const uint32_t f0 = 0xFEu << sh0, f1 = f0 << 16;                     // flip masks (+1 <-> -1)
     const uint32_t *l32 = reinterpret_cast<const uint32_t *>(lds + off);
+    if constexpr (MH) {
+        if constexpr (NB == 4) {
+            const uint32_t w = l32[0];
+            const uint32_t m2 = mismatch2(w, l32[-1], l32[1], *reinterpret_cast<const uint32_t *>(lds + off - P + up_add),
+                                          *reinterpret_cast<const uint32_t *>(lds + off + P + dn_add));
+            uint32_t d0 = __builtin_amdgcn_ubfe(m2, sh0, 8), d1 = __builtin_amdgcn_ubfe(m2, sh0 + 16, 8);
+            uint32_t x0 = 0, x1 = 0;
+            u.draws(hits, [&](uint32_t r) { hit_lds(d0, x0, r, A); });
+            u.draws(hits, [&](uint32_t r) { hit_lds(d1, x1, r, A); });
+            if constexpr (E) esum += d0 + d1;
+            const uint32_t nw = w ^ (x0 ? f0 : 0u) ^ (x1 ? f1 : 0u);
+            *reinterpret_cast<uint32_t *>(lds + off) = nw;
+            return nw;
+        } else {
+            const uint2 w = *reinterpret_cast<const uint2 *>(lds + off);
+            const uint2 up = *reinterpret_cast<const uint2 *>(lds + off - P + up_add);
+            const uint2 dn = *reinterpret_cast<const uint2 *>(lds + off + P + dn_add);
+            const uint32_t m2a = mismatch2(w.x, l32[-1], w.y, up.x, dn.x);
+            const uint32_t m2b = mismatch2(w.y, w.x, l32[2], up.y, dn.y);
+            uint32_t d0 = __builtin_amdgcn_ubfe(m2a, sh0, 8), d1 = __builtin_amdgcn_ubfe(m2a, sh0 + 16, 8);
+            uint32_t d2 = __builtin_amdgcn_ubfe(m2b, sh0, 8), d3 = __builtin_amdgcn_ubfe(m2b, sh0 + 16, 8);
+            uint32_t x0 = 0, x1 = 0, x2 = 0, x3 = 0;
+            for (uint32_t i = 0; i < hits; ++i) {
+                uint32_t ra, rb;
+                u.pair(ra, rb);
+                hit_lds(d0, x0, ra, A);
+                hit_lds(d2, x2, rb, A);
+            }
+            for (uint32_t i = 0; i < hits; ++i) {
+                uint32_t ra, rb;
+                u.pair(ra, rb);
+                hit_lds(d1, x1, ra, A);
+                hit_lds(d3, x3, rb, A);
+            }
+            if constexpr (E) esum += d0 + d1 + d2 + d3;
+            const uint2 nw = make_uint2(w.x ^ (x0 ? f0 : 0u) ^ (x1 ? f1 : 0u), w.y ^ (x2 ? f0 : 0u) ^ (x3 ? f1 : 0u));
+            *reinterpret_cast<uint2 *>(lds + off) = nw;
+            return (static_cast<uint64_t>(nw.y) << 32) | nw.x;
+        }
+    }
     uint32_t rr[NB / 2];
     u.draw(rr);
     if constexpr (NB == 4) {
@@ -413,7 +499,7 @@ __device__ __forceinline__ void edge_ghosts(uint8_t *run, uint32_t pl, uint32_t 
 template <class Unit, int SPT>
 __host__ __device__ constexpr bool place_in_lds() { return SPT * (sizeof(Unit) / 4 + 1) >= 40; }
 
-template <class Unit, int SPT, bool EARLY, bool PLDS>
+template <class Unit, int SPT, bool EARLY, bool PLDS, bool MH = false>
 __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8_t *lds) {
     constexpr int NB = Unit::kNB;
     const uint32_t L = a.L, R = a.R, nwg = a.nwg, t = threadIdx.x, nt = blockDim.x;
@@ -510,7 +596,8 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
                 if constexpr (PLDS) pl = place_lds[i * nt + t];
                 else pl = place[i] + zero;
                 const bool top = bslot && ((pl >> 27) & 1), bot = bslot && ((pl >> 28) & 1);
-                const uint64_t nw = update_unit<Unit, E>(lds, pl, P, top ? up_add : 0u, bot ? dn_add : 0u, c, u[i], A, esum);
+                const uint64_t nw = update_unit<Unit, E, MH>(lds, pl, P, top ? up_add : 0u, bot ? dn_add : 0u, c, u[i], A, esum,
+                                                                   a.hits);
                 const uint32_t off = pl & kOffMask;
                 const uint32_t yrow = top ? 1 : bot ? R : 0;   // only used for boundary units
                 const uint32_t x0 = off - kPad - yrow * P;
@@ -572,7 +659,7 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
         const uint32_t k = t + i * nt;
-        if (k < a.units) u[i].store(a.st, a.S, ubase + k, 4 * a.n_sweeps);
+        if (k < a.units) u[i].store(a.st, a.S, ubase + k, 4 * a.n_sweeps * (MH ? a.hits : 1));
     }
 }
 
@@ -582,7 +669,7 @@ __host__ __device__ constexpr bool early_slots(uint32_t upr, uint32_t units, uin
     return SPT > 2 && upr <= nt && units - upr >= (SPT - 1) * nt;
 }
 
-template <class Unit, int SPT, bool EARLY>
+template <class Unit, int SPT, bool EARLY, bool MH>
 __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     // Blocks b, b+8, b+16, ... share an XCD: give them consecutive strips so
@@ -593,7 +680,7 @@ __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
         if (threadIdx.x == 0) __hip_atomic_fetch_or(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    strip_body<Unit, SPT, EARLY, place_in_lds<Unit, SPT>()>(a, r, lds);
+    strip_body<Unit, SPT, EARLY, place_in_lds<Unit, SPT>(), MH>(a, r, lds);
 }
 
 // ---------------------------------------------------------------- per pass
@@ -605,14 +692,15 @@ struct PassArgs {
     int c;
     uint64_t T4, T8;
     int32_t *partial;  // one per block, or null
+    uint32_t hits;     // multi-hit kernels only
 };
 
 // Update unit k of colour c with spins and state in global memory; returns
 // the sum of s*h over the updated sites.  A unit reads only other-colour
 // bytes of its neighbour runs, which no thread writes during the pass.
-template <class Unit>
+template <class Unit, bool MH = false>
 __device__ __forceinline__ int unit_in_memory(uint8_t *sp, uint8_t *st, uint64_t S, uint32_t L, uint64_t k, int c,
-                                              uint64_t T4, uint64_t T8) {
+                                              uint64_t T4, uint64_t T8, uint32_t hits = 1) {
     constexpr int NB = Unit::kNB;
     const uint32_t upr = L / NB;
     const uint64_t y = k / upr;
@@ -627,22 +715,56 @@ __device__ __forceinline__ int unit_in_memory(uint8_t *sp, uint8_t *st, uint64_t
     const int p = static_cast<int>((c + y) & 1);
     Unit u;
     u.load(st, S, k);
-    uint32_t rr[NB / 2];
-    u.draw(rr);
-    u.store(st, S, k, 2);
     int sh = 0;
+    if constexpr (MH) {
+        // byte p + 2h is site h; the same draw order as the on-chip update
+        uint32_t mi[NB / 2], fl[NB / 2];
 #pragma unroll
-    for (int h = 0; h < NB / 2; ++h) sh += metropolis(w, m, p + 2 * h, rr[h], T4, T8);
+        for (int h = 0; h < NB / 2; ++h) {
+            mi[h] = static_cast<uint32_t>(m >> (8 * (p + 2 * h))) & 0xFFu;
+            fl[h] = 0;
+        }
+        if constexpr (NB == 4) {
+            u.draws(hits, [&](uint32_t r) { hit_mem(mi[0], fl[0], r, T4, T8); });
+            u.draws(hits, [&](uint32_t r) { hit_mem(mi[1], fl[1], r, T4, T8); });
+        } else {
+            for (uint32_t i = 0; i < hits; ++i) {
+                uint32_t ra, rb;
+                u.pair(ra, rb);
+                hit_mem(mi[0], fl[0], ra, T4, T8);
+                hit_mem(mi[2], fl[2], rb, T4, T8);
+            }
+            for (uint32_t i = 0; i < hits; ++i) {
+                uint32_t ra, rb;
+                u.pair(ra, rb);
+                hit_mem(mi[1], fl[1], ra, T4, T8);
+                hit_mem(mi[3], fl[3], rb, T4, T8);
+            }
+        }
+        u.store(st, S, k, 2 * hits);
+#pragma unroll
+        for (int h = 0; h < NB / 2; ++h) {
+            w ^= static_cast<uint64_t>(fl[h] * 0xFEu) << (8 * (p + 2 * h));
+            sh += 4 - 2 * static_cast<int>(mi[h]);
+        }
+    } else {
+        uint32_t rr[NB / 2];
+        u.draw(rr);
+        u.store(st, S, k, 2);
+#pragma unroll
+        for (int h = 0; h < NB / 2; ++h) sh += metropolis(w, m, p + 2 * h, rr[h], T4, T8);
+    }
     lds_put<NB>(sp + row + x0, w);
     return sh;
 }
 
-template <class Unit>
+template <class Unit, bool MH>
 __global__ __launch_bounds__(kBlock) void k_ising_pass(PassArgs a, uint64_t n_units) {
     const uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     int sh = 0;
     if (k < n_units)  // XS1024W: n_units is a multiple of 16, so rows stay whole
-        sh = unit_in_memory<Unit>(reinterpret_cast<uint8_t *>(a.spins), a.st, a.S, a.L, k, a.c, a.T4, a.T8);
+        sh = unit_in_memory<Unit, MH>(reinterpret_cast<uint8_t *>(a.spins), a.st, a.S, a.L, k, a.c, a.T4, a.T8,
+                                      a.hits);
     if (a.partial) {
         __shared__ int red[kBlock / 64];
         const int tot = block_sum(sh, red);
@@ -708,7 +830,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc
             continue;
         }
         const StripArgs a{d.spins, d.st, d.S, d.L, d.R, d.nwg, d.units, d.T4, d.T8, d.n_sweeps, d.trace,
-                          d.halo, 0, d.err};
+                          d.halo, 0, d.err, 1};
         if (early_slots<spt>(d.L / NB, d.units, blockDim.x)) strip_body<Unit, spt, true, false>(a, item.y, lds);
         else strip_body<Unit, spt, false, false>(a, item.y, lds);
     }
@@ -741,17 +863,17 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const int32_t *partial
 constexpr uint32_t kLdsMax = 160 * 1024;
 constexpr uint32_t kMaxThreads = 1024;
 
-template <class Unit, int SPT, bool EARLY>
-const void *strip_kernel() { return reinterpret_cast<const void *>(&k_ising_strip<Unit, SPT, EARLY>); }
+template <class Unit, int SPT, bool EARLY, bool MH>
+const void *strip_kernel() { return reinterpret_cast<const void *>(&k_ising_strip<Unit, SPT, EARLY, MH>); }
 
-template <class Unit>
+template <class Unit, bool MH = false>
 const void *strip_kernel_for(int spt, bool early) {
     switch (spt) {
-    case 1: return strip_kernel<Unit, 1, false>();
-    case 2: return strip_kernel<Unit, 2, false>();
-    case 4: return early ? strip_kernel<Unit, 4, true>() : strip_kernel<Unit, 4, false>();
-    case 8: return early ? strip_kernel<Unit, 8, true>() : strip_kernel<Unit, 8, false>();
-    case 16: return early ? strip_kernel<Unit, 16, true>() : strip_kernel<Unit, 16, false>();
+    case 1: return strip_kernel<Unit, 1, false, MH>();
+    case 2: return strip_kernel<Unit, 2, false, MH>();
+    case 4: return early ? strip_kernel<Unit, 4, true, MH>() : strip_kernel<Unit, 4, false, MH>();
+    case 8: return early ? strip_kernel<Unit, 8, true, MH>() : strip_kernel<Unit, 8, false, MH>();
+    case 16: return early ? strip_kernel<Unit, 16, true, MH>() : strip_kernel<Unit, 16, false, MH>();
     }
     return nullptr;
 }
@@ -778,17 +900,17 @@ inline bool plan_early(int spt, uint32_t upr, uint32_t units, uint32_t nt) {
     return false;
 }
 
-template <class Unit>
-hipError_t run_passes(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
+template <class Unit, bool MH>
+hipError_t run_passes(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st, uint32_t hits) {
     constexpr int NB = Unit::kNB;
     const uint64_t L = lat->L, n_units = L * L / NB;
     const unsigned blocks = static_cast<unsigned>((n_units + kBlock - 1) / kBlock);
-    PassArgs pa{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, 0, T4, T8, nullptr};
+    PassArgs pa{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, 0, T4, T8, nullptr, hits};
     for (uint64_t t = 0; t < n; ++t) {
         for (int c = 0; c < 2; ++c) {
             pa.c = c;
             pa.partial = (c == 1 && tr) ? lat->d_partial : nullptr;
-            hipLaunchKernelGGL(k_ising_pass<Unit>, dim3(blocks), dim3(kBlock), 0, st, pa, n_units);
+            hipLaunchKernelGGL((k_ising_pass<Unit, MH>), dim3(blocks), dim3(kBlock), 0, st, pa, n_units);
         }
         if (tr) hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, st, lat->d_partial,
                                    static_cast<uint64_t>(blocks), tr + t);
@@ -796,9 +918,21 @@ hipError_t run_passes(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t 
     return hipGetLastError();
 }
 
-template <class Unit>
-hipError_t run_strips(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
+template <class Unit, bool MH>
+hipError_t run_strips(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st, uint32_t hits) {
     const IsingPlan &pl = lat->plan;
+    const void *fn = strip_kernel_for<Unit, MH>(pl.spt, pl.early);
+    if (MH) {
+        // The plan was sized with the single-hit kernel: give this one the
+        // same LDS and check that every strip can still be resident.
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(pl.lds));
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, static_cast<int>(pl.threads), pl.lds) != hipSuccess ||
+            static_cast<uint64_t>(occ) * lat->gen->n_cu < pl.nwg) {
+            (void)hipGetLastError();
+            return run_passes<Unit, MH>(lat, T4, T8, n, tr, st, hits);
+        }
+    }
     if (tr && pl.nwg > 1) {
         hipLaunchKernelGGL(k_zero_u32, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                            reinterpret_cast<uint32_t *>(tr), n);
@@ -810,9 +944,8 @@ hipError_t run_strips(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t 
         lat->epoch = 0;
     }
     StripArgs a{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, pl.R, pl.nwg, pl.units, T4, T8, n,
-                tr, lat->d_halo, static_cast<uint32_t>(lat->epoch), lat->d_err};
+                tr, lat->d_halo, static_cast<uint32_t>(lat->epoch), lat->d_err, hits};
     void *args[] = {&a};
-    const void *fn = strip_kernel_for<Unit>(pl.spt, pl.early);
     hipError_t e;
     if (pl.nwg == 1)
         e = hipLaunchKernel(fn, dim3(1), dim3(pl.threads), args, pl.lds, st);
@@ -875,9 +1008,13 @@ bool plan_strips(uint32_t L, int max_spt, int n_cu, IsingPlan *out) {
 }
 
 template <class Unit>
-hipError_t run(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st) {
-    if (lat->plan.strips) return run_strips<Unit>(lat, T4, T8, n, tr, st);
-    return run_passes<Unit>(lat, T4, T8, n, tr, st);
+hipError_t run(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st, uint32_t hits) {
+    if (hits == 1) {
+        if (lat->plan.strips) return run_strips<Unit, false>(lat, T4, T8, n, tr, st, 1);
+        return run_passes<Unit, false>(lat, T4, T8, n, tr, st, 1);
+    }
+    if (lat->plan.strips) return run_strips<Unit, true>(lat, T4, T8, n, tr, st, hits);
+    return run_passes<Unit, true>(lat, T4, T8, n, tr, st, hits);
 }
 
 constexpr uint32_t kBatchLdsCap = 80 * 1024;  // keeps two batch workgroups per CU
@@ -1053,17 +1190,18 @@ hipError_t launch_zero(uint32_t *p, uint64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st) {
+hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st,
+                        uint32_t hits) {
     // Thresholds floor(exp(-beta dE) 2^32) in IEEE double on the host.
     const uint64_t T4 = static_cast<uint64_t>(std::floor(std::exp(-4.0 * beta) * 4294967296.0));
     const uint64_t T8 = static_cast<uint64_t>(std::floor(std::exp(-8.0 * beta) * 4294967296.0));
     switch (lat->gen->kind) {
-    case RNGX_LCG32: return run<SmallUnit<Lcg32>>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_LCG64: return run<SmallUnit<Lcg64>>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_MWC: return run<SmallUnit<Mwc>>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_XORWOW: return run<SmallUnit<Xorwow>>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_PHILOX4X32_10: return run<PhiloxUnit>(lat, T4, T8, n_sweeps, d_trace, st);
-    case RNGX_XS1024W: return run<XsUnit>(lat, T4, T8, n_sweeps, d_trace, st);
+    case RNGX_LCG32: return run<SmallUnit<Lcg32>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_LCG64: return run<SmallUnit<Lcg64>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_MWC: return run<SmallUnit<Mwc>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_XORWOW: return run<SmallUnit<Xorwow>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_PHILOX4X32_10: return run<PhiloxUnit>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_XS1024W: return run<XsUnit>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     }
     return hipErrorInvalidValue;
 }

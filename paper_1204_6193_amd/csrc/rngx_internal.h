@@ -135,7 +135,8 @@ hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
 void jump_table(rngx_kind kind, uint64_t step, uint64_t count, std::vector<uint64_t> *u64s,
                 std::vector<uint32_t> *u32s);
 hipError_t launch_hot_start(Ising *lat, uint64_t seed, hipStream_t st);
-hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st);
+hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st,
+                        uint32_t hits = 1);  // hits: Metropolis updates per visited site
 hipError_t launch_zero(uint32_t *p, uint64_t n, hipStream_t st);
 bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out);
 int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int max);  // strip candidates

@@ -313,3 +313,64 @@ def test_batch_argument_errors(rngx):
     b = rngx.ising_batch_create([x], [0.4], [1])
     assert rngx.load().ising_destroy(x.handle) == -7  # held by the batch
     b.destroy()
+
+
+# ---------------------------------------------------------------- multi-hit
+def _run_hits(rx, orc, L, kind, beta, sweeps, hits, plan=None, chunks=(None,)):
+    lat = rx.ising_create(L, kind, 3)
+    if plan is not None:
+        rx.ising_set_plan(lat, plan)
+    sp, st = orc.ising_create(L, kind, 3)
+    for n in chunks:
+        n = sweeps if n is None else n
+        tr = torch.zeros(n, dtype=torch.int32, device="cuda")
+        rx.ising_sweep_hits(lat, beta, n, hits, tr)
+        want_tr = orc.ising_sweeps(L, kind, beta, st, sp, n, hits=hits)
+        assert np.array_equal(tr.cpu().numpy(), want_tr), (L, kind, beta, hits)
+        assert np.array_equal(rx.ising_get_spins(lat).ravel(), sp), (L, kind, beta, hits)
+        assert np.array_equal(rx.rng_get_state(rx.ising_rng(lat)), st), (L, kind, beta, hits)
+    return lat
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("hits", [2, 3])
+def test_multihit_parity(rngx, orc, kind, hits):
+    """One workgroup (L = 32) and several strips (L = 512), bit-exact."""
+    print(f"case ising multihit {kind} hits={hits}", flush=True)
+    for beta in (0.4, ex.BETA_C):
+        _run_hits(rngx, orc, 32, kind, beta, 12, hits, chunks=(5, 7))
+    lat = _run_hits(rngx, orc, 512, kind, 0.4, 3, hits)
+    assert rngx.ising_info(lat)["strips"] > 1
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_multihit_per_pass_path_and_many_hits(rngx, orc, kind):
+    """The per-pass kernels (plan 0) with 2 hits, and 100 hits on chip."""
+    print(f"case ising multihit passes {kind}", flush=True)
+    _run_hits(rngx, orc, 64, kind, 0.4, 3, 2, plan=0)
+    _run_hits(rngx, orc, 32, kind, ex.BETA_C, 2, 100)
+
+
+def test_multihit_extremes_and_errors(rngx, orc):
+    for beta in (0.0, 1e9):
+        _run_hits(rngx, orc, 48, "lcg32", beta, 3, 2)
+        _run_hits(rngx, orc, 48, "xs1024w", beta, 3, 3)
+    lat = rngx.ising_create(32, "lcg32", 1)
+    for bad in (0, (1 << 20) + 1):
+        with pytest.raises(rngx.RngxError):
+            rngx.ising_sweep_hits(lat, 0.4, 1, bad)
+
+
+def test_multihit_statistics(rngx):
+    """k = 2 leaves the equilibrium unchanged: XS1024W at L = 32, beta_c."""
+    L, beta, n_eq, n_meas = 32, ex.BETA_C, 50_000, 500_000
+    lat = rngx.ising_create(L, "xs1024w", 7)
+    rngx.ising_sweep_hits(lat, beta, n_eq, 2)
+    tr = torch.zeros(n_meas, dtype=torch.int32, device="cuda")
+    rngx.ising_sweep_hits(lat, beta, n_meas, 2, tr)
+    e, se, c, sc = isingstats.estimates(tr.cpu().numpy(), L * L, beta)
+    ee, ce = _exact(L, beta)
+    print(f"stat multihit k=2 xs1024w L={L} e={e:.6f}+-{se:.6f} z={(e - ee) / se:+.2f} "
+          f"C={c:.5f}+-{sc:.5f} z={(c - ce) / sc:+.2f}", flush=True)
+    assert abs(e - ee) < 3 * se
+    assert abs(c - ce) < 3 * sc
