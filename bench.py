@@ -104,20 +104,26 @@ def bench_skip(rx, kind, reps=5):
     return round(sum(durs) / len(durs), 4)
 
 
-def bench_ising(rx, kind, L, sweeps, beta=0.4):
+def bench_ising(rx, kind, L, sweeps, beta=0.4, hits=1):
     """One call of `sweeps` sweeps (energy trace on), after the plan
-    autotuner (untimed; it restores spins and streams) and 5 warm-up sweeps."""
+    autotuner (untimed; it restores spins and streams) and 5 warm-up sweeps.
+    With hits > 1 every visited site gets `hits` updates; flips_per_ns counts
+    attempted updates."""
     import torch
     lat = rx.ising_create(L, kind, 1)
     plans = rx.ising_plans(lat)
     tune_ms = rx.ising_autotune(lat, beta, 20, reps=1)
-    rx.ising_sweep(lat, beta, 5)
+    rx.ising_sweep_hits(lat, beta, 5, hits)
     tr = torch.zeros(sweeps, dtype=torch.int32, device="cuda")
-    durs, _ = time_launches(lambda: rx.ising_sweep(lat, beta, sweeps, tr), 1, 0)
+    durs, _ = time_launches(lambda: rx.ising_sweep_hits(lat, beta, sweeps, hits, tr), 1, 0)
     ms = durs[0]
-    return {"sweeps": sweeps, "ms": round(ms, 3), "flips_per_ns": round(L * L * sweeps / (ms * 1e6), 2),
-            "strips": rx.ising_info(lat)["strips"],
-            "autotune": {"plans": plans, "ms_per_20_sweeps": [round(m, 3) for m in tune_ms]}}
+    rec = {"sweeps": sweeps, "ms": round(ms, 3), "flips_per_ns": round(L * L * sweeps * hits / (ms * 1e6), 2),
+           "strips": rx.ising_info(lat)["strips"],
+           "autotune": {"plans": plans, "ms_per_20_sweeps": [round(m, 3) for m in tune_ms]}}
+    if hits > 1:
+        rec["hits"] = hits
+        rec["ns_per_attempted_flip"] = round(ms * 1e6 / (L * L * sweeps * hits), 5)
+    return rec
 
 
 def bench_ising_batch(rx, n=512, sweeps=10000, base_sweeps=1000, seed=1):
@@ -359,6 +365,11 @@ def main():
         beta_c = math.log(1 + math.sqrt(2)) / 2
         parts["ising_L4096_betac"] = {"xs1024w": bench_ising(rx, "xs1024w", 4096, args.ising_sweeps, beta_c)}
         print(f"# ising L=4096 xs1024w beta_c: {parts['ising_L4096_betac']}", file=sys.stderr, flush=True)
+        mh = {"k2": {k: bench_ising(rx, k, 4096, 200, hits=2) for k in KINDS},
+              "k100": {k: bench_ising(rx, k, 4096, 10, hits=100) for k in KINDS}}
+        parts["ising_L4096_multihit"] = mh
+        print(f"# ising L=4096 multi-hit: " + json.dumps({h: {k: v["flips_per_ns"] for k, v in r.items()}
+                                                         for h, r in mh.items()}), file=sys.stderr, flush=True)
         if not args.skip_batched:
             parts["ising_batch"] = bench_ising_batch(rx)
             print(f"# ising batch: {parts['ising_batch']}", file=sys.stderr, flush=True)

@@ -101,10 +101,11 @@ struct SmallUnit {
     __device__ void load(const uint8_t *st, uint64_t S, uint64_t u) { g.load(st, S, u); }
     __device__ void store(uint8_t *st, uint64_t S, uint64_t u, uint64_t) const { g.store(st, S, u); }
     __device__ void draw(uint32_t (&r)[2]) { r[0] = g.next(); r[1] = g.next(); }
-    // n draws in order, each handed to f (multi-hit updates)
-    template <class F>
-    __device__ void draws(uint32_t n, F &&f) {
-        for (uint32_t i = 0; i < n; ++i) f(g.next());
+    // multi-hit updates: n draws in order to f0, then n more to f1
+    template <class F0, class F1>
+    __device__ void draws2(uint32_t n, F0 &&f0, F1 &&f1) {
+        for (uint32_t i = 0; i < n; ++i) f0(g.next());
+        for (uint32_t i = 0; i < n; ++i) f1(g.next());
     }
 };
 
@@ -131,13 +132,17 @@ struct PhiloxUnit {
         r[1] = j == 0 ? b1 : j == 1 ? b2 : j == 2 ? b3 : b0;
         pos += 2;
     }
-    template <class F>
-    __device__ void draws(uint32_t n, F &&f) {
+    // as SmallUnit::draws2, in one loop so that a block serves four draws in
+    // a row also across the two runs
+    template <class F0, class F1>
+    __device__ void draws2(uint32_t n, F0 &&f0, F1 &&f1) {
         uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
-        for (uint32_t i = 0; i < n; ++i) {
+        for (uint32_t i = 0; i < 2 * n; ++i) {
             const uint32_t j = static_cast<uint32_t>(pos) & 3;
             if (i == 0 || j == 0) philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);
-            f(j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3);
+            const uint32_t r = j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3;
+            if (i < n) f0(r);
+            else f1(r);
             ++pos;
         }
     }
@@ -381,8 +386,7 @@ __device__ __forceinline__ uint64_t update_unit(uint8_t *lds, uint32_t pl, uint3
                                           *reinterpret_cast<const uint32_t *>(lds + off + P + dn_add));
             uint32_t d0 = __builtin_amdgcn_ubfe(m2, sh0, 8), d1 = __builtin_amdgcn_ubfe(m2, sh0 + 16, 8);
             uint32_t x0 = 0, x1 = 0;
-            u.draws(hits, [&](uint32_t r) { hit_lds(d0, x0, r, A); });
-            u.draws(hits, [&](uint32_t r) { hit_lds(d1, x1, r, A); });
+            u.draws2(hits, [&](uint32_t r) { hit_lds(d0, x0, r, A); }, [&](uint32_t r) { hit_lds(d1, x1, r, A); });
             if constexpr (E) esum += d0 + d1;
             const uint32_t nw = w ^ (x0 ? f0 : 0u) ^ (x1 ? f1 : 0u);
             *reinterpret_cast<uint32_t *>(lds + off) = nw;
@@ -725,8 +729,8 @@ __device__ __forceinline__ int unit_in_memory(uint8_t *sp, uint8_t *st, uint64_t
             fl[h] = 0;
         }
         if constexpr (NB == 4) {
-            u.draws(hits, [&](uint32_t r) { hit_mem(mi[0], fl[0], r, T4, T8); });
-            u.draws(hits, [&](uint32_t r) { hit_mem(mi[1], fl[1], r, T4, T8); });
+            u.draws2(hits, [&](uint32_t r) { hit_mem(mi[0], fl[0], r, T4, T8); },
+                     [&](uint32_t r) { hit_mem(mi[1], fl[1], r, T4, T8); });
         } else {
             for (uint32_t i = 0; i < hits; ++i) {
                 uint32_t ra, rb;
