@@ -67,6 +67,10 @@ def lib():
         L.orc_ising_energy.argtypes = [ctypes.c_uint32, vp]
         L.orc_ising_sweeps.restype = i32
         L.orc_ising_sweeps.argtypes = [ctypes.c_uint32, i32, ctypes.c_double, vp, vp, u64, vp]
+        L.orc_xs1024_variant_steps.restype = i32
+        L.orc_xs1024_variant_steps.argtypes = [i32, vp, u64]
+        L.orc_xs1024_equidistribution.restype = i32
+        L.orc_xs1024_equidistribution.argtypes = [i32, i32, vp]
         L.orc_ising_sweeps_hits.restype = i32
         L.orc_ising_sweeps_hits.argtypes = [ctypes.c_uint32, i32, ctypes.c_double, vp, vp, u64, ctypes.c_uint32, vp]
         _lib = L
@@ -139,6 +143,24 @@ def jump(kind: str, S: int, st: np.ndarray, n: int, lo: int = 0, hi: int | None 
     hi = S if hi is None else hi
     w = _words(n)
     _check(lib().orc_jump(_CODE[kind], S, _ptr(st), lo, hi, _ptr(w), len(w)), "jump")
+
+
+XS1024_VARIANTS = ("L329 R347 L344", "R329 L347 R344", "L344 R347 L329", "R344 L347 R329")
+
+
+def xs1024_variant_steps(variant: int, words, n: int) -> np.ndarray:
+    """n steps of a shift-direction variant of the XORShift-1024 part on 32
+    words (word 0 most significant); variant 0 is the generator's."""
+    W = np.array(words, dtype=np.uint32).copy()
+    _check(lib().orc_xs1024_variant_steps(variant, _ptr(W), n), "variant steps")
+    return W
+
+
+def xs1024_equidistribution(variant: int, lane: int) -> np.ndarray:
+    """t_l for l = 1..32 (lane -1: warp order); see orc_xs1024_equidistribution."""
+    t = np.zeros(32, dtype=np.int32)
+    _check(lib().orc_xs1024_equidistribution(variant, lane, _ptr(t)), "equidistribution")
+    return t
 
 
 def ising_threshold(beta: float, dE: int) -> int:

@@ -144,6 +144,86 @@ static void xs1024_step(uint32_t *W)
     for (int i = 0; i < XS_WORDS; i++) W[i] ^= t[i];
 }
 
+/* The four shift-direction choices sharing the characteristic polynomial of
+ * eq. (threeshift) (Sec. XORShift generators, equidistribution paragraph):
+ * 0 = L a, R b, L c (the generator above), 1 = R a, L b, R c,
+ * 2 = L c, R b, L a, 3 = R c, L b, R a, with (a, b, c) = (329, 347, 344).
+ * n steps of variant v on W in place; returns -1 for a bad variant. */
+int orc_xs1024_variant_steps(int v, uint32_t *W, uint64_t n)
+{
+    if (v < 0 || v > 3) return -1;
+    const unsigned sh[3] = {v < 2 ? XS_A : XS_C, XS_B, v < 2 ? XS_C : XS_A};
+    const int left_first = (v % 2) == 0; /* L R L, else R L R */
+    uint32_t t[XS_WORDS];
+    for (uint64_t k = 0; k < n; k++)
+        for (int j = 0; j < 3; j++) {
+            if ((j % 2 == 0) == left_first) big_shl(W, sh[j], t);
+            else big_shr(W, sh[j], t);
+            for (int i = 0; i < XS_WORDS; i++) W[i] ^= t[i];
+        }
+    return 0;
+}
+
+/* Dimensions of equidistribution of the XORShift-1024 part (the paper tests
+ * them as Panneton and L'Ecuyer do, Sec. XORShift generators).  For
+ * resolution l (the l most significant bits of each 32-bit output) t_l is
+ * the largest t such that the l-bit truncations of t successive outputs are
+ * equidistributed: the t*l output bits, as GF(2)-linear functions of the
+ * 1024-bit state, are linearly independent (t_l <= 1024/l).  Outputs:
+ * lane 0..31 = that word after each step (single-thread order); lane = -1 =
+ * the 32 words of each step in order (warp order).  The Weyl term is not
+ * GF(2)-linear and is left out.  t_out[l-1] for l = 1..32.  Returns 0, -1 for
+ * bad arguments, -3 if memory runs out. */
+int orc_xs1024_equidistribution(int v, int lane, int32_t *t_out)
+{
+    if (v < 0 || v > 3 || lane < -1 || lane > 31) return -1;
+    enum { K = 1024, T = 1024, NW64 = K / 64 };
+    /* out[k*T + n]: output n of the run started from unit state e_k (bit k of X,
+     * counted from the most significant end), so bit j of output n, as a linear
+     * function of the start state, is the row (out[k*T + n] >> (31 - j) & 1)_k. */
+    uint32_t *out = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)K * T);
+    uint64_t (*basis)[NW64] = malloc(sizeof(uint64_t) * K * NW64);
+    unsigned char *have = malloc(K);
+    if (!out || !basis || !have) { free(out); free(basis); free(have); return -3; }
+    for (int k = 0; k < K; k++) {
+        uint32_t W[XS_WORDS];
+        memset(W, 0, sizeof W);
+        W[k / 32] = 1u << (31 - k % 32);
+        if (lane >= 0) {
+            for (int n = 0; n < T; n++) { orc_xs1024_variant_steps(v, W, 1); out[(size_t)k * T + n] = W[lane]; }
+        } else {
+            for (int n = 0; n < T; n += XS_WORDS) {
+                orc_xs1024_variant_steps(v, W, 1);
+                for (int i = 0; i < XS_WORDS; i++) out[(size_t)k * T + n + i] = W[i];
+            }
+        }
+    }
+    for (int l = 1; l <= 32; l++) {
+        memset(have, 0, K);
+        int t = 0, dependent = 0;
+        for (int n = 0; n < T && !dependent; n++) {
+            for (int j = 0; j < l && !dependent; j++) {
+                uint64_t row[NW64];
+                memset(row, 0, sizeof row);
+                for (int k = 0; k < K; k++)
+                    if ((out[(size_t)k * T + n] >> (31 - j)) & 1u) row[k / 64] |= 1ull << (k % 64);
+                for (;;) { /* reduce against the basis; a zero row is dependent */
+                    int p = -1;
+                    for (int w = NW64 - 1; w >= 0 && p < 0; w--)
+                        if (row[w]) p = 64 * w + 63 - __builtin_clzll(row[w]);
+                    if (p < 0) { dependent = 1; break; }
+                    if (!have[p]) { memcpy(basis[p], row, sizeof row); have[p] = 1; break; }
+                    for (int w = 0; w < NW64; w++) row[w] ^= basis[p][w];
+                }
+            }
+            if (!dependent) t = n + 1;
+        }
+        t_out[l - 1] = t;
+    }
+    free(out); free(basis); free(have);
+    return 0;
+}
+
 /* Weyl sequence, eq. (weylgen) and its closed form y_n = y_0 + n c mod 2^32;
  * combined output y_n (I + R^16) + x (mod 2^32), gamma = w/2 = 16. */
 static uint32_t weyl_mix(uint32_t y0, uint64_t n)
