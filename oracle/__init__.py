@@ -8,7 +8,8 @@ and in `exact_ising.py` (high-precision exact finite-lattice values); this
 module only marshals numpy buffers.
 
 Kinds are named by string so that the oracle does not depend on the product's
-enum values: "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w".
+enum values: "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w",
+"philox4x32_7".
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
 SOURCES = [os.path.join(HERE, "rng_oracle.c")]
 
-KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w"]
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7"]
 _CODE = {k: i + 1 for i, k in enumerate(KINDS)}
 OUT_U32, OUT_F32, OUT_XOR = 0, 1, 2
 

@@ -38,7 +38,11 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_LCG32 = 1, ORC_LCG64, ORC_MWC, ORC_XORWOW, ORC_PHILOX, ORC_XS1024W };
+enum { ORC_LCG32 = 1, ORC_LCG64, ORC_MWC, ORC_XORWOW, ORC_PHILOX, ORC_XS1024W, ORC_PHILOX7 };
+/* Philox4x32 with 10 rounds (ORC_PHILOX) or 7 (ORC_PHILOX7); everything but the
+ * round count is shared. */
+#define IS_PHILOX(kind) ((kind) == ORC_PHILOX || (kind) == ORC_PHILOX7)
+#define PHILOX_R(kind) ((kind) == ORC_PHILOX7 ? 7 : 10)
 enum { ORC_OUT_U32 = 0, ORC_OUT_F32 = 1, ORC_OUT_XOR = 2 };
 
 /* ------------------------------------------------------------------------ */
@@ -75,7 +79,6 @@ uint64_t orc_splitmix(uint64_t seed, uint64_t k) { return orc_mix64(seed + k * S
 #define PHILOX_M1 0xCD9E8D57u
 #define PHILOX_W0 0x9E3779B9u
 #define PHILOX_W1 0xBB67AE85u
-#define PHILOX_ROUNDS 10
 /* XORShift-1024 shifts, XORShift section: a = 329 (left), b = 347 (right),
  * c = 344 (left) on a 1024-bit word. */
 #define XS_A 329u
@@ -92,7 +95,8 @@ size_t orc_state_bytes(int kind, uint64_t S)
     case ORC_LCG64: return 8 * S;
     case ORC_MWC: return 8 * S;
     case ORC_XORWOW: return 24 * S;
-    case ORC_PHILOX: return 16 * S;
+    case ORC_PHILOX:
+    case ORC_PHILOX7: return 16 * S;
     case ORC_XS1024W: return 4 * S + 8 * (S / 32) + 4;
     default: return 0;
     }
@@ -100,7 +104,7 @@ size_t orc_state_bytes(int kind, uint64_t S)
 
 static int kind_ok(int kind, uint64_t S)
 {
-    if (kind < ORC_LCG32 || kind > ORC_XS1024W) return 0;
+    if (kind < ORC_LCG32 || kind > ORC_PHILOX7) return 0;
     if (kind == ORC_XS1024W && S % 32 != 0) return 0;
     return 1;
 }
@@ -234,11 +238,12 @@ static uint32_t weyl_mix(uint32_t y0, uint64_t n)
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-r (Salmon et al. 2011; S-box as in the counter-based section:
- * L' = mullo(R,M), R' = mulhi(R,M) ^ k ^ L).  Counter (ctr0, ctr1, 0, 0). */
-static void philox4x32(uint32_t k0, uint32_t k1, uint64_t block, uint32_t out[4])
+ * L' = mullo(R,M), R' = mulhi(R,M) ^ k ^ L).  Counter (ctr0, ctr1, 0, 0).
+ * rounds = 10, or 7 for the faster variant the section also measures. */
+static void philox4x32(uint32_t k0, uint32_t k1, uint64_t block, int rounds, uint32_t out[4])
 {
     uint32_t x0 = (uint32_t)block, x1 = (uint32_t)(block >> 32), x2 = 0, x3 = 0;
-    for (int r = 0; r < PHILOX_ROUNDS; r++) {
+    for (int r = 0; r < rounds; r++) {
         if (r > 0) { k0 += PHILOX_W0; k1 += PHILOX_W1; }
         uint64_t p0 = (uint64_t)PHILOX_M0 * x0;
         uint64_t p1 = (uint64_t)PHILOX_M1 * x2;
@@ -287,7 +292,7 @@ int orc_seed(int kind, uint64_t S, uint64_t seed, void *st)
             v[s] = (uint32_t)e; d[s] = (uint32_t)(e >> 32);
             if ((x[s] | y[s] | z[s] | w[s] | v[s]) == 0) x[s] = 1;
         }
-    } else if (kind == ORC_PHILOX) {
+    } else if (IS_PHILOX(kind)) {
         uint32_t *k0 = (uint32_t *)b, *k1 = k0 + S;
         uint64_t *pos = (uint64_t *)(b + 8 * S);
         for (uint64_t s = 0; s < S; s++) {
@@ -371,13 +376,13 @@ int orc_generate(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, uint6
                 D[s] += WEYL_C;
                 emit(mode, out, k, width, s - lo, D[s] + V[s]);
             }
-    } else if (kind == ORC_PHILOX) {
+    } else if (IS_PHILOX(kind)) {
         uint32_t *k0 = (uint32_t *)b, *k1 = k0 + S;
         uint64_t *pos = (uint64_t *)(b + 8 * S);
         for (uint64_t s = lo; s < hi; s++)
             for (uint64_t k = 0; k < count; k++) {
                 uint32_t blk[4];
-                philox4x32(k0[s], k1[s], pos[s] / 4, blk);
+                philox4x32(k0[s], k1[s], pos[s] / 4, PHILOX_R(kind), blk);
                 emit(mode, out, k, width, s - lo, blk[pos[s] % 4]);
                 pos[s]++;
             }
@@ -404,7 +409,7 @@ int orc_step_n(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, uint64_
     if (!kind_ok(kind, S) || lo > hi || hi > S) return -1;
     if (kind == ORC_XS1024W && (lo % 32 || hi % 32)) return -1;
     uint8_t *b = (uint8_t *)st;
-    if (kind == ORC_PHILOX) { /* counter-based: stepping is counting */
+    if (IS_PHILOX(kind)) { /* counter-based: stepping is counting */
         uint64_t *pos = (uint64_t *)(b + 8 * S);
         for (uint64_t s = lo; s < hi; s++) pos[s] += n;
         return 0;
@@ -589,7 +594,7 @@ int orc_jump(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, const uin
             D[s] += (uint32_t)n_lo * WEYL_C;
         }
         free(v);
-    } else if (kind == ORC_PHILOX) {
+    } else if (IS_PHILOX(kind)) {
         uint64_t *pos = (uint64_t *)(b + 8 * S);
         for (uint64_t s = lo; s < hi; s++) pos[s] += n_lo;
     } else {

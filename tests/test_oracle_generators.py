@@ -6,8 +6,11 @@ a*2^32 - 1 a safe prime; MWC equals the multiplicative LCG y -> a y mod p.
 XORWOW (XORShift section; recurrence from Marsaglia 2003): the xorshift part
 has a primitive degree-160 minimal polynomial, so with the Weyl term the
 period is 2^192 - 2^32 as the paper states.
-Philox4x32-10 (counter-based section): only structural checks are possible
-here; agreement with the published constants is "parity unpinned".
+Philox4x32-10 and -7 (counter-based section): only structural checks are
+possible here; agreement with the published constants is "parity unpinned".
+The seven-round variant is pinned to the ten-round one: three further rounds
+(written out here from the section's S-box) turn its block into the
+ten-round block.
 """
 import numpy as np
 import pytest
@@ -138,16 +141,17 @@ def test_xorwow_weyl_part_and_output(orc):
         assert np.array_equal(out[0].astype(np.uint64), (d + v) & np.uint64(M32))
 
 
-def test_philox_counter_and_key_semantics(orc):
+@pytest.mark.parametrize("kind", ["philox4x32_10", "philox4x32_7"])
+def test_philox_counter_and_key_semantics(orc, kind):
     # Output k of a stream is word k%4 of block k/4; the position jump is exact;
     # blocks of one key are distinct (the rounds are a bijection of the counter).
     S = 4
-    st = orc.seed("philox4x32_10", S, 1)
-    full = orc.generate("philox4x32_10", S, st.copy(), 64)
+    st = orc.seed(kind, S, 1)
+    full = orc.generate(kind, S, st.copy(), 64)
     for n in (0, 1, 3, 4, 5, 31):
         a = st.copy()
-        orc.jump("philox4x32_10", S, a, n)
-        part = orc.generate("philox4x32_10", S, a, 64 - n)
+        orc.jump(kind, S, a, n)
+        part = orc.generate(kind, S, a, 64 - n)
         assert np.array_equal(part, full[n:])
     blocks = {tuple(full[4 * b:4 * b + 4, 0]) for b in range(16)}
     assert len(blocks) == 16
@@ -156,13 +160,38 @@ def test_philox_counter_and_key_semantics(orc):
     assert len(set(k0.tolist())) == S
 
 
-def test_philox_output_balance(orc):
+@pytest.mark.parametrize("kind", ["philox4x32_10", "philox4x32_7"])
+def test_philox_output_balance(orc, kind):
     # Coarse sanity (not a pin of the constants): bits are balanced.
     S = 64
-    st = orc.seed("philox4x32_10", S, 1)
-    out = orc.generate("philox4x32_10", S, st, 256)
+    st = orc.seed(kind, S, 1)
+    out = orc.generate(kind, S, st, 256)
     bits = np.unpackbits(out.view(np.uint8))
     assert abs(bits.mean() - 0.5) < 0.005
+
+
+def _philox_round(x, k0, k1):
+    # one round: products of words 0 and 2 with the multipliers; the high
+    # halves are mixed with the other words and the round key
+    p0 = 0xD2511F53 * x[0]
+    p1 = 0xCD9E8D57 * x[2]
+    return [((p1 >> 32) ^ x[1] ^ k0) & M32, p1 & M32, ((p0 >> 32) ^ x[3] ^ k1) & M32, p0 & M32]
+
+
+def test_philox7_is_the_first_seven_rounds(orc):
+    S = 8
+    st = orc.seed("philox4x32_7", S, 3)
+    assert np.array_equal(st, orc.seed("philox4x32_10", S, 3))  # same keys, same positions
+    b7 = orc.generate("philox4x32_7", S, st.copy(), 8)
+    b10 = orc.generate("philox4x32_10", S, st.copy(), 8)
+    k0s, k1s = st.view(np.uint32)[:S], st.view(np.uint32)[S:2 * S]
+    for s in range(S):
+        for blk in range(2):
+            x = [int(v) for v in b7[4 * blk:4 * blk + 4, s]]
+            for r in (7, 8, 9):
+                x = _philox_round(x, (int(k0s[s]) + r * 0x9E3779B9) & M32, (int(k1s[s]) + r * 0xBB67AE85) & M32)
+            assert x == [int(v) for v in b10[4 * blk:4 * blk + 4, s]], (s, blk)
+    assert not np.array_equal(b7, b10)
 
 
 def test_f32_conversion_exact(orc):
