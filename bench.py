@@ -27,9 +27,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 S_FULL, COUNT_FULL = 1 << 20, 4096
-KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10"]
+KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7"]
 # state bytes read + written once per launch, per stream
-STATE_BYTES = {"lcg32": 4, "lcg64": 8, "mwc": 8, "xorwow": 24, "philox4x32_10": 16, "xs1024w": 4 + 8 / 32}
+STATE_BYTES = {"lcg32": 4, "lcg64": 8, "mwc": 8, "xorwow": 24, "philox4x32_10": 16, "philox4x32_7": 16,
+               "xs1024w": 4 + 8 / 32}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "xs1024w_fill_u32_2p20x4096_hbm_traffic.md")
 KERNEL_SOURCES = ["paper_1204_6193_amd/csrc/gen.hip", "paper_1204_6193_amd/csrc/rngx_device.h"]
 

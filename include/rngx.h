@@ -74,7 +74,8 @@ typedef enum {
     RNGX_MWC = 3,           /* lag-1 multiply-with-carry, base 2^32, a = 4294967118; out x (MWC sec.) */
     RNGX_XORWOW = 4,        /* 160-bit xorshift (2,1,4) + Weyl d += 362437; out d + v (XORShift sec.) */
     RNGX_PHILOX4X32_10 = 5, /* counter-based Philox4x32, 10 rounds (counter-based section)         */
-    RNGX_XS1024W = 6        /* the paper's XORShift-1024 (329,347,344) + Weyl (XORShift section)    */
+    RNGX_XS1024W = 6,       /* the paper's XORShift-1024 (329,347,344) + Weyl (XORShift section)    */
+    RNGX_PHILOX4X32_7 = 7   /* Philox4x32 with 7 rounds (counter-based section); otherwise as 5     */
 } rngx_kind;
 
 typedef enum {

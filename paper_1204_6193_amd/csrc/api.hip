@@ -176,13 +176,14 @@ size_t state_bytes(rngx_kind kind, uint64_t S) {
     case RNGX_LCG64: return 8 * S;
     case RNGX_MWC: return 8 * S;
     case RNGX_XORWOW: return 24 * S;
-    case RNGX_PHILOX4X32_10: return 16 * S;
+    case RNGX_PHILOX4X32_10:
+    case RNGX_PHILOX4X32_7: return 16 * S;
     case RNGX_XS1024W: return 4 * S + 8 * (S / 32) + 4;
     }
     return 0;
 }
 
-bool kind_valid(int kind) { return kind >= RNGX_LCG32 && kind <= RNGX_XS1024W; }
+bool kind_valid(int kind) { return kind >= RNGX_LCG32 && kind <= RNGX_PHILOX4X32_7; }
 
 rngx_status fail(rngx_status st, const std::string &msg) { g_error = msg; return st; }
 rngx_status hip_fail(hipError_t e, const char *what) {

@@ -41,6 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_seed_small(rngx_kind kind, uint8_t *
         for (int i = 0; i < 6; ++i) u32[i * S + s] = w[i];
         break;
     }
+    case RNGX_PHILOX4X32_7:
     case RNGX_PHILOX4X32_10: {
         const uint64_t z = splitmix(seed, 1 + s);
         u32[s] = static_cast<uint32_t>(z);
@@ -313,6 +314,7 @@ const void *config_kernel(rngx_kind kind, int mode, const rngx_fill_config &c) {
     case RNGX_MWC: return config_kernel<Mwc>(mode, c);
     case RNGX_XORWOW: return config_kernel<Xorwow>(mode, c);
     case RNGX_PHILOX4X32_10: return config_kernel<Philox>(mode, c);
+    case RNGX_PHILOX4X32_7: return config_kernel<Philox7>(mode, c);
     case RNGX_XS1024W: return mode == kOutU32 ? xs_kernel<kOutU32>(c.block) : xs_kernel<kOutF32>(c.block);
     }
     return nullptr;
@@ -395,6 +397,7 @@ hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
     case RNGX_MWC: return fill_small<Mwc, MODE>(g, out, count, st);
     case RNGX_XORWOW: return fill_small<Xorwow, MODE>(g, out, count, st);
     case RNGX_PHILOX4X32_10: return fill_small<Philox, MODE>(g, out, count, st);
+    case RNGX_PHILOX4X32_7: return fill_small<Philox7, MODE>(g, out, count, st);
     case RNGX_XS1024W: return fill_xs<MODE>(g, out, count, st);
     }
     return hipErrorInvalidValue;

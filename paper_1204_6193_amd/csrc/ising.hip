@@ -111,7 +111,8 @@ struct SmallUnit {
 
 // Philox with only key and position held: the two draws of a pass come from
 // one block unless they straddle a block boundary.
-struct PhiloxUnit {
+template <int ROUNDS>
+struct PhiloxUnitR {
     static constexpr int kNB = 4;
     uint32_t k0, k1;
     uint64_t pos;
@@ -125,10 +126,10 @@ struct PhiloxUnit {
     }
     __device__ void draw(uint32_t (&r)[2]) {
         uint32_t b0, b1, b2, b3;
-        philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);
+        philox_block<ROUNDS>(k0, k1, pos >> 2, b0, b1, b2, b3);
         const uint32_t j = static_cast<uint32_t>(pos) & 3;
         r[0] = j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3;
-        if (j == 3) philox_block(k0, k1, (pos >> 2) + 1, b0, b1, b2, b3);
+        if (j == 3) philox_block<ROUNDS>(k0, k1, (pos >> 2) + 1, b0, b1, b2, b3);
         r[1] = j == 0 ? b1 : j == 1 ? b2 : j == 2 ? b3 : b0;
         pos += 2;
     }
@@ -139,7 +140,7 @@ struct PhiloxUnit {
         uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
         for (uint32_t i = 0; i < 2 * n; ++i) {
             const uint32_t j = static_cast<uint32_t>(pos) & 3;
-            if (i == 0 || j == 0) philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);
+            if (i == 0 || j == 0) philox_block<ROUNDS>(k0, k1, pos >> 2, b0, b1, b2, b3);
             const uint32_t r = j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3;
             if (i < n) f0(r);
             else f1(r);
@@ -147,6 +148,8 @@ struct PhiloxUnit {
         }
     }
 };
+using PhiloxUnit = PhiloxUnitR<10>;
+using PhiloxUnit7 = PhiloxUnitR<7>;
 
 // XS1024W lane pair u: lane u%16 of instance u/16 of the handle (words 2u,
 // 2u+1 = streams 2u and 2u+1).  Two instance steps per pass; the draws are
@@ -1034,6 +1037,7 @@ const void *batch_kernel_for(rngx_kind kind) {
     case RNGX_MWC: return batch_kernel<SmallUnit<Mwc>>();
     case RNGX_XORWOW: return batch_kernel<SmallUnit<Xorwow>>();
     case RNGX_PHILOX4X32_10: return batch_kernel<PhiloxUnit>();
+    case RNGX_PHILOX4X32_7: return batch_kernel<PhiloxUnit7>();
     case RNGX_XS1024W: return batch_kernel<XsUnit>();
     }
     return nullptr;
@@ -1133,6 +1137,7 @@ hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
     case RNGX_MWC: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Mwc>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     case RNGX_XORWOW: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Xorwow>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ising_batch<PhiloxUnit>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
+    case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_ising_batch<PhiloxUnit7>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     case RNGX_XS1024W: hipLaunchKernelGGL(k_ising_batch<XsUnit>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     }
     return hipGetLastError();
@@ -1162,6 +1167,7 @@ int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int ma
     case RNGX_MWC: return list_plans<SmallUnit<Mwc>>(L, 16, n_cu, out, max);
     case RNGX_XORWOW: return list_plans<SmallUnit<Xorwow>>(L, 16, n_cu, out, max);
     case RNGX_PHILOX4X32_10: return list_plans<PhiloxUnit>(L, 16, n_cu, out, max);
+    case RNGX_PHILOX4X32_7: return list_plans<PhiloxUnit7>(L, 16, n_cu, out, max);
     case RNGX_XS1024W: return list_plans<XsUnit>(L, 16, n_cu, out, max);
     }
     return 0;
@@ -1174,6 +1180,7 @@ bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
     case RNGX_MWC: return plan_strips<SmallUnit<Mwc>>(L, 16, n_cu, out);
     case RNGX_XORWOW: return plan_strips<SmallUnit<Xorwow>>(L, 16, n_cu, out);
     case RNGX_PHILOX4X32_10: return plan_strips<PhiloxUnit>(L, 16, n_cu, out);
+    case RNGX_PHILOX4X32_7: return plan_strips<PhiloxUnit7>(L, 16, n_cu, out);
     case RNGX_XS1024W: return plan_strips<XsUnit>(L, 16, n_cu, out);
     }
     return false;
@@ -1205,6 +1212,7 @@ hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_t
     case RNGX_MWC: return run<SmallUnit<Mwc>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_XORWOW: return run<SmallUnit<Xorwow>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_PHILOX4X32_10: return run<PhiloxUnit>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_PHILOX4X32_7: return run<PhiloxUnit7>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_XS1024W: return run<XsUnit>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     }
     return hipErrorInvalidValue;

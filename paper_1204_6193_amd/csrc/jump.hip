@@ -279,6 +279,7 @@ void jump_table(rngx_kind kind, uint64_t step, uint64_t count, std::vector<uint6
     }
     case RNGX_XORWOW: poly_table<160>(xorwow_minpoly(), step, count, u32s); break;
     case RNGX_XS1024W: poly_table<1024>(xs1024_minpoly(), step, count, u32s); break;
+    case RNGX_PHILOX4X32_7:
     case RNGX_PHILOX4X32_10: break;
     }
 }
@@ -303,6 +304,7 @@ hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st) {
         hipLaunchKernelGGL(k_skip_mwc, dim3(blocks_for(S)), dim3(kBlock), 0, st,
                            reinterpret_cast<uint64_t *>(g->d_state), S, host_powmod_p(kMwcA, n));
         break;
+    case RNGX_PHILOX4X32_7:
     case RNGX_PHILOX4X32_10:
         hipLaunchKernelGGL(k_skip_philox, dim3(blocks_for(S)), dim3(kBlock), 0, st,
                            reinterpret_cast<uint64_t *>(g->d_state + 8 * S), S, n);

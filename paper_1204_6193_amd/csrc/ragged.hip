@@ -131,6 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_ragged_start_small(rngx_kind kind, c
         o[5 * n_items + i] = p[5 * S + s] + static_cast<uint32_t>(j * chunk) * kWeylC;
         break;
     }
+    case RNGX_PHILOX4X32_7:
     case RNGX_PHILOX4X32_10: {
         const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
         uint32_t *o = reinterpret_cast<uint32_t *>(scratch);
@@ -356,6 +357,7 @@ hipError_t launch_stream_fill(rngx_kind kind, const uint8_t *st_in, uint8_t *st_
     case RNGX_MWC: hipLaunchKernelGGL(k_stream_fill_small<Mwc>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
     case RNGX_XORWOW: hipLaunchKernelGGL(k_stream_fill_small<Xorwow>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
     case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_stream_fill_small<Philox>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
+    case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_stream_fill_small<Philox7>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
     default: break;
     }
     return hipGetLastError();
@@ -468,6 +470,7 @@ hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st) {
     case RNGX_MWC: hipLaunchKernelGGL(k_ragged_gen_small<Mwc>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_XORWOW: hipLaunchKernelGGL(k_ragged_gen_small<Xorwow>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ragged_gen_small<Philox>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_ragged_gen_small<Philox7>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     default: break;
     }
     return hipGetLastError();

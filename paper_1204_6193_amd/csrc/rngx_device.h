@@ -86,12 +86,14 @@ struct Xorwow {
     }
 };
 
-// Philox4x32-10 block function on counter (lo, hi, 0, 0) with key (k0, k1).
+// Philox4x32-R block function on counter (lo, hi, 0, 0) with key (k0, k1);
+// R = 10, or 7 for the faster variant of the counter-based section.
+template <int ROUNDS = 10>
 __device__ inline void philox_block(uint32_t k0, uint32_t k1, uint64_t blk, uint32_t &o0, uint32_t &o1,
                                     uint32_t &o2, uint32_t &o3) {
     uint32_t x0 = static_cast<uint32_t>(blk), x1 = static_cast<uint32_t>(blk >> 32), x2 = 0, x3 = 0;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 0; r < ROUNDS; ++r) {
         const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * x0;
         const uint64_t p1 = static_cast<uint64_t>(kPhiloxM1) * x2;
         const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ x1 ^ k0;
@@ -104,25 +106,28 @@ __device__ inline void philox_block(uint32_t k0, uint32_t k1, uint64_t blk, uint
     o0 = x0; o1 = x1; o2 = x2; o3 = x3;
 }
 
-struct Philox {
+template <int ROUNDS>
+struct PhiloxR {
     uint32_t k0, k1, b0, b1, b2, b3;
     uint64_t pos;
     __device__ void load(const uint8_t *st, uint64_t S, uint64_t s) {
         const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
         k0 = p[s]; k1 = p[S + s];
         pos = reinterpret_cast<const uint64_t *>(st + 8 * S)[s];
-        if (pos & 3) philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);  // resume mid-block
+        if (pos & 3) philox_block<ROUNDS>(k0, k1, pos >> 2, b0, b1, b2, b3);  // resume mid-block
     }
     __device__ void store(uint8_t *st, uint64_t S, uint64_t s) const {
         reinterpret_cast<uint64_t *>(st + 8 * S)[s] = pos;
     }
     __device__ uint32_t next() {
         const uint32_t j = static_cast<uint32_t>(pos) & 3;
-        if (j == 0) philox_block(k0, k1, pos >> 2, b0, b1, b2, b3);
+        if (j == 0) philox_block<ROUNDS>(k0, k1, pos >> 2, b0, b1, b2, b3);
         ++pos;
         return j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3;
     }
 };
+using Philox = PhiloxR<10>;
+using Philox7 = PhiloxR<7>;
 
 // ---------------------------------------------------------------------------
 // XORShift-1024 on wave64: one 1024-bit instance per 16-lane DPP row, two
@@ -209,9 +214,10 @@ __device__ __forceinline__ void jump(Xorwow &g, const uint64_t *, const uint32_t
     g.x = s[0]; g.y = s[1]; g.z = s[2]; g.w = s[3]; g.v = s[4];
     g.d += static_cast<uint32_t>(j * C) * kWeylC;
 }
-__device__ __forceinline__ void jump(Philox &g, const uint64_t *, const uint32_t *, uint64_t j, uint64_t C) {
+template <int ROUNDS>
+__device__ __forceinline__ void jump(PhiloxR<ROUNDS> &g, const uint64_t *, const uint32_t *, uint64_t j, uint64_t C) {
     g.pos += j * C;
-    if (g.pos & 3) philox_block(g.k0, g.k1, g.pos >> 2, g.b0, g.b1, g.b2, g.b3);  // resume mid-block
+    if (g.pos & 3) philox_block<ROUNDS>(g.k0, g.k1, g.pos >> 2, g.b0, g.b1, g.b2, g.b3);  // resume mid-block
 }
 
 // y * A mod p for the MWC modulus p = a 2^32 - 1, using 2^64 = R (mod p)

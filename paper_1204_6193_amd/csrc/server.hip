@@ -121,8 +121,8 @@ struct Server {
     std::vector<std::shared_ptr<ServerRequest>> inflight;
     std::unordered_map<uint64_t, std::shared_ptr<ServerRequest>> all;
     std::map<std::pair<uint32_t, int>, ClientGen *> gens;
-    const uint64_t *t64[7] = {};  // per-kind jump tables for chunks of stream_fill_chunk(kind)
-    const uint32_t *t32[7] = {};
+    const uint64_t *t64[8] = {};  // per-kind jump tables for chunks of stream_fill_chunk(kind)
+    const uint32_t *t32[8] = {};
     std::unordered_map<uint32_t, uint64_t> ising_count;
     std::deque<uint64_t> completed;  // finished tickets not yet returned by wait_any
     uint64_t next_ticket = 1;
@@ -293,7 +293,7 @@ rngx_status server_create(const rngx_server_config *cfg, Server **out) {
         return fail(RNGX_E_NOMEM, "cannot allocate the memory budget");
     }
     // jump tables for requests of up to kMaxServedValues values, every kind
-    for (int k = RNGX_LCG32; k <= RNGX_XS1024W; ++k) {
+    for (int k = RNGX_LCG32; k <= RNGX_PHILOX4X32_7; ++k) {
         const rngx_kind kind = static_cast<rngx_kind>(k);
         const uint64_t C = stream_fill_chunk(kind);
         const uint64_t steps = kind == RNGX_XS1024W ? kMaxServedValues / 32 : kMaxServedValues;

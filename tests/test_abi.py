@@ -45,7 +45,7 @@ def test_create_validation(rngx):
     lib = rngx.load()
     h = ctypes.c_void_p()
     assert lib.rng_create(0, 16, 1, ctypes.byref(h)) == -1
-    assert lib.rng_create(7, 16, 1, ctypes.byref(h)) == -1
+    assert lib.rng_create(8, 16, 1, ctypes.byref(h)) == -1
     assert lib.rng_create(1, 0, 1, ctypes.byref(h)) == -1
     assert lib.rng_create(6, 48, 1, ctypes.byref(h)) == -2 and "% 32" in _err(lib)
     assert lib.rng_create(1, (1 << 36) + 1, 1, ctypes.byref(h)) == -5
@@ -79,7 +79,7 @@ def test_fill_configuration_lists(rngx):
     lib = rngx.load()
     small = rngx.rng_fill_configs("lcg32")
     assert len(small) == 7 and small[0] == (1, 4, 512) and (0, 4, 256) in small
-    for kind in ("lcg64", "mwc", "xorwow", "philox4x32_10"):
+    for kind in ("lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7"):
         assert rngx.rng_fill_configs(kind) == small
     xs = rngx.rng_fill_configs("xs1024w")
     assert len(xs) == 4 and all(v == 2 for _, v, _ in xs) and xs[0] == (1, 2, 1024)

@@ -13,7 +13,7 @@ from oracle import exact_ising as ex
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w"]
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7"]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -175,7 +175,7 @@ def _exact(L, beta):
     raise KeyError((L, beta))
 
 
-GATED = ("xs1024w", "philox4x32_10", "mwc", "lcg64")   # LCG32 and XORWOW: reported only
+GATED = ("xs1024w", "philox4x32_10", "philox4x32_7", "mwc", "lcg64")  # LCG32, XORWOW: reported only
 
 
 def test_statistics_all_kinds(rngx):

@@ -5,7 +5,7 @@ import torch
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w"]
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7"]
 
 
 def _lengths(kind, n_units, seed):

@@ -10,7 +10,7 @@ import torch
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w"]
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7"]
 
 
 def _sizes(kind):
