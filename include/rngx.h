@@ -127,6 +127,14 @@ typedef struct {
  * at most one of its 16 distinct splitmix64 words is 0.) */
 rngx_status rng_create(rngx_kind kind, uint64_t n_streams, uint64_t seed, rngx_gen *out);
 
+/* XS1024W only: sub-stream seeding (XORShift section: the sequence is cut
+ * into blocks of 2^137 numbers, assigned to the instances in turn).  Every
+ * instance g starts from the state rng_create gives instance 0 and skips
+ * g * 2^137 steps; step counters are 0 (g * 2^137 mod 2^64) and the Weyl
+ * seed is rng_create's.  Synchronous.  Errors as rng_create, and
+ * RNGX_E_INVALID for any other kind. */
+rngx_status rng_create_substreams(rngx_kind kind, uint64_t n_streams, uint64_t seed, rngx_gen *out);
+
 /* Release the handle and its device memory (waits for the device first). */
 rngx_status rng_destroy(rngx_gen g);
 

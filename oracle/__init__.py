@@ -146,6 +146,29 @@ def jump(kind: str, S: int, st: np.ndarray, n: int, lo: int = 0, hi: int | None 
     _check(lib().orc_jump(_CODE[kind], S, _ptr(st), lo, hi, _ptr(w), len(w)), "jump")
 
 
+SUBSTREAM_LOG2 = 137  # XS1024W instances are 2^137 steps apart (Sec. XORShift generators)
+
+
+def seed_substreams(kind: str, S: int, seed_: int, lo_inst: int = 0, hi_inst: int | None = None) -> np.ndarray:
+    """XS1024W sub-stream seeding: every instance starts from the state of
+    instance 0 of seed(kind, S, seed_) and skips g * 2^137 steps (the paper
+    partitions the sequence into blocks of 2^137 numbers, one per instance).
+    Composed of the pinned seeding and jump-ahead.  Only instances
+    [lo_inst, hi_inst) are filled in (the rest keep their plain seeding),
+    since each costs one jump."""
+    if kind != "xs1024w":
+        raise ValueError("sub-stream seeding is defined for xs1024w")
+    st = seed(kind, S, seed_)
+    G = S // 32
+    hi_inst = G if hi_inst is None else hi_inst
+    W = st.view(np.uint32)
+    base = W[:32].copy()
+    for g in range(max(lo_inst, 1), hi_inst):
+        W[32 * g: 32 * g + 32] = base
+        jump(kind, S, st, g << SUBSTREAM_LOG2, lo=32 * g, hi=32 * g + 32)
+    return st
+
+
 XS1024_VARIANTS = ("L329 R347 L344", "R329 L347 R344", "L344 R347 L329", "R344 L347 R329")
 
 

@@ -27,6 +27,7 @@ STATUS = {0: "RNGX_OK", -1: "RNGX_E_INVALID", -2: "RNGX_E_ALIGN", -3: "RNGX_E_NO
 _u64, _i32, _vp, _sz = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
 SIGNATURES = {
     "rng_create": (_i32, [_i32, _u64, _u64, ctypes.POINTER(_vp)]),
+    "rng_create_substreams": (_i32, [_i32, _u64, _u64, ctypes.POINTER(_vp)]),
     "rng_destroy": (_i32, [_vp]),
     "rng_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_u64)]),
     "rng_fill_u32": (_i32, [_vp, _vp, _u64, _vp]),
@@ -162,6 +163,13 @@ class Gen:
 def rng_create(kind, n_streams: int, seed: int) -> Gen:
     h = _vp()
     _check(load().rng_create(_kind(kind), n_streams, seed, ctypes.byref(h)))
+    return Gen(h.value)
+
+
+def rng_create_substreams(kind, n_streams: int, seed: int) -> Gen:
+    """XS1024W: instance g = instance 0 of rng_create skipped g * 2^137 steps."""
+    h = _vp()
+    _check(load().rng_create_substreams(_kind(kind), n_streams, seed, ctypes.byref(h)))
     return Gen(h.value)
 
 

@@ -214,6 +214,21 @@ rngx_status rng_create(rngx_kind kind, uint64_t n_streams, uint64_t seed, rngx_g
     return RNGX_OK;
 }
 
+rngx_status rng_create_substreams(rngx_kind kind, uint64_t n_streams, uint64_t seed, rngx_gen *out) {
+    if (!out) return fail(RNGX_E_INVALID, "out is NULL");
+    if (kind != RNGX_XS1024W) return fail(RNGX_E_INVALID, "sub-stream seeding is defined for XS1024W only");
+    Gen *g;
+    if (rngx_status s = alloc_gen(kind, n_streams, &g)) return s;
+    hipError_t e = launch_seed(g, seed, nullptr);
+    if (e == hipSuccess) e = launch_substreams(g, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) { free_gen(g); return hip_fail(e, "sub-stream seeding"); }
+    reg(g);
+    *out = reinterpret_cast<rngx_gen>(g);
+    clear_error();
+    return RNGX_OK;
+}
+
 rngx_status rng_destroy(rngx_gen h) {
     Gen *g;
     if (rngx_status s = check_gen(h, &g)) return s;

@@ -219,6 +219,24 @@ __global__ __launch_bounds__(kBlock) void k_skip_xs(uint8_t *st, uint64_t S, Jum
     if ((t & 15) == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[g] += n;
 }
 
+// Sub-stream seeding (XORShift section): instance g (g >= 1) takes instance
+// 0's xorshift words and skips g * 2^137 steps, applying x^(2^(137+i)) mod P
+// (polys[32 i ..], coefficient j at bit j%32 of word j/32) for every set bit
+// i of g by Horner's rule.  Instance 0 is only read.  The step counters stay
+// as seeded: g * 2^137 is 0 modulo 2^64.
+__global__ __launch_bounds__(kBlock) void k_substreams_xs(uint8_t *st, uint64_t S, const uint32_t *polys,
+                                                           uint32_t nbits) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t G = S / 32, g = t >> 4, lane = t & 15;
+    if (g >= G || g == 0) return;  // whole 16-lane rows
+    uint2 *W = reinterpret_cast<uint2 *>(st);
+    const uint2 w = W[lane];
+    uint32_t a = w.x, b = w.y;
+    for (uint32_t i = 0; i < nbits; ++i)
+        if ((g >> i) & 1) xs1024_apply_poly(polys + 32 * i, a, b);
+    W[t] = make_uint2(a, b);
+}
+
 struct Aff { uint64_t a, c; };
 Aff aff_after(Aff f, Aff g) { return {f.a * g.a, f.a * g.c + f.c}; }
 Aff aff_pow(Aff f, uint64_t n) {
@@ -327,6 +345,36 @@ hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st) {
     }
     }
     return hipGetLastError();
+}
+
+hipError_t launch_substreams(Gen *g, hipStream_t st) {
+    const uint64_t G = g->S / 32;
+    if (g->kind != RNGX_XS1024W) return hipErrorInvalidValue;
+    if (G < 2) return hipSuccess;
+    uint32_t nbits = 0;
+    while ((G - 1) >> nbits) ++nbits;
+    // x^(2^137) mod P by 137 squarings, then one more squaring per bit
+    const Poly &P = xs1024_minpoly();
+    Poly J(P.size(), 0);
+    J[0] = 2;  // x
+    for (int k = 0; k < 137; ++k) J = poly_mod(poly_square(J), P);
+    std::vector<uint32_t> words(32ull * nbits, 0);
+    for (uint32_t i = 0; i < nbits; ++i) {
+        for (int j = 0; j < 1024; ++j)
+            if (poly_bit(J, j)) words[32ull * i + j / 32] |= 1u << (j % 32);
+        J = poly_mod(poly_square(J), P);
+    }
+    uint32_t *d_polys = nullptr;
+    hipError_t e = hipMalloc(&d_polys, 4 * words.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(d_polys, words.data(), 4 * words.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_substreams_xs, dim3(blocks_for(16 * G)), dim3(kBlock), 0, st, g->d_state, g->S, d_polys,
+                           nbits);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_polys);
+    return e;
 }
 
 }  // namespace rngx

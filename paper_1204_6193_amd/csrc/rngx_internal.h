@@ -126,6 +126,7 @@ int fill_configs(rngx_kind kind, const rngx_fill_config **list);  // autotuner c
 int fill_default(rngx_kind kind);
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st);
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
+hipError_t launch_substreams(Gen *g, hipStream_t st);  // XS1024W: instance g skips g 2^137 steps (synchronous)
 
 // Host-side jump tables for j = 0 .. count-1 steps of size `step`:
 //  LCG32/LCG64: (A, C) pairs of the affine map f^(j step), 2 u64 each;

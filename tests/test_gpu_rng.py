@@ -304,3 +304,33 @@ def test_full_size_sampled_parity(rngx, orc, kind):
     assert np.array_equal(rngx.rng_get_state(g3), rngx.rng_get_state(g))
     assert np.array_equal(rngx.rng_get_state(g2), rngx.rng_get_state(g))
     torch.cuda.empty_cache()
+
+
+def test_substream_seeding(rngx, orc):
+    """Instance g = instance 0 of the plain seeding skipped g * 2^137 steps:
+    sampled instances (indices with several bits set, up to 15 jumps)
+    against the oracle's jump-ahead; counters 0; a fill continues them."""
+    print("case substreams", flush=True)
+    for S, sample in ((32 * 40, (1, 2, 3, 5, 39)), (32 * (1 << 15), (16384, 32767))):
+        g = rngx.rng_create_substreams("xs1024w", S, 9)
+        got = rngx.rng_get_state(g)
+        plain = orc.seed("xs1024w", S, 9)
+        W = got.view(np.uint32)
+        assert np.array_equal(W[:32], plain.view(np.uint32)[:32])
+        assert np.all(got[4 * S: 4 * S + 8 * (S // 32)].view(np.uint64) == 0)
+        assert np.array_equal(got[-4:], plain[-4:])
+        for inst in sample:
+            one = orc.seed("xs1024w", 32, 9)  # one instance: words of instance 0, counter 0
+            one.view(np.uint32)[:32] = plain.view(np.uint32)[:32]
+            one[-4:] = plain[-4:]
+            orc.jump("xs1024w", 32, one, inst << 137)
+            assert np.array_equal(W[32 * inst: 32 * inst + 32], one.view(np.uint32)[:32]), (S, inst)
+        del g
+    g = rngx.rng_create_substreams("xs1024w", 32 * 40, 9)
+    st = rngx.rng_get_state(g)
+    out = torch.empty(32 * 40 * 16, dtype=torch.int32, device="cuda")
+    rngx.rng_fill_u32(g, out, 16)
+    want = orc.generate("xs1024w", 32 * 40, st, 16)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32).reshape(16, -1), want)
+    with pytest.raises(rngx.RngxError):
+        rngx.rng_create_substreams("lcg32", 64, 1)

@@ -79,3 +79,19 @@ def test_xs1024w_period(orc):
     assert np.array_equal(a[:128], st[:128])
     # step counter advanced by (2^1024 - 1) mod 2^64
     assert int(a[128:136].view(np.uint64)[0]) == (1 << 64) - 1
+
+
+def test_substream_seeding_composes(orc):
+    # instance 0 is the plain seeding's; instance g+1 is instance g skipped
+    # 2^137 steps (jumps of 2^137 compose); counters stay 0 (2^137 g mod 2^64)
+    S = 32 * 3
+    st = orc.seed_substreams("xs1024w", S, 9)
+    plain = orc.seed("xs1024w", S, 9)
+    W, P = st.view(np.uint32), plain.view(np.uint32)
+    assert np.array_equal(W[:32], P[:32])
+    nxt = st.copy()
+    orc.jump("xs1024w", S, nxt, 1 << 137, lo=32, hi=64)
+    assert np.array_equal(nxt.view(np.uint32)[32:64], W[64:96])
+    assert not np.array_equal(W[32:64], W[64:96])
+    assert np.all(st[4 * S: 4 * S + 8 * 3].view(np.uint64) == 0)
+    assert np.array_equal(st[-4:], plain[-4:])  # shared Weyl seed
