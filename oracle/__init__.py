@@ -9,7 +9,8 @@ module only marshals numpy buffers.
 
 Kinds are named by string so that the oracle does not depend on the product's
 enum values: "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w",
-"philox4x32_7".
+"philox4x32_7", "lcg32_sub", "lcg64_sub" (sub-stream LCGs sharing one
+sequence).
 """
 from __future__ import annotations
 
@@ -23,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
 SOURCES = [os.path.join(HERE, "rng_oracle.c")]
 
-KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7"]
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7", "lcg32_sub", "lcg64_sub"]
 _CODE = {k: i + 1 for i, k in enumerate(KINDS)}
 OUT_U32, OUT_F32, OUT_XOR = 0, 1, 2
 

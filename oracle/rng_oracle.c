@@ -38,7 +38,14 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_LCG32 = 1, ORC_LCG64, ORC_MWC, ORC_XORWOW, ORC_PHILOX, ORC_XS1024W, ORC_PHILOX7 };
+enum { ORC_LCG32 = 1, ORC_LCG64, ORC_MWC, ORC_XORWOW, ORC_PHILOX, ORC_XS1024W, ORC_PHILOX7, ORC_LCG32S, ORC_LCG64S };
+/* Sub-stream LCGs (LCG section, eq. lcg_skipping with t = S): the S streams
+ * share one global sequence g_0 = the plain seeding's stream-0 value,
+ * g_{n+1} = a g_n + c.  Stream s starts at g_s and steps S positions at a
+ * time with the S-step map (A_S, C_S), so output k of stream s is
+ * g_{s + (k+1) S}: an interleaved fill out[k S + s] is the global sequence
+ * from position S on.  Image: x[S], then A_S and C_S (u32 for LCG32, u64 for
+ * LCG64). */
 /* Philox4x32 with 10 rounds (ORC_PHILOX) or 7 (ORC_PHILOX7); everything but the
  * round count is shared. */
 #define IS_PHILOX(kind) ((kind) == ORC_PHILOX || (kind) == ORC_PHILOX7)
@@ -93,6 +100,8 @@ size_t orc_state_bytes(int kind, uint64_t S)
     switch (kind) {
     case ORC_LCG32: return 4 * S;
     case ORC_LCG64: return 8 * S;
+    case ORC_LCG32S: return 4 * S + 8;
+    case ORC_LCG64S: return 8 * S + 16;
     case ORC_MWC: return 8 * S;
     case ORC_XORWOW: return 24 * S;
     case ORC_PHILOX:
@@ -104,7 +113,7 @@ size_t orc_state_bytes(int kind, uint64_t S)
 
 static int kind_ok(int kind, uint64_t S)
 {
-    if (kind < ORC_LCG32 || kind > ORC_PHILOX7) return 0;
+    if (kind < ORC_LCG32 || kind > ORC_LCG64S) return 0;
     if (kind == ORC_XS1024W && S % 32 != 0) return 0;
     return 1;
 }
@@ -271,6 +280,16 @@ int orc_seed(int kind, uint64_t S, uint64_t seed, void *st)
     } else if (kind == ORC_LCG64) {
         uint64_t *x = (uint64_t *)b;
         for (uint64_t s = 0; s < S; s++) x[s] = orc_splitmix(seed, 1 + s);
+    } else if (kind == ORC_LCG32S) {
+        uint32_t *x = (uint32_t *)b, g = (uint32_t)orc_splitmix(seed, 1), A = 1, C = 0;
+        for (uint64_t s = 0; s < S; s++) { x[s] = g; g = LCG32_A * g + LCG32_C; }
+        for (uint64_t s = 0; s < S; s++) { A = LCG32_A * A; C = LCG32_A * C + LCG32_C; } /* S steps composed */
+        x[S] = A; x[S + 1] = C;
+    } else if (kind == ORC_LCG64S) {
+        uint64_t *x = (uint64_t *)b, g = orc_splitmix(seed, 1), A = 1, C = 0;
+        for (uint64_t s = 0; s < S; s++) { x[s] = g; g = LCG64_A * g + LCG64_C; }
+        for (uint64_t s = 0; s < S; s++) { A = LCG64_A * A; C = LCG64_A * C + LCG64_C; }
+        x[S] = A; x[S + 1] = C;
     } else if (kind == ORC_MWC) {
         /* x = low word, carry = high word mod (a-1): then 0 <= y < p with
          * p = a*2^32 - 1; y = 0 is a fixed point and is replaced by x = 1. */
@@ -354,6 +373,20 @@ int orc_generate(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, uint6
         for (uint64_t s = lo; s < hi; s++)
             for (uint64_t k = 0; k < count; k++) {
                 x[s] = LCG64_A * x[s] + LCG64_C;
+                emit(mode, out, k, width, s - lo, (uint32_t)(x[s] >> 32));
+            }
+    } else if (kind == ORC_LCG32S) {
+        uint32_t *x = (uint32_t *)b, A = x[S], C = x[S + 1];
+        for (uint64_t s = lo; s < hi; s++)
+            for (uint64_t k = 0; k < count; k++) {
+                x[s] = A * x[s] + C;
+                emit(mode, out, k, width, s - lo, x[s]);
+            }
+    } else if (kind == ORC_LCG64S) {
+        uint64_t *x = (uint64_t *)b, A = x[S], C = x[S + 1];
+        for (uint64_t s = lo; s < hi; s++)
+            for (uint64_t k = 0; k < count; k++) {
+                x[s] = A * x[s] + C;
                 emit(mode, out, k, width, s - lo, (uint32_t)(x[s] >> 32));
             }
     } else if (kind == ORC_MWC) {
@@ -569,6 +602,14 @@ int orc_jump(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, const uin
     } else if (kind == ORC_LCG64) {
         aff64 f = { LCG64_A, LCG64_C }, fn = aff_pow(f, n_le, n_words);
         uint64_t *x = (uint64_t *)b;
+        for (uint64_t s = lo; s < hi; s++) x[s] = fn.a * x[s] + fn.c;
+    } else if (kind == ORC_LCG32S) {
+        uint32_t *x = (uint32_t *)b;
+        aff64 f = { x[S], x[S + 1] }, fn = aff_pow(f, n_le, n_words); /* mod 2^64, reduced below */
+        for (uint64_t s = lo; s < hi; s++) x[s] = (uint32_t)(fn.a * x[s] + fn.c);
+    } else if (kind == ORC_LCG64S) {
+        uint64_t *x = (uint64_t *)b;
+        aff64 f = { x[S], x[S + 1] }, fn = aff_pow(f, n_le, n_words);
         for (uint64_t s = lo; s < hi; s++) x[s] = fn.a * x[s] + fn.c;
     } else if (kind == ORC_MWC) {
         uint64_t p = (MWC_A << 32) - 1, an = 1, sq = MWC_A;

@@ -224,3 +224,26 @@ def test_seeding_distinct_and_deterministic(orc):
         assert np.array_equal(a, b) and not np.array_equal(a, c)
         out = orc.generate(kind, S, a, 4)
         assert len(set(out[0].tolist())) > S - 4  # streams do not coincide
+
+
+@pytest.mark.parametrize("kind,S", [("lcg32_sub", 37), ("lcg32_sub", 64), ("lcg64_sub", 37)])
+def test_substream_lcg_is_the_global_sequence(orc, kind, S):
+    # eq. lcg_skipping with t = S: an interleaved fill of the S streams is the
+    # one global sequence from position S on (serial LCG written out here)
+    bits = 32 if kind == "lcg32_sub" else 64
+    a, c = (1664525, 1013904223) if bits == 32 else (2862933555777941757, 1442695040888963407)
+    m = (1 << bits) - 1
+    plain = orc.seed(kind.replace("_sub", ""), S, 7)
+    g = int(plain.view(np.uint32 if bits == 32 else np.uint64)[0])  # g_0: the plain stream-0 value
+    seq = []
+    for _ in range(S * 9):
+        seq.append(g)
+        g = (a * g + c) & m
+    st = orc.seed(kind, S, 7)
+    words = st.view(np.uint32 if bits == 32 else np.uint64)
+    assert [int(v) for v in words[:S]] == seq[:S]
+    A, C = int(words[S]), int(words[S + 1])
+    assert A == pow(a, S, 1 << bits) and C == sum(c * pow(a, i, 1 << bits) for i in range(S)) & m
+    out = orc.generate(kind, S, st, 8).ravel()
+    want = np.array([v if bits == 32 else v >> 32 for v in seq[S:9 * S]], dtype=np.uint64)
+    assert np.array_equal(out.astype(np.uint64), want)

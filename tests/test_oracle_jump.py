@@ -9,7 +9,8 @@ parts, and Philox's counter.
 import numpy as np
 import pytest
 
-KIND_S = {"lcg32": 5, "lcg64": 5, "mwc": 5, "xorwow": 5, "philox4x32_10": 5, "xs1024w": 64}
+KIND_S = {"lcg32": 5, "lcg64": 5, "mwc": 5, "xorwow": 5, "philox4x32_10": 5, "xs1024w": 64, "philox4x32_7": 5,
+          "lcg32_sub": 5, "lcg64_sub": 5}
 
 
 @pytest.mark.parametrize("kind", list(KIND_S))
