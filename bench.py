@@ -188,20 +188,20 @@ def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_units=64):
             "per_launch_requests": baseline_units, "per_launch_gsamples_s": round(sub / base_s / 1e9, 3)}
 
 
-def bench_serve(rx, n_req=5000, rate=2000.0, clients=64, slots=8, inflight=32, seed=1, budget=64 << 30):
+def bench_serve(rx, n_req=20000, rate=2000.0, clients=64, slots=8, inflight=32, seed=1, budget=64 << 30):
     """Poisson arrivals (numpy default_rng(seed)); 90% fills (kind uniform over
-    the six, count = floor(2^(10 + 18 u)), u32/f32 half each), 10% Ising jobs
+    every kind, count = floor(2^(10 + 18 u)), u32/f32 half each), 10% Ising jobs
     (L in {64, ..., 2048} powers of two, 100 sweeps, beta uniform in
     [0.3, 0.6], kind uniform).  Latency = submission to completion."""
     import threading
     import numpy as np
     rng = np.random.default_rng(seed)
-    kinds = list(rx.KINDS)
+    kinds = [k for k in rx.KINDS if not k.endswith("_sub")]  # sub-stream LCGs are not served
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     reqs = []
     for i in range(n_req):
         c = int(rng.integers(clients))
-        k = kinds[int(rng.integers(6))]
+        k = kinds[int(rng.integers(len(kinds)))]
         if rng.random() < 0.9:
             reqs.append(("fill", c, k, int(2 ** (10 + 18 * rng.random())), bool(rng.random() < 0.5)))
         else:
@@ -364,7 +364,9 @@ def main():
             print(f"# ising L=4096 {kind}: {ising[kind]}", file=sys.stderr, flush=True)
         parts["ising_L4096_beta0.4"] = ising
         beta_c = math.log(1 + math.sqrt(2)) / 2
-        parts["ising_L4096_betac"] = {"xs1024w": bench_ising(rx, "xs1024w", 4096, args.ising_sweeps, beta_c)}
+        parts["ising_L4096_betac"] = {
+            kind: bench_ising(rx, kind, 4096, args.ising_sweeps if kind == "xs1024w" else max(100, args.ising_sweeps // 10),
+                              beta_c) for kind in KINDS}
         print(f"# ising L=4096 xs1024w beta_c: {parts['ising_L4096_betac']}", file=sys.stderr, flush=True)
         mh = {"k2": {k: bench_ising(rx, k, 4096, 200, hits=2) for k in KINDS},
               "k100": {k: bench_ising(rx, k, 4096, 10, hits=100) for k in KINDS}}

@@ -48,6 +48,11 @@
  *   XS1024W  word i of instance g = low32 (i even) / high32 (i odd) of
  *            SM(1 + 16 g + i/2); Weyl seed y0 = high32(SM(0)) shared by all
  *            instances; step counter 0
+ *   LCG32_SUB / LCG64_SUB: one global sequence g_0 = the LCG32 / LCG64
+ *            stream-0 value above, g_{n+1} = a g_n + c; stream s starts at
+ *            g_s and steps S positions with the S-step map (A_S, C_S), so
+ *            output k of stream s is g_{s + (k+1) S} and an interleaved fill
+ *            is the global sequence from position S on
  *
  * Checkpoint image (rng_get_state / rng_set_state), little-endian,
  * structure of arrays:
@@ -57,6 +62,9 @@
  *   PHILOX   u32 k0[S] k1[S] u64 pos[S]  (pos = outputs consumed)
  *   XS1024W  u32 W[S] (W[32g+i] = word i of instance g, word 0 most
  *            significant) u64 n[S/32] (steps taken) u32 y0
+ *   LCG32_SUB u32 x[S], u32 A_S, u32 C_S   LCG64_SUB u64 x[S], u64 A_S, C_S
+ *            (rng_set_state refuses an image whose (A_S, C_S) is not the
+ *            handle's, with RNGX_E_STATE)
  */
 #ifndef RNGX_H
 #define RNGX_H
@@ -75,7 +83,9 @@ typedef enum {
     RNGX_XORWOW = 4,        /* 160-bit xorshift (2,1,4) + Weyl d += 362437; out d + v (XORShift sec.) */
     RNGX_PHILOX4X32_10 = 5, /* counter-based Philox4x32, 10 rounds (counter-based section)         */
     RNGX_XS1024W = 6,       /* the paper's XORShift-1024 (329,347,344) + Weyl (XORShift section)    */
-    RNGX_PHILOX4X32_7 = 7   /* Philox4x32 with 7 rounds (counter-based section); otherwise as 5     */
+    RNGX_PHILOX4X32_7 = 7,  /* Philox4x32 with 7 rounds (counter-based section); otherwise as 5     */
+    RNGX_LCG32_SUB = 8,     /* LCG32 sub-streams of one sequence (eq. lcg_skipping, t = S), below   */
+    RNGX_LCG64_SUB = 9      /* LCG64 sub-streams of one sequence, as 8                              */
 } rngx_kind;
 
 typedef enum {
@@ -323,6 +333,8 @@ rngx_status ising_batch_destroy(rngx_ising_batch b);
  * one kind run in submission order; results depend only on the client's own
  * requests, not on what else is served.  The server allocates its budget
  * once; no request allocates device memory.
+ *   (kinds: every kind but the sub-stream LCGs, whose streams only exist as
+ *   parts of one S-stream sequence: RNGX_E_INVALID)
  *   srv_submit_fill:  the next `count` (<= 2^28) outputs of the (client, kind)
  *     stream, contiguous (XS1024W: the instance's values in warp order), as
  *     uint32 or as FP32 (u >> 8) * 2^-24 if as_f32.  Long requests are cut

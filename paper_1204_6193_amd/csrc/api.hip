@@ -101,6 +101,11 @@ rngx_status alloc_gen(rngx_kind kind, uint64_t S, Gen **out) {
     g->kind = kind;
     g->S = S;
     g->state_bytes = state_bytes(kind, S);
+    if (is_sub_lcg(kind)) {
+        affine_power(kind == RNGX_LCG32_SUB ? kLcg32A : kLcg64A, kind == RNGX_LCG32_SUB ? kLcg32C : kLcg64C, S,
+                     &g->sub_a, &g->sub_c);
+        if (kind == RNGX_LCG32_SUB) { g->sub_a &= 0xFFFFFFFFull; g->sub_c &= 0xFFFFFFFFull; }
+    }
     if (hipGetDevice(&g->device) != hipSuccess) { delete g; return fail(RNGX_E_HIP, "hipGetDevice failed"); }
     hipError_t e = hipMalloc(&g->d_state, g->state_bytes);
     if (e != hipSuccess) {
@@ -178,12 +183,14 @@ size_t state_bytes(rngx_kind kind, uint64_t S) {
     case RNGX_XORWOW: return 24 * S;
     case RNGX_PHILOX4X32_10:
     case RNGX_PHILOX4X32_7: return 16 * S;
+    case RNGX_LCG32_SUB: return 4 * S + 8;
+    case RNGX_LCG64_SUB: return 8 * S + 16;
     case RNGX_XS1024W: return 4 * S + 8 * (S / 32) + 4;
     }
     return 0;
 }
 
-bool kind_valid(int kind) { return kind >= RNGX_LCG32 && kind <= RNGX_PHILOX4X32_7; }
+bool kind_valid(int kind) { return kind >= RNGX_LCG32 && kind <= RNGX_LCG64_SUB; }
 
 rngx_status fail(rngx_status st, const std::string &msg) { g_error = msg; return st; }
 rngx_status hip_fail(hipError_t e, const char *what) {
@@ -380,7 +387,7 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
     if (items.size() > 0xFFFFFFFFull) return fail(RNGX_E_OVERFLOW, "too many chunks in one ragged plan");
     std::vector<uint64_t> t64;
     std::vector<uint32_t> t32;
-    jump_table(g->kind, plan.step, plan.max_j + 1, &t64, &t32);
+    jump_table_gen(g, plan.step, plan.max_j + 1, &t64, &t32);
     DeviceScope ds(g->device);
     Ragged *r = new Ragged{};
     r->magic = kRaggedMagic;
@@ -463,6 +470,18 @@ rngx_status rng_set_state(rngx_gen h, const void *host_buf, size_t bytes, void *
         return fail(RNGX_E_STATE, "state image has " + std::to_string(bytes) + " bytes, expected " +
                                       std::to_string(g->state_bytes));
     if (rngx_status s = validate_image(g->kind, g->S, static_cast<const uint8_t *>(host_buf))) return s;
+    if (is_sub_lcg(g->kind)) {
+        uint64_t A, C;
+        if (g->kind == RNGX_LCG32_SUB) {
+            const uint32_t *p = static_cast<const uint32_t *>(host_buf);
+            A = p[g->S]; C = p[g->S + 1];
+        } else {
+            const uint64_t *p = static_cast<const uint64_t *>(host_buf);
+            A = p[g->S]; C = p[g->S + 1];
+        }
+        if (A != g->sub_a || C != g->sub_c)
+            return fail(RNGX_E_STATE, "the image's S-step map is not this handle's (sub-stream LCG)");
+    }
     DeviceScope ds(g->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(g->d_state, host_buf, bytes, hipMemcpyHostToDevice, st);
@@ -834,7 +853,8 @@ rngx_status srv_submit_fill(rngx_server h, uint32_t client, rngx_kind kind, uint
     Server *s;
     if (rngx_status st = check_server(h, &s)) return st;
     if (!ticket) return fail(RNGX_E_INVALID, "ticket is NULL");
-    if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind");
+    if (!kind_valid(kind) || is_sub_lcg(kind))
+        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG kinds are not served)");
     if (count == 0) return fail(RNGX_E_INVALID, "count must be positive");
     if (count > kMaxServedValues) return fail(RNGX_E_OVERFLOW, "count exceeds 2^28");
     if (rngx_status st = server_submit_fill(s, client, kind, count, as_f32, ticket)) return st;
@@ -847,7 +867,8 @@ rngx_status srv_submit_ising(rngx_server h, uint32_t client, rngx_kind kind, uin
     Server *s;
     if (rngx_status st = check_server(h, &s)) return st;
     if (!ticket) return fail(RNGX_E_INVALID, "ticket is NULL");
-    if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind");
+    if (!kind_valid(kind) || is_sub_lcg(kind))
+        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG kinds are not served)");
     if (L < 16 || L % 16) return fail(RNGX_E_ALIGN, "L must be a multiple of 16 and at least 16");
     if (L > kMaxL) return fail(RNGX_E_OVERFLOW, "L must not exceed 16384");
     if (!std::isfinite(beta) || beta < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");

@@ -26,6 +26,24 @@ __global__ __launch_bounds__(kBlock) void k_seed_small(rngx_kind kind, uint8_t *
     switch (kind) {
     case RNGX_LCG32: u32[s] = static_cast<uint32_t>(splitmix(seed, 1 + s)); break;
     case RNGX_LCG64: u64[s] = splitmix(seed, 1 + s); break;
+    case RNGX_LCG32_SUB:
+    case RNGX_LCG64_SUB: {
+        // stream s at position s of the sequence from the plain stream-0 value;
+        // the S-step map after the states
+        const bool l32 = kind == RNGX_LCG32_SUB;
+        const uint64_t a = l32 ? kLcg32A : kLcg64A, c = l32 ? kLcg32C : kLcg64C;
+        const uint64_t g0 = l32 ? static_cast<uint32_t>(splitmix(seed, 1)) : splitmix(seed, 1);
+        uint64_t A, C;
+        affine_power(a, c, s, &A, &C);
+        if (l32) u32[s] = static_cast<uint32_t>(A * g0 + C);
+        else u64[s] = A * g0 + C;
+        if (s == 0) {
+            affine_power(a, c, S, &A, &C);
+            if (l32) { u32[S] = static_cast<uint32_t>(A); u32[S + 1] = static_cast<uint32_t>(C); }
+            else { u64[S] = A; u64[S + 1] = C; }
+        }
+        break;
+    }
     case RNGX_MWC: {
         const uint64_t z = splitmix(seed, 1 + s);
         uint64_t x = z & 0xFFFFFFFFull, c = (z >> 32) % (kMwcA - 1);
@@ -315,6 +333,8 @@ const void *config_kernel(rngx_kind kind, int mode, const rngx_fill_config &c) {
     case RNGX_XORWOW: return config_kernel<Xorwow>(mode, c);
     case RNGX_PHILOX4X32_10: return config_kernel<Philox>(mode, c);
     case RNGX_PHILOX4X32_7: return config_kernel<Philox7>(mode, c);
+    case RNGX_LCG32_SUB: return config_kernel<Lcg32Sub>(mode, c);
+    case RNGX_LCG64_SUB: return config_kernel<Lcg64Sub>(mode, c);
     case RNGX_XS1024W: return mode == kOutU32 ? xs_kernel<kOutU32>(c.block) : xs_kernel<kOutF32>(c.block);
     }
     return nullptr;
@@ -398,6 +418,8 @@ hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
     case RNGX_XORWOW: return fill_small<Xorwow, MODE>(g, out, count, st);
     case RNGX_PHILOX4X32_10: return fill_small<Philox, MODE>(g, out, count, st);
     case RNGX_PHILOX4X32_7: return fill_small<Philox7, MODE>(g, out, count, st);
+    case RNGX_LCG32_SUB: return fill_small<Lcg32Sub, MODE>(g, out, count, st);
+    case RNGX_LCG64_SUB: return fill_small<Lcg64Sub, MODE>(g, out, count, st);
     case RNGX_XS1024W: return fill_xs<MODE>(g, out, count, st);
     }
     return hipErrorInvalidValue;

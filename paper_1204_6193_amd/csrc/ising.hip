@@ -1033,7 +1033,9 @@ const void *batch_kernel() { return reinterpret_cast<const void *>(&k_ising_batc
 const void *batch_kernel_for(rngx_kind kind) {
     switch (kind) {
     case RNGX_LCG32: return batch_kernel<SmallUnit<Lcg32>>();
+    case RNGX_LCG32_SUB: return batch_kernel<SmallUnit<Lcg32Sub>>();
     case RNGX_LCG64: return batch_kernel<SmallUnit<Lcg64>>();
+    case RNGX_LCG64_SUB: return batch_kernel<SmallUnit<Lcg64Sub>>();
     case RNGX_MWC: return batch_kernel<SmallUnit<Mwc>>();
     case RNGX_XORWOW: return batch_kernel<SmallUnit<Xorwow>>();
     case RNGX_PHILOX4X32_10: return batch_kernel<PhiloxUnit>();
@@ -1133,7 +1135,9 @@ hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
     const dim3 grid(b->grid), block(kBatchThreads);
     switch (b->kind) {
     case RNGX_LCG32: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg32>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
+    case RNGX_LCG32_SUB: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg32Sub>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     case RNGX_LCG64: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg64>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
+    case RNGX_LCG64_SUB: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg64Sub>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     case RNGX_MWC: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Mwc>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     case RNGX_XORWOW: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Xorwow>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
     case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ising_batch<PhiloxUnit>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
@@ -1163,7 +1167,9 @@ int list_plans(uint32_t L, int max_spt, int n_cu, IsingPlan *out, int max) {
 int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int max) {
     switch (kind) {
     case RNGX_LCG32: return list_plans<SmallUnit<Lcg32>>(L, 16, n_cu, out, max);
+    case RNGX_LCG32_SUB: return list_plans<SmallUnit<Lcg32Sub>>(L, 16, n_cu, out, max);
     case RNGX_LCG64: return list_plans<SmallUnit<Lcg64>>(L, 16, n_cu, out, max);
+    case RNGX_LCG64_SUB: return list_plans<SmallUnit<Lcg64Sub>>(L, 16, n_cu, out, max);
     case RNGX_MWC: return list_plans<SmallUnit<Mwc>>(L, 16, n_cu, out, max);
     case RNGX_XORWOW: return list_plans<SmallUnit<Xorwow>>(L, 16, n_cu, out, max);
     case RNGX_PHILOX4X32_10: return list_plans<PhiloxUnit>(L, 16, n_cu, out, max);
@@ -1176,7 +1182,9 @@ int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int ma
 bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
     switch (kind) {
     case RNGX_LCG32: return plan_strips<SmallUnit<Lcg32>>(L, 16, n_cu, out);
+    case RNGX_LCG32_SUB: return plan_strips<SmallUnit<Lcg32Sub>>(L, 16, n_cu, out);
     case RNGX_LCG64: return plan_strips<SmallUnit<Lcg64>>(L, 16, n_cu, out);
+    case RNGX_LCG64_SUB: return plan_strips<SmallUnit<Lcg64Sub>>(L, 16, n_cu, out);
     case RNGX_MWC: return plan_strips<SmallUnit<Mwc>>(L, 16, n_cu, out);
     case RNGX_XORWOW: return plan_strips<SmallUnit<Xorwow>>(L, 16, n_cu, out);
     case RNGX_PHILOX4X32_10: return plan_strips<PhiloxUnit>(L, 16, n_cu, out);
@@ -1208,7 +1216,9 @@ hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_t
     const uint64_t T8 = static_cast<uint64_t>(std::floor(std::exp(-8.0 * beta) * 4294967296.0));
     switch (lat->gen->kind) {
     case RNGX_LCG32: return run<SmallUnit<Lcg32>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_LCG32_SUB: return run<SmallUnit<Lcg32Sub>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_LCG64: return run<SmallUnit<Lcg64>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_LCG64_SUB: return run<SmallUnit<Lcg64Sub>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_MWC: return run<SmallUnit<Mwc>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_XORWOW: return run<SmallUnit<Xorwow>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_PHILOX4X32_10: return run<PhiloxUnit>(lat, T4, T8, n_sweeps, d_trace, st, hits);

@@ -302,9 +302,37 @@ void jump_table(rngx_kind kind, uint64_t step, uint64_t count, std::vector<uint6
     }
 }
 
+void jump_table_gen(const Gen *g, uint64_t step, uint64_t count, std::vector<uint64_t> *u64s,
+                    std::vector<uint32_t> *u32s) {
+    if (!is_sub_lcg(g->kind)) { jump_table(g->kind, step, count, u64s, u32s); return; }
+    // sub-stream LCGs: powers of the handle's S-step map
+    u64s->clear();
+    u32s->clear();
+    const Aff fs = aff_pow(Aff{g->sub_a, g->sub_c}, step);
+    Aff cur{1, 0};
+    for (uint64_t j = 0; j < count; ++j) {
+        u64s->push_back(cur.a);
+        u64s->push_back(cur.c);
+        cur = aff_after(fs, cur);
+    }
+}
+
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st) {
     const uint64_t S = g->S;
     switch (g->kind) {
+    case RNGX_LCG32_SUB: {
+        const Aff f = aff_pow({g->sub_a, g->sub_c}, n);  // mod 2^64 reduces correctly mod 2^32
+        hipLaunchKernelGGL(k_skip_affine32, dim3(blocks_for(S)), dim3(kBlock), 0, st,
+                           reinterpret_cast<uint32_t *>(g->d_state), S, static_cast<uint32_t>(f.a),
+                           static_cast<uint32_t>(f.c));
+        break;
+    }
+    case RNGX_LCG64_SUB: {
+        const Aff f = aff_pow({g->sub_a, g->sub_c}, n);
+        hipLaunchKernelGGL(k_skip_affine64, dim3(blocks_for(S)), dim3(kBlock), 0, st,
+                           reinterpret_cast<uint64_t *>(g->d_state), S, f.a, f.c);
+        break;
+    }
     case RNGX_LCG32: {
         const Aff f = aff_pow({kLcg32A, kLcg32C}, n);  // mod 2^64 reduces correctly mod 2^32
         hipLaunchKernelGGL(k_skip_affine32, dim3(blocks_for(S)), dim3(kBlock), 0, st,

@@ -105,12 +105,26 @@ __global__ __launch_bounds__(kBlock) void k_ragged_start_small(rngx_kind kind, c
     const RaggedItem it = items[i];
     const uint64_t s = it.unit, j = it.j;
     switch (kind) {
+    case RNGX_LCG32_SUB:  // the S-step map goes after the chunk states, as in the image
+        if (i == 0) {
+            const uint32_t *h = reinterpret_cast<const uint32_t *>(st) + S;
+            reinterpret_cast<uint32_t *>(scratch)[n_items] = h[0];
+            reinterpret_cast<uint32_t *>(scratch)[n_items + 1] = h[1];
+        }
+        [[fallthrough]];
     case RNGX_LCG32: {
         const uint32_t x = reinterpret_cast<const uint32_t *>(st)[s];
         reinterpret_cast<uint32_t *>(scratch)[i] =
             static_cast<uint32_t>(t64[2 * j]) * x + static_cast<uint32_t>(t64[2 * j + 1]);
         break;
     }
+    case RNGX_LCG64_SUB:
+        if (i == 0) {
+            const uint64_t *h = reinterpret_cast<const uint64_t *>(st) + S;
+            reinterpret_cast<uint64_t *>(scratch)[n_items] = h[0];
+            reinterpret_cast<uint64_t *>(scratch)[n_items + 1] = h[1];
+        }
+        [[fallthrough]];
     case RNGX_LCG64: {
         const uint64_t x = reinterpret_cast<const uint64_t *>(st)[s];
         reinterpret_cast<uint64_t *>(scratch)[i] = t64[2 * j] * x + t64[2 * j + 1];
@@ -471,6 +485,8 @@ hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st) {
     case RNGX_XORWOW: hipLaunchKernelGGL(k_ragged_gen_small<Xorwow>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ragged_gen_small<Philox>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_ragged_gen_small<Philox7>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    case RNGX_LCG32_SUB: hipLaunchKernelGGL(k_ragged_gen_small<Lcg32Sub>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    case RNGX_LCG64_SUB: hipLaunchKernelGGL(k_ragged_gen_small<Lcg64Sub>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     default: break;
     }
     return hipGetLastError();

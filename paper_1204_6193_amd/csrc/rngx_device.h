@@ -57,6 +57,42 @@ struct Lcg64 {
     __device__ uint32_t next() { x = kLcg64A * x + kLcg64C; return static_cast<uint32_t>(x >> 32); }
 };
 
+// n-step map of x -> a x + c modulo 2^64 (also right modulo 2^32 in its low
+// words), by repeated squaring.
+__host__ __device__ inline void affine_power(uint64_t a, uint64_t c, uint64_t n, uint64_t *A, uint64_t *C) {
+    uint64_t ra = 1, rc = 0;
+    for (; n; n >>= 1) {
+        if (n & 1) { rc = a * rc + c; ra = a * ra; }
+        c = a * c + c;
+        a = a * a;
+    }
+    *A = ra;
+    *C = rc;
+}
+
+// Sub-stream LCGs (eq. lcg_skipping with t = S): every stream steps S
+// positions of one global sequence with the S-step map (A, C), kept after the
+// S states in the image (u32 pair for LCG32, u64 pair for LCG64).
+struct Lcg32Sub {
+    uint32_t x, A, C;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t s) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
+        x = p[s]; A = p[S]; C = p[S + 1];
+    }
+    __device__ void store(uint8_t *st, uint64_t, uint64_t s) const { reinterpret_cast<uint32_t *>(st)[s] = x; }
+    __device__ uint32_t next() { x = A * x + C; return x; }
+};
+
+struct Lcg64Sub {
+    uint64_t x, A, C;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t s) {
+        const uint64_t *p = reinterpret_cast<const uint64_t *>(st);
+        x = p[s]; A = p[S]; C = p[S + 1];
+    }
+    __device__ void store(uint8_t *st, uint64_t, uint64_t s) const { reinterpret_cast<uint64_t *>(st)[s] = x; }
+    __device__ uint32_t next() { x = A * x + C; return static_cast<uint32_t>(x >> 32); }
+};
+
 struct Mwc {
     uint64_t y;  // carry << 32 | x
     __device__ void load(const uint8_t *st, uint64_t, uint64_t s) { y = reinterpret_cast<const uint64_t *>(st)[s]; }

@@ -31,7 +31,9 @@ struct Gen {
     int n_cu;           // compute units of the device
     int fill_cfg;       // fill configuration (index into the kind's list), -1: default
     int resident[8];    // per configuration: workgroups that fit at once, -1: not known yet
+    uint64_t sub_a, sub_c;  // sub-stream LCG kinds: the S-step map (A_S, C_S) of the image header
 };
+inline bool is_sub_lcg(rngx_kind k) { return k == RNGX_LCG32_SUB || k == RNGX_LCG64_SUB; }
 constexpr int kMaxFillConfigs = 8;
 
 // One chunk of one stream's (XS1024W: one instance's) ragged request.
@@ -135,6 +137,9 @@ hipError_t launch_substreams(Gen *g, hipStream_t st);  // XS1024W: instance g sk
 //  PHILOX: empty (the counter jumps by j step).
 void jump_table(rngx_kind kind, uint64_t step, uint64_t count, std::vector<uint64_t> *u64s,
                 std::vector<uint32_t> *u32s);
+// As jump_table, for a handle (sub-stream LCG kinds use the handle's S-step map).
+void jump_table_gen(const Gen *g, uint64_t step, uint64_t count, std::vector<uint64_t> *u64s,
+                    std::vector<uint32_t> *u32s);
 hipError_t launch_hot_start(Ising *lat, uint64_t seed, hipStream_t st);
 hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_trace, hipStream_t st,
                         uint32_t hits = 1);  // hits: Metropolis updates per visited site

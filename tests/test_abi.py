@@ -45,7 +45,7 @@ def test_create_validation(rngx):
     lib = rngx.load()
     h = ctypes.c_void_p()
     assert lib.rng_create(0, 16, 1, ctypes.byref(h)) == -1
-    assert lib.rng_create(8, 16, 1, ctypes.byref(h)) == -1
+    assert lib.rng_create(10, 16, 1, ctypes.byref(h)) == -1
     assert lib.rng_create(1, 0, 1, ctypes.byref(h)) == -1
     assert lib.rng_create(6, 48, 1, ctypes.byref(h)) == -2 and "% 32" in _err(lib)
     assert lib.rng_create(1, (1 << 36) + 1, 1, ctypes.byref(h)) == -5
@@ -79,14 +79,14 @@ def test_fill_configuration_lists(rngx):
     lib = rngx.load()
     small = rngx.rng_fill_configs("lcg32")
     assert len(small) == 7 and small[0] == (1, 4, 512) and (0, 4, 256) in small
-    for kind in ("lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7"):
+    for kind in ("lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7", "lcg32_sub", "lcg64_sub"):
         assert rngx.rng_fill_configs(kind) == small
     xs = rngx.rng_fill_configs("xs1024w")
     assert len(xs) == 4 and all(v == 2 for _, v, _ in xs) and xs[0] == (1, 2, 1024)
     for paced, v, block in small + xs:
         assert paced in (0, 1) and v in (2, 4) and block in (256, 512, 1024)
     n = ctypes.c_int()
-    assert lib.rng_fill_configs(9, None, ctypes.byref(n)) == -1
+    assert lib.rng_fill_configs(10, None, ctypes.byref(n)) == -1
     assert lib.rng_fill_configs(1, None, None) == -1
     bogus = ctypes.c_void_p(0x1234560)
     assert lib.rng_set_fill_config(bogus, 0) == -1

@@ -13,7 +13,7 @@ from oracle import exact_ising as ex
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7"]
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7", "lcg32_sub", "lcg64_sub"]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -374,3 +374,23 @@ def test_multihit_statistics(rngx):
           f"C={c:.5f}+-{sc:.5f} z={(c - ce) / sc:+.2f}", flush=True)
     assert abs(e - ee) < 3 * se
     assert abs(c - ce) < 3 * sc
+
+
+def test_substream_lcg32_fails_the_ising_test(rngx):
+    """Table 2's checkerboard rows at L = 1024, beta = 0.4: LCG32 drawn as
+    sub-streams of one sequence (eq. lcg_skipping with t = S) misses the exact
+    energy by many standard errors, LCG32 with per-stream seeds does not."""
+    L, beta, n_eq, n_meas = 1024, 0.4, 2000, 20000
+    ee, ce = _exact(L, beta)
+    z = {}
+    for kind in ("lcg32_sub", "lcg32", "lcg64_sub"):
+        lat = rngx.ising_create(L, kind, 1)
+        rngx.ising_sweep(lat, beta, n_eq)
+        tr = torch.zeros(n_meas, dtype=torch.int32, device="cuda")
+        rngx.ising_sweep(lat, beta, n_meas, tr)
+        e, se, c, sc = isingstats.estimates(tr.cpu().numpy(), L * L, beta)
+        z[kind] = ((e - ee) / se, (c - ce) / sc)
+        print(f"stat table2 {kind:10s} L={L} e={e:.7f}+-{se:.7f} z={z[kind][0]:+.1f} "
+              f"C={c:.5f}+-{sc:.5f} z={z[kind][1]:+.1f}", flush=True)
+    assert abs(z["lcg32_sub"][0]) > 20
+    assert abs(z["lcg32"][0]) < 4 and abs(z["lcg32"][1]) < 4

@@ -40,6 +40,8 @@ def test_server_fills_equal_direct_fills(rngx, orc):
         (rngx.rng_fill_f32 if f else rngx.rng_fill_u32)(gens[(c, k)], out, steps)
         want = out.cpu().numpy().view(np.uint32)[:n]
         assert np.array_equal(host.view(np.uint32), want), (c, k, n, f)
+    with pytest.raises(rngx.RngxError):  # sub-stream LCGs are parts of one S-stream sequence
+        srv.submit_fill(1, "lcg32_sub", 10, False)
     srv.destroy()
 
 
