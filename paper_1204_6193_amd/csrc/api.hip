@@ -76,6 +76,7 @@ void free_ragged(Ragged *r) {
     (void)hipFree(r->d_t64);
     (void)hipFree(r->d_t32);
     (void)hipFree(r->d_slots);
+    (void)hipFree(r->d_lane);
     r->magic = 0;
     delete r;
 }
@@ -399,6 +400,16 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
     hipError_t e = hipSuccess;
     if (!items.empty()) {
         e = hipMalloc(&r->d_items, sizeof(RaggedItem) * items.size());
+        if (e == hipSuccess && ragged_affine(g->kind)) {
+            // lane i starts i+1 steps into its chunk; entry 64: the 64-step advance
+            uint64_t a = g->kind == RNGX_LCG32 ? kLcg32A : g->kind == RNGX_LCG64 ? kLcg64A : g->sub_a;
+            uint64_t c = g->kind == RNGX_LCG32 ? kLcg32C : g->kind == RNGX_LCG64 ? kLcg64C : g->sub_c;
+            std::vector<uint64_t> lane(130);
+            for (int i = 0; i < 64; ++i) affine_power(a, c, i + 1, &lane[2 * i], &lane[2 * i + 1]);
+            affine_power(a, c, 64, &lane[128], &lane[129]);
+            e = hipMalloc(&r->d_lane, 8 * lane.size());
+            if (e == hipSuccess) e = hipMemcpy(r->d_lane, lane.data(), 8 * lane.size(), hipMemcpyHostToDevice);
+        }
         if (e == hipSuccess && !plan.slots.empty()) e = hipMalloc(&r->d_slots, 4 * plan.slots.size());
         if (e == hipSuccess && !plan.slots.empty())
             e = hipMemcpy(r->d_slots, plan.slots.data(), 4 * plan.slots.size(), hipMemcpyHostToDevice);

@@ -94,6 +94,57 @@ __global__ __launch_bounds__(kBlock) void k_ragged_gen_small(const RaggedItem *i
     if (mine && it.last) g.store(st, S, it.unit);
 }
 
+// Affine kinds (LCG32, LCG64 and their sub-stream forms): one wave per
+// chunk, leapfrogging.  The wave's stores are aligned to 64-word (256-byte)
+// spans of the output: in step k lane i writes word A + 64 k + i, A being the
+// chunk's first word rounded down to a multiple of 64, i.e. chunk position
+// p = 64 k + i - mis (mis = first word - A).  A lane starts at its first
+// position p0 (the (p0+1)-step map from the chunk's start state, lane_maps[p0];
+// lane_maps[64] is the 64-step map) and advances 64 steps per store; spans
+// inside the chunk are whole and written non-temporally, the chunk's first
+// and last spans word by word.  The streams' states are only read here; the
+// lane that writes a stream's last value puts the final state in
+// scratch[item] for k_ragged_commit_affine.
+template <bool L64>
+__global__ __launch_bounds__(kBlock) void k_ragged_affine(const RaggedItem *items, uint64_t n_items,
+                                                           const uint64_t *t64, const uint64_t *lane_maps,
+                                                           const uint8_t *st, uint64_t *scratch, uint32_t *out) {
+    const uint64_t q = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    if (q >= n_items) return;  // whole waves
+    const RaggedItem it = items[q];
+    const uint64_t x0 = L64 ? reinterpret_cast<const uint64_t *>(st)[it.unit]
+                            : reinterpret_cast<const uint32_t *>(st)[it.unit];
+    const uint64_t xc = t64[2 * it.j] * x0 + t64[2 * it.j + 1];  // state at the chunk's start
+    const uint32_t mis = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out) >> 2) + it.out) & 63;
+    const uint32_t p0 = (lane + 64 - mis) & 63;
+    uint64_t x = lane_maps[2 * p0] * xc + lane_maps[2 * p0 + 1];
+    const uint64_t Am = lane_maps[128], Cm = lane_maps[129];
+    const int64_t len = it.len;
+    const uint32_t kend = static_cast<uint32_t>((len + mis + 63) >> 6);
+    uint32_t *o = out + (it.out - mis) + lane;
+    for (uint32_t k = 0; k < kend; ++k) {
+        const int64_t p = 64 * static_cast<int64_t>(k) + lane - mis;
+        const uint32_t v = L64 ? static_cast<uint32_t>(x >> 32) : static_cast<uint32_t>(x);
+        if (64 * static_cast<int64_t>(k) >= mis && 64 * static_cast<int64_t>(k) + 64 - mis <= len)
+            __builtin_nontemporal_store(v, o);  // a whole span
+        else if (p >= 0 && p < len)
+            *o = v;
+        if (it.last && p == len - 1) scratch[q] = x;
+        if (p >= 0) x = Am * x + Cm;
+        o += 64;
+    }
+}
+
+template <bool L64>
+__global__ __launch_bounds__(kBlock) void k_ragged_commit_affine(const RaggedItem *items, uint64_t n_items,
+                                                                  const uint64_t *scratch, uint8_t *st) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_items || !items[i].last) return;
+    if (L64) reinterpret_cast<uint64_t *>(st)[items[i].unit] = scratch[i];
+    else reinterpret_cast<uint32_t *>(st)[items[i].unit] = static_cast<uint32_t>(scratch[i]);
+}
+
 // Start states of the chunks of the small-state kinds, written to scratch in
 // the kind's structure-of-arrays layout with n_items streams.
 __global__ __launch_bounds__(kBlock) void k_ragged_start_small(rngx_kind kind, const RaggedItem *items,
@@ -377,7 +428,12 @@ hipError_t launch_stream_fill(rngx_kind kind, const uint8_t *st_in, uint8_t *st_
     return hipGetLastError();
 }
 
-uint64_t ragged_chunk(rngx_kind) { return 4096; }
+bool ragged_affine(rngx_kind kind) {
+    return kind == RNGX_LCG32 || kind == RNGX_LCG64 || kind == RNGX_LCG32_SUB || kind == RNGX_LCG64_SUB;
+}
+
+// outputs per chunk: a lane's (4096) or, for the affine kinds, a wave's
+uint64_t ragged_chunk(rngx_kind kind) { return ragged_affine(kind) ? 65536 : 4096; }
 
 void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan) {
     std::vector<RaggedItem> &items = plan->items;
@@ -461,6 +517,7 @@ void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu
 }
 
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items) {
+    if (ragged_affine(kind)) return 8 * n_items;  // final states
     return kind == RNGX_XS1024W ? 136 * n_items : state_bytes(kind, n_items);
 }
 
@@ -474,6 +531,22 @@ hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st) {
                            r->d_slots, r->n_slots, g->d_state, g->S, r->d_t32, C, r->d_scratch, d_out);
         hipLaunchKernelGGL(k_ragged_commit_xs, dim3(blocks_for(16 * n)), dim3(kBlock), 0, st, r->d_items, n,
                            r->d_scratch, g->d_state, g->S);
+        return hipGetLastError();
+    }
+    if (ragged_affine(g->kind)) {
+        const bool l64 = g->kind == RNGX_LCG64 || g->kind == RNGX_LCG64_SUB;
+        uint64_t *scr = reinterpret_cast<uint64_t *>(r->d_scratch);
+        if (l64) {
+            hipLaunchKernelGGL(k_ragged_affine<true>, dim3(blocks_for(64 * n)), dim3(kBlock), 0, st, r->d_items, n,
+                               r->d_t64, r->d_lane, g->d_state, scr, d_out);
+            hipLaunchKernelGGL(k_ragged_commit_affine<true>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n,
+                               scr, g->d_state);
+        } else {
+            hipLaunchKernelGGL(k_ragged_affine<false>, dim3(blocks_for(64 * n)), dim3(kBlock), 0, st, r->d_items, n,
+                               r->d_t64, r->d_lane, g->d_state, scr, d_out);
+            hipLaunchKernelGGL(k_ragged_commit_affine<false>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n,
+                               scr, g->d_state);
+        }
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_ragged_start_small, dim3(blocks_for(n)), dim3(kBlock), 0, st, g->kind, r->d_items, n,

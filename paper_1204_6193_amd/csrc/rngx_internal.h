@@ -57,6 +57,7 @@ struct Ragged {
     uint64_t step;       // jump table step: chunk j starts j*step outputs (steps) in
     uint32_t n_slots;    // XS1024W: rows of the generation kernel
     uint32_t *d_slots;   // XS1024W: first item of each row, n_slots + 1 entries
+    uint64_t *d_lane;    // affine kinds: (i+1)-step maps for lanes i = 0..63, then the 64-step map
 };
 
 // How a lattice is swept: as strips held on chip by co-resident
@@ -162,6 +163,7 @@ struct RaggedPlan {
 constexpr uint32_t kXsRowsPerCu = 128;      // 8 waves per SIMD x 4 SIMDs x 4 rows
 constexpr uint64_t kXsMinSlotSteps = 2048;  // slots are not cut finer than this
 uint64_t ragged_chunk(rngx_kind kind);
+bool ragged_affine(rngx_kind kind);  // LCG32/LCG64 and sub-stream forms: one wave per chunk
 void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan);
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items);
 hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st);

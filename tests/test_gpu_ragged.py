@@ -13,9 +13,11 @@ def _lengths(kind, n_units, seed):
     lens = np.floor(2.0 ** rng.uniform(0, 14, size=n_units)).astype(np.int64)
     lens[0] = 0                                  # an empty request
     lens[1] = 1
-    lens[-1] = 600_000 if kind == "xs1024w" else 20_000   # several chunks
+    lens[-1] = 600_000 if kind == "xs1024w" else 200_000  # several chunks
     if kind == "xs1024w":
         lens[2] = 262_144 + 31                   # one full chunk and a partial step
+    else:
+        lens[2], lens[3] = 65_536, 128           # a whole wave chunk, whole 64-value steps
     return lens
 
 
