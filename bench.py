@@ -307,7 +307,7 @@ def main():
                          "(energy trace on); prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent streams shard by index range with no communication).", file=sys.stderr)
         sys.exit(2)
 
