@@ -58,9 +58,11 @@ def test_ragged_parity(rngx, orc, kind):
     assert np.array_equal(u.cpu().numpy().view(np.uint32).reshape(5, S), orc.generate(kind, S, st, 5))
 
 
-def test_ragged_graph_replay(rngx, orc):
-    kind, S = "xs1024w", 256
-    lens = _lengths(kind, S // 32, 8)
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
+def test_ragged_graph_replay(rngx, orc, kind):
+    print(f"case ragged graph {kind}", flush=True)
+    S = 256 if kind == "xs1024w" else 37
+    lens = _lengths(kind, S // 32 if kind == "xs1024w" else S, 8)
     off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
     ga, gb = rngx.rng_create(kind, S, 2), rngx.rng_create(kind, S, 2)
     pa, pb = rngx.rng_ragged_create(ga, off), rngx.rng_ragged_create(gb, off)
