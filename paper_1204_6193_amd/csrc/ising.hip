@@ -1025,7 +1025,7 @@ hipError_t run(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hi
 }
 
 constexpr uint32_t kBatchLdsCap = 80 * 1024;  // keeps two batch workgroups per CU
-constexpr uint32_t kMaxGang = 32;             // most strips of one batch replica
+constexpr uint32_t kMaxGang = 64;             // most strips of one batch replica
 
 template <class Unit>
 const void *batch_kernel() { return reinterpret_cast<const void *>(&k_ising_batch<Unit>); }

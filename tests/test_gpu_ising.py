@@ -243,10 +243,13 @@ def test_batch_equals_individual_sweeps(rngx, kind):
 @pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
 def test_batch_gangs_and_memory_replicas(rngx, kind):
     """Large replicas run as gangs of strip workgroups (L = 1024: 16 strips;
-    1008, 784: odd strip counts; 272: two) or, beyond the largest gang, in
-    memory (L = 2048); each equals ising_sweep on the lattice alone."""
+    1008, 784: odd strip counts; 272: two; 2048: 64, the largest gang;
+    976 = 16 * 61: XS1024W strips of 16 rows only, 61 of them) or, beyond the
+    largest gang, in memory (L = 4096); each equals ising_sweep on the
+    lattice alone."""
     print(f"case batch gangs {kind}", flush=True)
-    Ls, betas, sweeps = [1024, 1008, 784, 272, 2048, 48], [0.4, 0.35, 0.5, 0.44, 0.41, 0.3], [3, 2, 4, 3, 2, 5]
+    Ls = [1024, 1008, 784, 272, 2048, 976, 4096, 48]
+    betas, sweeps = [0.4, 0.35, 0.5, 0.44, 0.41, 0.45, 0.38, 0.3], [3, 2, 4, 3, 2, 3, 2, 5]
     lats = [rngx.ising_create(L, kind, 300 + i) for i, L in enumerate(Ls)]
     twins = [rngx.ising_create(L, kind, 300 + i) for i, L in enumerate(Ls)]
     traces = [torch.full((s,), 7, dtype=torch.int32, device="cuda") for s in sweeps]

@@ -334,3 +334,21 @@ def test_substream_seeding(rngx, orc):
     assert np.array_equal(out.cpu().numpy().view(np.uint32).reshape(16, -1), want)
     with pytest.raises(rngx.RngxError):
         rngx.rng_create_substreams("lcg32", 64, 1)
+
+
+def test_substream_lcg_state_header_is_checked(rngx, orc):
+    """A sub-stream LCG image must carry the handle's S-step map; the image
+    of a handle with another S is refused and the state is left as it was."""
+    for kind in ("lcg32_sub", "lcg64_sub"):
+        g = rngx.rng_create(kind, 100, 3)
+        img = rngx.rng_get_state(g)
+        assert np.array_equal(img, orc.seed(kind, 100, 3))
+        other = orc.seed(kind, 100, 4)
+        rngx.rng_set_state(g, other)                      # same S: accepted
+        assert np.array_equal(rngx.rng_get_state(g), other)
+        bad = other.copy()
+        words = bad.view(np.uint32 if kind == "lcg32_sub" else np.uint64)
+        words[100] += 2                                   # a different A_S
+        with pytest.raises(rngx.RngxError):
+            rngx.rng_set_state(g, bad)
+        assert np.array_equal(rngx.rng_get_state(g), other)
