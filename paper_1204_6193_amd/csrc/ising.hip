@@ -25,6 +25,7 @@
 // end, so E = -sum over colour-1 sites of s h = -sum (4 - 2 m_after).
 #include <algorithm>
 #include <cmath>
+#include <numeric>
 #include <type_traits>
 #include <vector>
 
@@ -214,6 +215,7 @@ struct ReplicaDesc {
     uint32_t R, nwg, units;  // strips: rows and units per strip, strip count
     uint64_t *halo;   // strips: 2 slots x nwg x 2 rows x L/4 tagged words
     uint32_t *err;    // the lattice's error word (a strip gave up waiting)
+    uint32_t R_last;  // strips: rows of the last strip (1..R; the others have R)
 };
 
 struct StripArgs {
@@ -227,6 +229,7 @@ struct StripArgs {
     uint32_t epoch0;            // pass tags of this call are epoch0 + 1, epoch0 + 2, ...
     uint32_t *err;
     uint32_t hits;              // Metropolis updates per visited site (multi-hit kernels)
+    uint32_t R0;                // rows of every strip but the last: strip r starts at row r*R0
 };
 
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -511,7 +514,7 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
     constexpr int NB = Unit::kNB;
     const uint32_t L = a.L, R = a.R, nwg = a.nwg, t = threadIdx.x, nt = blockDim.x;
     const uint32_t P = lds_pitch(L);
-    const uint64_t row0 = static_cast<uint64_t>(r) * R;
+    const uint64_t row0 = static_cast<uint64_t>(r) * a.R0;
     const uint32_t upr = L / NB;             // units per row
     const uint32_t last0 = a.units - upr;    // first unit of the bottom row
     const uint32_t W = L / 4;                // halo words per row
@@ -529,7 +532,7 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
     __syncthreads();
     refresh_ghosts(lds, L, 0, R + 2, t, nt);
 
-    const uint64_t ubase = static_cast<uint64_t>(r) * a.units;
+    const uint64_t ubase = row0 * upr;  // first unit (and stream) of the strip
     Unit u[SPT];
     uint32_t place[PLDS ? 1 : SPT];
     uint32_t *place_lds = reinterpret_cast<uint32_t *>(lds + (R + 4) * P + 80);  // [slot][thread] when PLDS
@@ -836,9 +839,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc
             replica_in_memory<Unit>(d, red_s);
             continue;
         }
-        const StripArgs a{d.spins, d.st, d.S, d.L, d.R, d.nwg, d.units, d.T4, d.T8, d.n_sweeps, d.trace,
-                          d.halo, 0, d.err, 1};
-        if (early_slots<spt>(d.L / NB, d.units, blockDim.x)) strip_body<Unit, spt, true, false>(a, item.y, lds);
+        const uint32_t R = item.y + 1 == d.nwg ? d.R_last : d.R;
+        const uint32_t units = R * (d.L / NB);
+        const StripArgs a{d.spins, d.st, d.S, d.L, R, d.nwg, units, d.T4, d.T8, d.n_sweeps, d.trace,
+                          d.halo, 0, d.err, 1, d.R};
+        if (early_slots<spt>(d.L / NB, units, blockDim.x)) strip_body<Unit, spt, true, false>(a, item.y, lds);
         else strip_body<Unit, spt, false, false>(a, item.y, lds);
     }
 }
@@ -951,7 +956,7 @@ hipError_t run_strips(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t 
         lat->epoch = 0;
     }
     StripArgs a{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, pl.R, pl.nwg, pl.units, T4, T8, n,
-                tr, lat->d_halo, static_cast<uint32_t>(lat->epoch), lat->d_err, hits};
+                tr, lat->d_halo, static_cast<uint32_t>(lat->epoch), lat->d_err, hits, pl.R};
     void *args[] = {&a};
     hipError_t e;
     if (pl.nwg == 1)
@@ -1064,16 +1069,25 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
         const uint32_t L = l->L;
         ReplicaDesc d{l->d_spins, l->gen->d_state, l->gen->S, L, kReplicaMemory, threshold(betas[i], 4),
                       threshold(betas[i], 8), n_sweeps[i], traces ? traces[i] : nullptr, 0, 0, 0, nullptr, l->d_err};
-        // fewest strips (one if possible) whose strip fits the workgroup's LDS and unit slots
-        for (uint32_t R = L; R >= 2; --R) {
-            if (L % R) continue;
+        // Fewest strips (one if possible) that fit the workgroup's LDS and
+        // unit slots: strips of R rows and a last one of R_last = L - (nwg-1) R
+        // rows (2 <= R_last <= R), so that L need not be a multiple of R.
+        // XS1024W strips hold whole instances (128 sites), so R is a multiple
+        // of g = 128 / gcd(L, 128) (L is a multiple of 16, hence of g).
+        const uint32_t g = nb == 8 ? 128u / std::gcd(L, 128u) : 1u;
+        for (uint32_t want = 1; want <= kMaxGang; ++want) {
+            uint32_t R = (L + want - 1) / want;
+            R = std::min((R + g - 1) / g * g, L);
+            const uint32_t nwg = (L + R - 1) / R;
+            const uint32_t R_last = L - (nwg - 1) * R;
+            if (nwg > 1 && R_last < 2) continue;  // a strip's top and bottom rows are distinct
             const uint64_t units = static_cast<uint64_t>(R) * L / nb;
             if (units > max_units || strip_lds_bytes(L, R) > kBatchLdsCap) continue;
-            if (nb == 8 && (static_cast<uint64_t>(R) * L) % 128) continue;
-            const uint32_t nwg = L / R;
-            if (nwg > kMaxGang) break;
+            if (nb == 8 && ((static_cast<uint64_t>(R) * L) % 128 || (static_cast<uint64_t>(R_last) * L) % 128))
+                continue;
             d.mode = nwg == 1 ? kReplicaOnChip : kReplicaStrips;
             d.R = R;
+            d.R_last = R_last;
             d.nwg = nwg;
             d.units = static_cast<uint32_t>(units);
             lds = std::max<uint32_t>(lds, static_cast<uint32_t>(strip_lds_bytes(L, R)));

@@ -242,11 +242,12 @@ def test_batch_equals_individual_sweeps(rngx, kind):
 
 @pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
 def test_batch_gangs_and_memory_replicas(rngx, kind):
-    """Large replicas run as gangs of strip workgroups (L = 1024: 16 strips;
-    1008, 784: odd strip counts; 272: two; 2048: 64, the largest gang;
-    976 = 16 * 61: XS1024W strips of 16 rows only, 61 of them) or, beyond the
-    largest gang, in memory (L = 4096); each equals ising_sweep on the
-    lattice alone."""
+    """Large replicas run as gangs of strip workgroups or, beyond the largest
+    gang, in memory (L = 4096); each equals ising_sweep on the lattice alone.
+    XS1024W gangs: 1024 = 16 x 64 rows; 1008 = 15 x 64 + 48; 976 = 15 x 64
+    + 16 (a last strip of one XS1024W row of instances); 784 = 9 x 80 + 64;
+    272 = 2 x 136; 2048 = 64 x 32, the largest gang.  LCG32: 1008 = 16 x 63
+    (odd rows), 976 = 14 x 66 + 52, 784 = 9 x 79 + 73."""
     print(f"case batch gangs {kind}", flush=True)
     Ls = [1024, 1008, 784, 272, 2048, 976, 4096, 48]
     betas, sweeps = [0.4, 0.35, 0.5, 0.44, 0.41, 0.45, 0.38, 0.3], [3, 2, 4, 3, 2, 3, 2, 5]
