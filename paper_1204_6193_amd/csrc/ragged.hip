@@ -18,6 +18,7 @@
 // 16-lane row generates all chunks of its slot in turn, so no row waits on a
 // longer one and the only jumps are those at the cuts.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "rngx_internal.h"
@@ -118,22 +119,35 @@ __global__ __launch_bounds__(kBlock) void k_ragged_affine(const RaggedItem *item
     const uint64_t xc = t64[2 * it.j] * x0 + t64[2 * it.j + 1];  // state at the chunk's start
     const uint32_t mis = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out) >> 2) + it.out) & 63;
     const uint32_t p0 = (lane + 64 - mis) & 63;
-    uint64_t x = lane_maps[2 * p0] * xc + lane_maps[2 * p0 + 1];
-    const uint64_t Am = lane_maps[128], Cm = lane_maps[129];
+    using T = std::conditional_t<L64, uint64_t, uint32_t>;  // 32-bit kinds: arithmetic mod 2^32
+    T x = static_cast<T>(lane_maps[2 * p0] * xc + lane_maps[2 * p0 + 1]);
+    const T Am = static_cast<T>(lane_maps[128]), Cm = static_cast<T>(lane_maps[129]);
     const int64_t len = it.len;
     const uint32_t kend = static_cast<uint32_t>((len + mis + 63) >> 6);
+    // Spans k in [kb, kw) are whole (64 k >= mis and 64 k + 64 - mis <= len);
+    // the body loop takes them up to, not including, the last span, which
+    // holds the stream's last value and goes through the checked loop.
+    const uint32_t kb = mis ? 1u : 0u;
+    const uint32_t kw = static_cast<uint32_t>((len + mis) >> 6);
+    const uint32_t kl = kend ? (kw < kend - 1 ? kw : kend - 1) : 0u;
+    const uint32_t body_end = kl > kb ? kl : kb;
     uint32_t *o = out + (it.out - mis) + lane;
-    for (uint32_t k = 0; k < kend; ++k) {
+    auto checked = [&](uint32_t k) {
         const int64_t p = 64 * static_cast<int64_t>(k) + lane - mis;
         const uint32_t v = L64 ? static_cast<uint32_t>(x >> 32) : static_cast<uint32_t>(x);
-        if (64 * static_cast<int64_t>(k) >= mis && 64 * static_cast<int64_t>(k) + 64 - mis <= len)
-            __builtin_nontemporal_store(v, o);  // a whole span
-        else if (p >= 0 && p < len)
-            *o = v;
+        if (p >= 0 && p < len) *o = v;
         if (it.last && p == len - 1) scratch[q] = x;
         if (p >= 0) x = Am * x + Cm;
         o += 64;
+    };
+    uint32_t k = 0;
+    for (; k < kb && k < kend; ++k) checked(k);
+    for (; k < body_end; ++k) {
+        __builtin_nontemporal_store(L64 ? static_cast<uint32_t>(x >> 32) : static_cast<uint32_t>(x), o);
+        x = Am * x + Cm;
+        o += 64;
     }
+    for (; k < kend; ++k) checked(k);
 }
 
 template <bool L64>
