@@ -305,6 +305,9 @@ def main():
     ap.add_argument("--profile-ising", action="store_true",
                     help="for rocprofv3: `steps` XS1024W Ising calls of 200 sweeps each at L=4096, beta=0.4 "
                          "(energy trace on); prints no JSON")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="for rocprofv3: `steps` runs of the 512-replica XS1024W batch (L in 16..1024, "
+                         "numpy default_rng(1)) at 1000 sweeps each; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported "
@@ -322,6 +325,18 @@ def main():
             rx.ising_sweep(lat, 0.4, 200, tr)
         torch.cuda.synchronize()
         print(f"profile pass done: {args.steps} calls of 200 sweeps at L=4096", flush=True)
+        return
+    if args.profile_batch:
+        import numpy as np
+        rng = np.random.default_rng(1)
+        Ls = [int(x) for x in rng.choice(np.arange(16, 1025, 16), size=512)]
+        betas = [float(b) for b in rng.uniform(0.3, 0.6, size=512)]
+        lats = [rx.ising_create(L, "xs1024w", 1000 + i) for i, L in enumerate(Ls)]
+        batch = rx.ising_batch_create(lats, betas, [1000] * 512)
+        for _ in range(args.steps):
+            rx.ising_batch_run(batch)
+        torch.cuda.synchronize()
+        print(f"profile pass done: {args.steps} batch runs of 512 replicas x 1000 sweeps", flush=True)
         return
     out = torch.empty(S_FULL * COUNT_FULL, dtype=torch.int32, device="cuda")
     if args.profile_pass:
