@@ -266,6 +266,31 @@ def test_batch_gangs_and_memory_replicas(rngx, kind):
                                   rngx.rng_get_state(rngx.ising_rng(tw))), (rep, i)
 
 
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
+def test_batch_every_size_to_1040(rngx, kind):
+    """One batch of every L = 16, 32, ..., 1040: on-chip replicas and gangs
+    with every last-strip height the strip rule produces, more items than
+    resident workgroups (gangs start while others run); each replica equals
+    ising_sweep on the lattice alone."""
+    print(f"case batch every size {kind}", flush=True)
+    Ls = list(range(16, 1041, 16))
+    rng = np.random.default_rng(17)
+    betas = [float(b) for b in rng.uniform(0.3, 0.6, size=len(Ls))]
+    sweeps = [int(x) for x in rng.integers(1, 4, size=len(Ls))]
+    lats = [rngx.ising_create(L, kind, 500 + i) for i, L in enumerate(Ls)]
+    twins = [rngx.ising_create(L, kind, 500 + i) for i, L in enumerate(Ls)]
+    traces = [torch.full((s,), 7, dtype=torch.int32, device="cuda") for s in sweeps]
+    batch = rngx.ising_batch_create(lats, betas, sweeps, traces)
+    rngx.ising_batch_run(batch)
+    for i, tw in enumerate(twins):
+        tt = torch.zeros(sweeps[i], dtype=torch.int32, device="cuda")
+        rngx.ising_sweep(tw, betas[i], sweeps[i], tt)
+        assert torch.equal(traces[i], tt), Ls[i]
+        assert np.array_equal(rngx.ising_get_spins(lats[i]), rngx.ising_get_spins(tw)), Ls[i]
+        assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[i])),
+                              rngx.rng_get_state(rngx.ising_rng(tw))), Ls[i]
+
+
 def test_batch_small_replicas_match_oracle(rngx, orc):
     kind = "xs1024w"
     Ls, betas, sweeps = [16, 48, 96], [0.31, 0.44, 0.58], [3, 5, 2]
