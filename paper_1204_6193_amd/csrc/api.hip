@@ -401,12 +401,12 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
     if (!items.empty()) {
         e = hipMalloc(&r->d_items, sizeof(RaggedItem) * items.size());
         if (e == hipSuccess && ragged_affine(g->kind)) {
-            // lane i starts i+1 steps into its chunk; entry 64: the 64-step advance
+            // entry i: the (i+1)-step map (a lane whose first position is i); entry 256: the 256-step advance
             uint64_t a = g->kind == RNGX_LCG32 ? kLcg32A : g->kind == RNGX_LCG64 ? kLcg64A : g->sub_a;
             uint64_t c = g->kind == RNGX_LCG32 ? kLcg32C : g->kind == RNGX_LCG64 ? kLcg64C : g->sub_c;
-            std::vector<uint64_t> lane(130);
-            for (int i = 0; i < 64; ++i) affine_power(a, c, i + 1, &lane[2 * i], &lane[2 * i + 1]);
-            affine_power(a, c, 64, &lane[128], &lane[129]);
+            std::vector<uint64_t> lane(514);
+            for (int i = 0; i < 256; ++i) affine_power(a, c, i + 1, &lane[2 * i], &lane[2 * i + 1]);
+            affine_power(a, c, 256, &lane[512], &lane[513]);
             e = hipMalloc(&r->d_lane, 8 * lane.size());
             if (e == hipSuccess) e = hipMemcpy(r->d_lane, lane.data(), 8 * lane.size(), hipMemcpyHostToDevice);
         }

@@ -96,16 +96,20 @@ __global__ __launch_bounds__(kBlock) void k_ragged_gen_small(const RaggedItem *i
 }
 
 // Affine kinds (LCG32, LCG64 and their sub-stream forms): one wave per
-// chunk, leapfrogging.  The wave's stores are aligned to 64-word (256-byte)
-// spans of the output: in step k lane i writes word A + 64 k + i, A being the
-// chunk's first word rounded down to a multiple of 64, i.e. chunk position
-// p = 64 k + i - mis (mis = first word - A).  A lane starts at its first
-// position p0 (the (p0+1)-step map from the chunk's start state, lane_maps[p0];
-// lane_maps[64] is the 64-step map) and advances 64 steps per store; spans
-// inside the chunk are whole and written non-temporally, the chunk's first
-// and last spans word by word.  The streams' states are only read here; the
-// lane that writes a stream's last value puts the final state in
+// chunk, leapfrogging four values per lane.  The wave's stores are aligned
+// to 256-word (1 KiB) spans of the output: in step k lane i writes words
+// A + 256 k + 4 i + j (j = 0..3), A being the chunk's first word rounded down
+// to a multiple of 256, i.e. chunk positions b + j with b = 256 k + 4 i - mis
+// (mis = first word - A).  A lane keeps the state of position b (the
+// (b+1)-step map from the chunk's start state, lane_maps[b] for its first
+// step with b >= 0), derives b+1..b+3 by single steps and advances 256 steps
+// per store (lane_maps[256]).  Whole spans before the chunk's last one are
+// written as one 16-byte non-temporal store per lane with no checks; the
+// first and last spans word by word.  The streams' states are only read
+// here; the lane that writes a stream's last value puts the final state in
 // scratch[item] for k_ragged_commit_affine.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kAffSpan = 256;  // words per wave store (64 lanes x 4)
 template <bool L64>
 __global__ __launch_bounds__(kBlock) void k_ragged_affine(const RaggedItem *items, uint64_t n_items,
                                                            const uint64_t *t64, const uint64_t *lane_maps,
@@ -117,35 +121,46 @@ __global__ __launch_bounds__(kBlock) void k_ragged_affine(const RaggedItem *item
     const uint64_t x0 = L64 ? reinterpret_cast<const uint64_t *>(st)[it.unit]
                             : reinterpret_cast<const uint32_t *>(st)[it.unit];
     const uint64_t xc = t64[2 * it.j] * x0 + t64[2 * it.j + 1];  // state at the chunk's start
-    const uint32_t mis = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out) >> 2) + it.out) & 63;
-    const uint32_t p0 = (lane + 64 - mis) & 63;
+    const uint32_t mis = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out) >> 2) + it.out) & (kAffSpan - 1);
     using T = std::conditional_t<L64, uint64_t, uint32_t>;  // 32-bit kinds: arithmetic mod 2^32
-    T x = static_cast<T>(lane_maps[2 * p0] * xc + lane_maps[2 * p0 + 1]);
-    const T Am = static_cast<T>(lane_maps[128]), Cm = static_cast<T>(lane_maps[129]);
+    // first position of the lane in a step with b >= 0 (step 0 if 4 lane >= mis, else step 1)
+    const uint32_t pf = 4 * lane >= mis ? 4 * lane - mis : kAffSpan + 4 * lane - mis;
+    T x = static_cast<T>(lane_maps[2 * pf] * xc + lane_maps[2 * pf + 1]);
+    const T s0 = static_cast<T>(lane_maps[0] * xc + lane_maps[1]);  // state of position 0
+    const T a1 = static_cast<T>(lane_maps[0]), c1 = static_cast<T>(lane_maps[1]);  // the one-step map
+    const T Am = static_cast<T>(lane_maps[2 * kAffSpan]), Cm = static_cast<T>(lane_maps[2 * kAffSpan + 1]);
     const int64_t len = it.len;
-    const uint32_t kend = static_cast<uint32_t>((len + mis + 63) >> 6);
-    // Spans k in [kb, kw) are whole (64 k >= mis and 64 k + 64 - mis <= len);
+    const uint32_t kend = static_cast<uint32_t>((len + mis + kAffSpan - 1) / kAffSpan);
+    // Spans k in [kb, kw) are whole (256 k >= mis and 256 k + 256 - mis <= len);
     // the body loop takes them up to, not including, the last span, which
     // holds the stream's last value and goes through the checked loop.
     const uint32_t kb = mis ? 1u : 0u;
-    const uint32_t kw = static_cast<uint32_t>((len + mis) >> 6);
+    const uint32_t kw = static_cast<uint32_t>((len + mis) / kAffSpan);
     const uint32_t kl = kend ? (kw < kend - 1 ? kw : kend - 1) : 0u;
     const uint32_t body_end = kl > kb ? kl : kb;
-    uint32_t *o = out + (it.out - mis) + lane;
+    auto word = [](T v) { return L64 ? static_cast<uint32_t>(v >> 32) : static_cast<uint32_t>(v); };
+    uint32_t *o = out + (it.out - mis) + 4 * lane;
     auto checked = [&](uint32_t k) {
-        const int64_t p = 64 * static_cast<int64_t>(k) + lane - mis;
-        const uint32_t v = L64 ? static_cast<uint32_t>(x >> 32) : static_cast<uint32_t>(x);
-        if (p >= 0 && p < len) *o = v;
-        if (it.last && p == len - 1) scratch[q] = x;
-        if (p >= 0) x = Am * x + Cm;
-        o += 64;
+        const int64_t b = static_cast<int64_t>(kAffSpan) * k + 4 * lane - mis;
+        T y = b >= 0 ? x : s0;  // state of the lane's first position >= 0
+        for (int j = 0; j < 4; ++j) {
+            const int64_t p = b + j;
+            if (p < 0) continue;
+            if (p < len) o[j] = word(y);
+            if (it.last && p == len - 1) scratch[q] = y;
+            y = a1 * y + c1;
+        }
+        if (b >= 0) x = Am * x + Cm;
+        o += kAffSpan;
     };
     uint32_t k = 0;
     for (; k < kb && k < kend; ++k) checked(k);
     for (; k < body_end; ++k) {
-        __builtin_nontemporal_store(L64 ? static_cast<uint32_t>(x >> 32) : static_cast<uint32_t>(x), o);
+        const T y1 = a1 * x + c1, y2 = a1 * y1 + c1, y3 = a1 * y2 + c1;
+        const u32x4 v = {word(x), word(y1), word(y2), word(y3)};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(o));
         x = Am * x + Cm;
-        o += 64;
+        o += kAffSpan;
     }
     for (; k < kend; ++k) checked(k);
 }

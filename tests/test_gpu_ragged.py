@@ -82,6 +82,26 @@ def test_ragged_graph_replay(rngx, orc, kind):
         assert np.array_equal(rngx.rng_get_state(ga), rngx.rng_get_state(gb)), rep
 
 
+@pytest.mark.parametrize("kind", ["lcg32", "lcg64", "xs1024w", "mwc"])
+def test_ragged_into_unaligned_view(rngx, orc, kind):
+    """The output starts one word past a 16-byte boundary (a view of a larger
+    buffer): values match the oracle and the words around it stay untouched."""
+    print(f"case ragged unaligned {kind}", flush=True)
+    S = 96 if kind == "xs1024w" else 37
+    lens = _lengths(kind, S // 32 if kind == "xs1024w" else S, 12)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    total = int(off[-1])
+    g = rngx.rng_create(kind, S, 4)
+    plan = rngx.rng_ragged_create(g, off)
+    buf = torch.full((total + 2,), -1, dtype=torch.int32, device="cuda")
+    rngx.rng_fill_ragged_u32(plan, buf[1:])
+    got = buf.cpu().numpy().view(np.uint32)
+    st = orc.seed(kind, S, 4)
+    assert np.array_equal(got[1:total + 1], _oracle_ragged(orc, kind, S, st, lens)), kind
+    assert got[0] == 0xFFFFFFFF and got[total + 1] == 0xFFFFFFFF
+    assert np.array_equal(rngx.rng_get_state(g), st), kind
+
+
 def test_ragged_argument_errors(rngx):
     g = rngx.rng_create("lcg32", 8, 1)
     with pytest.raises(rngx.RngxError):
