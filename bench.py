@@ -308,6 +308,9 @@ def main():
     ap.add_argument("--profile-batch", action="store_true",
                     help="for rocprofv3: `steps` runs of the 512-replica XS1024W batch (L in 16..1024, "
                          "numpy default_rng(1)) at 1000 sweeps each; prints no JSON")
+    ap.add_argument("--profile-ragged", action="store_true",
+                    help="for rocprofv3: `steps` ragged fills of the 10^4-request plan (lengths log-uniform in "
+                         "[2^10, 2^22], numpy default_rng(1)) for XS1024W, then LCG32; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this library runs on one GPU; --gpus {args.gpus} is not supported "
@@ -325,6 +328,22 @@ def main():
             rx.ising_sweep(lat, 0.4, 200, tr)
         torch.cuda.synchronize()
         print(f"profile pass done: {args.steps} calls of 200 sweeps at L=4096", flush=True)
+        return
+    if args.profile_ragged:
+        import numpy as np
+        rng = np.random.default_rng(1)
+        lens = np.floor(2.0 ** (10 + 12 * rng.random(10000))).astype(np.uint64)
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+        out = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
+        for kind in ("xs1024w", "lcg32"):
+            g = rx.rng_create(kind, 32 * 10000 if kind == "xs1024w" else 10000, 1)
+            plan = rx.rng_ragged_create(g, off)
+            for _ in range(args.steps):
+                rx.rng_fill_ragged_u32(plan, out)
+            torch.cuda.synchronize()
+            plan.destroy()
+        print(f"profile pass done: {args.steps} ragged fills of {int(off[-1])} values, xs1024w and lcg32",
+              flush=True)
         return
     if args.profile_batch:
         import numpy as np
