@@ -73,6 +73,8 @@ def lib():
         L.orc_xs1024_variant_steps.argtypes = [i32, vp, u64]
         L.orc_xs1024_equidistribution.restype = i32
         L.orc_xs1024_equidistribution.argtypes = [i32, i32, vp]
+        L.orc_philox4x32_block.restype = None
+        L.orc_philox4x32_block.argtypes = [vp, vp, i32, vp]
         L.orc_ising_sweeps_hits.restype = i32
         L.orc_ising_sweeps_hits.argtypes = [ctypes.c_uint32, i32, ctypes.c_double, vp, vp, u64, ctypes.c_uint32, vp]
         _lib = L
@@ -128,6 +130,16 @@ def generate(kind: str, S: int, st: np.ndarray, count: int, lo: int = 0, hi: int
         out = np.zeros((count, w), dtype=np.float32 if mode == OUT_F32 else np.uint32)
     _check(lib().orc_generate(_CODE[kind], S, _ptr(st), lo, hi, count, mode, _ptr(out)), "generate")
     return out
+
+
+def philox4x32_block(ctr, key, rounds: int = 10) -> list:
+    """Philox4x32-`rounds` of a full 128-bit counter (4 words) under a
+    64-bit key (2 words); returns the 4 output words."""
+    c = np.array(ctr, dtype=np.uint32)
+    k = np.array(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_block(_ptr(c), _ptr(k), rounds, _ptr(out))
+    return [int(v) for v in out]
 
 
 def step_n(kind: str, S: int, st: np.ndarray, n: int, lo: int = 0, hi: int | None = None):

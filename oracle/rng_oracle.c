@@ -13,8 +13,10 @@
  *
  * Parity status of each function is stated in its comment; the pins live in
  * tests/test_oracle_*.py.  Philox4x32-10's round constants and XORWOW's
- * shift triple come from their original publications, which print no test
- * vectors that are available here: "parity unpinned" for those constants.
+ * shift triple come from their original publications; they are pinned by
+ * the published Philox known-answer vectors and by an independent
+ * implementation (rocRAND's source headers, compiled for the host by the
+ * tests).
  *
  * Conventions (project definitions where the paper is silent):
  *   - every recursive generator steps first and then outputs, so output #0
@@ -247,11 +249,14 @@ static uint32_t weyl_mix(uint32_t y0, uint64_t n)
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-r (Salmon et al. 2011; S-box as in the counter-based section:
- * L' = mullo(R,M), R' = mulhi(R,M) ^ k ^ L).  Counter (ctr0, ctr1, 0, 0).
- * rounds = 10, or 7 for the faster variant the section also measures. */
-static void philox4x32(uint32_t k0, uint32_t k1, uint64_t block, int rounds, uint32_t out[4])
+ * L' = mullo(R,M), R' = mulhi(R,M) ^ k ^ L), on a full 128-bit counter
+ * ctr[0..3] and key key[0..1]; the key is bumped by the Weyl constants
+ * before every round but the first.  rounds = 10, or 7 for the faster
+ * variant the section also measures.  Pinned by the published known-answer
+ * vectors and by rocRAND's engine (tests). */
+void orc_philox4x32_block(const uint32_t ctr[4], const uint32_t key[2], int rounds, uint32_t out[4])
 {
-    uint32_t x0 = (uint32_t)block, x1 = (uint32_t)(block >> 32), x2 = 0, x3 = 0;
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3], k0 = key[0], k1 = key[1];
     for (int r = 0; r < rounds; r++) {
         if (r > 0) { k0 += PHILOX_W0; k1 += PHILOX_W1; }
         uint64_t p0 = (uint64_t)PHILOX_M0 * x0;
@@ -265,6 +270,14 @@ static void philox4x32(uint32_t k0, uint32_t k1, uint64_t block, int rounds, uin
         x0 = n0; x1 = n1; x2 = n2; x3 = n3;
     }
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Block `block` of a stream with key (k0, k1): counter (block_lo, block_hi, 0, 0). */
+static void philox4x32(uint32_t k0, uint32_t k1, uint64_t block, int rounds, uint32_t out[4])
+{
+    const uint32_t ctr[4] = {(uint32_t)block, (uint32_t)(block >> 32), 0, 0};
+    const uint32_t key[2] = {k0, k1};
+    orc_philox4x32_block(ctr, key, rounds, out);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -6,11 +6,11 @@ a*2^32 - 1 a safe prime; MWC equals the multiplicative LCG y -> a y mod p.
 XORWOW (XORShift section; recurrence from Marsaglia 2003): the xorshift part
 has a primitive degree-160 minimal polynomial, so with the Weyl term the
 period is 2^192 - 2^32 as the paper states.
-Philox4x32-10 and -7 (counter-based section): only structural checks are
-possible here; agreement with the published constants is "parity unpinned".
-The seven-round variant is pinned to the ten-round one: three further rounds
-(written out here from the section's S-box) turn its block into the
-ten-round block.
+Philox4x32-10 and -7 (counter-based section): structural checks here; the
+published known-answer vectors and rocRAND's engine pin the block function
+(test_oracle_kat.py).  The seven-round variant is also tied to the ten-round
+one: three further rounds (written out here from the section's S-box) turn
+its block into the ten-round block.
 """
 import numpy as np
 import pytest
