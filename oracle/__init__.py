@@ -10,7 +10,8 @@ module only marshals numpy buffers.
 Kinds are named by string so that the oracle does not depend on the product's
 enum values: "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w",
 "philox4x32_7", "lcg32_sub", "lcg64_sub" (sub-stream LCGs sharing one
-sequence).
+sequence), "lfg521", "lfg1279" (additive lagged Fibonacci, lags (521, 353)
+and (1279, 861), 1024 lanes per block-shared instance).
 """
 from __future__ import annotations
 
@@ -24,7 +25,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
 SOURCES = [os.path.join(HERE, "rng_oracle.c")]
 
-KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7", "lcg32_sub", "lcg64_sub"]
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7", "lcg32_sub", "lcg64_sub",
+         "lfg521", "lfg1279"]
+LFG_W = 1024  # lanes (streams) of one lagged Fibonacci instance
+LFG_LAGS = {"lfg521": (521, 353), "lfg1279": (1279, 861)}
 _CODE = {k: i + 1 for i, k in enumerate(KINDS)}
 OUT_U32, OUT_F32, OUT_XOR = 0, 1, 2
 

@@ -40,7 +40,24 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_LCG32 = 1, ORC_LCG64, ORC_MWC, ORC_XORWOW, ORC_PHILOX, ORC_XS1024W, ORC_PHILOX7, ORC_LCG32S, ORC_LCG64S };
+enum { ORC_LCG32 = 1, ORC_LCG64, ORC_MWC, ORC_XORWOW, ORC_PHILOX, ORC_XS1024W, ORC_PHILOX7, ORC_LCG32S, ORC_LCG64S,
+       ORC_LFG521, ORC_LFG1279 };
+/* Additive lagged Fibonacci generators (Lagged Fibonacci section, eq.
+ * used_fibonacci): u_n = u_{n-r} + u_{n-s} mod 1 with (r, s) = (521, 353) or
+ * (1279, 861).  The values are u_n = x_n / 2^32 with 32-bit words x_n, so the
+ * mod-1 addition is exact: x_n = x_{n-r} + x_{n-s} mod 2^32 (m = 2^32 in the
+ * section's general form), output x_n.  An instance is one such sequence,
+ * shared by the threads of a block; its LFG_W lanes are the streams: stream
+ * s is lane s % LFG_W of instance s / LFG_W, and output k of lane i is
+ * x_{k*LFG_W + i} of the instance's outputs (warp order, as for XS1024W).
+ * Image: u32 X[G][r], X[g][j] = x_{n-r+j} of instance g (its last r values,
+ * oldest first).  Seeding: X[g][j] = low32 (j even) / high32 (j odd) of
+ * SM(1 + H*g + j/2), H = (r+1)/2; if every word is even, X[g][0] |= 1 (an
+ * all-even start keeps the low bits zero forever). */
+#define IS_LFG(kind) ((kind) == ORC_LFG521 || (kind) == ORC_LFG1279)
+#define LFG_W 1024
+#define LFG_R(kind) ((kind) == ORC_LFG521 ? 521 : 1279)
+#define LFG_S(kind) ((kind) == ORC_LFG521 ? 353 : 861)
 /* Sub-stream LCGs (LCG section, eq. lcg_skipping with t = S): the S streams
  * share one global sequence g_0 = the plain seeding's stream-0 value,
  * g_{n+1} = a g_n + c.  Stream s starts at g_s and steps S positions at a
@@ -109,14 +126,17 @@ size_t orc_state_bytes(int kind, uint64_t S)
     case ORC_PHILOX:
     case ORC_PHILOX7: return 16 * S;
     case ORC_XS1024W: return 4 * S + 8 * (S / 32) + 4;
+    case ORC_LFG521:
+    case ORC_LFG1279: return 4 * (uint64_t)LFG_R(kind) * (S / LFG_W);
     default: return 0;
     }
 }
 
 static int kind_ok(int kind, uint64_t S)
 {
-    if (kind < ORC_LCG32 || kind > ORC_LCG64S) return 0;
+    if (kind < ORC_LCG32 || kind > ORC_LFG1279) return 0;
     if (kind == ORC_XS1024W && S % 32 != 0) return 0;
+    if (IS_LFG(kind) && S % LFG_W != 0) return 0;
     return 1;
 }
 
@@ -331,6 +351,18 @@ int orc_seed(int kind, uint64_t S, uint64_t seed, void *st)
             uint64_t z = orc_splitmix(seed, 1 + s);
             k0[s] = (uint32_t)z; k1[s] = (uint32_t)(z >> 32); pos[s] = 0;
         }
+    } else if (IS_LFG(kind)) {
+        const uint64_t r = LFG_R(kind), H = (r + 1) / 2;
+        uint32_t *X = (uint32_t *)b;
+        for (uint64_t g = 0; g < S / LFG_W; g++) {
+            uint32_t odd = 0;
+            for (uint64_t j = 0; j < r; j++) {
+                uint64_t z = orc_splitmix(seed, 1 + H * g + j / 2);
+                X[r * g + j] = (j % 2 == 0) ? (uint32_t)z : (uint32_t)(z >> 32);
+                odd |= X[r * g + j] & 1u;
+            }
+            if (!odd) X[r * g] |= 1u;
+        }
     } else { /* XS1024W */
         uint32_t *W = (uint32_t *)b;
         uint64_t *n = (uint64_t *)(b + 4 * S);
@@ -372,8 +404,31 @@ int orc_generate(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, uint6
 {
     if (!kind_ok(kind, S) || lo > hi || hi > S) return -1;
     if (kind == ORC_XS1024W && (lo % 32 || hi % 32)) return -1;
+    if (IS_LFG(kind) && (lo % LFG_W || hi % LFG_W)) return -1;
     uint64_t width = hi - lo;
     uint8_t *b = (uint8_t *)st;
+    if (IS_LFG(kind)) {
+        /* the instance's sequence through a ring of its last r values:
+         * buf[h] is x_{n-r}, buf[(h + r - s) % r] is x_{n-s} */
+        const uint64_t r = LFG_R(kind), sl = LFG_S(kind);
+        uint32_t *X = (uint32_t *)b;
+        uint32_t *buf = (uint32_t *)malloc(4 * r);
+        if (!buf) return -3;
+        for (uint64_t g = lo / LFG_W; g < hi / LFG_W; g++) {
+            memcpy(buf, &X[r * g], 4 * r);
+            uint64_t h = 0;
+            for (uint64_t k = 0; k < count; k++)
+                for (uint64_t i = 0; i < LFG_W; i++) {
+                    uint32_t x = buf[h] + buf[(h + r - sl) % r];
+                    buf[h] = x;
+                    h = (h + 1) % r;
+                    emit(mode, out, k, width, LFG_W * g + i - lo, x);
+                }
+            for (uint64_t j = 0; j < r; j++) X[r * g + j] = buf[(h + j) % r];
+        }
+        free(buf);
+        return 0;
+    }
     if (kind == ORC_LCG32) {
         uint32_t *x = (uint32_t *)b;
         for (uint64_t s = lo; s < hi; s++)
@@ -458,6 +513,15 @@ int orc_step_n(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, uint64_
     if (IS_PHILOX(kind)) { /* counter-based: stepping is counting */
         uint64_t *pos = (uint64_t *)(b + 8 * S);
         for (uint64_t s = lo; s < hi; s++) pos[s] += n;
+        return 0;
+    }
+    if (IS_LFG(kind)) { /* n rows of each instance, outputs discarded */
+        if (lo % LFG_W || hi % LFG_W) return -1;
+        uint32_t *xs = (uint32_t *)calloc(LFG_W, 4);
+        if (!xs) return -3;
+        for (uint64_t g = lo / LFG_W; g < hi / LFG_W; g++)
+            orc_generate(kind, S, st, LFG_W * g, LFG_W * g + LFG_W, n, ORC_OUT_XOR, xs);
+        free(xs);
         return 0;
     }
     uint32_t sink[32];
@@ -602,10 +666,74 @@ static void xs1024_lin(uint64_t *v)
     for (int i = 0; i < 16; i++) v[i] = (uint64_t)W[2 * i] | ((uint64_t)W[2 * i + 1] << 32);
 }
 
+/* LFG: with P(x) = x^r - x^(r-s) - 1, the characteristic polynomial of
+ * x_n = x_{n-s} + x_{n-r}, the shift by N outputs of an instance is
+ * J(E) for J(x) = x^N mod P(x) over Z/2^32 (P is monic, so the division
+ * needs no inverses): x_{m+N} = sum_i J_i x_{m+i}.  N = n rows = n*LFG_W
+ * values, given as n_le; poly_mulmod is a plain O(r^2) product followed by
+ * reduction from the top with x^r = x^(r-s) + 1. */
+static void lfg_mulmod(const uint32_t *a, const uint32_t *b, uint32_t *out, uint32_t *tmp, int r, int sl)
+{
+    memset(tmp, 0, 4 * (size_t)(2 * r - 1));
+    for (int i = 0; i < r; i++)
+        if (a[i])
+            for (int j = 0; j < r; j++) tmp[i + j] += a[i] * b[j];
+    for (int d = 2 * r - 2; d >= r; d--) { /* x^d = x^(d-s) + x^(d-r) */
+        tmp[d - sl] += tmp[d];
+        tmp[d - r] += tmp[d];
+        tmp[d] = 0;
+    }
+    memcpy(out, tmp, 4 * (size_t)r);
+}
+
+static int lfg_jump(int kind, uint64_t S, uint32_t *X, uint64_t lo, uint64_t hi, const uint64_t *n_le, int n_words)
+{
+    const int r = LFG_R(kind), sl = LFG_S(kind);
+    uint32_t *J = calloc(r, 4), *P = calloc(r, 4), *T = calloc(r, 4), *tmp = calloc(2 * r, 4), *E = calloc(2 * r, 4);
+    if (!J || !P || !T || !tmp || !E) { free(J); free(P); free(T); free(tmp); free(E); return -3; }
+    (void)S;
+    /* P = x^LFG_W mod P(x) (one row), J = P^n */
+    J[0] = 1;
+    P[0] = 0;
+    {
+        uint32_t *xp = calloc(r, 4);
+        xp[0] = 1;
+        for (int k = 0; k < LFG_W; k++) { /* multiply by x */
+            uint32_t top = xp[r - 1];
+            memmove(xp + 1, xp, 4 * (size_t)(r - 1));
+            xp[0] = top;          /* x^r -> 1 */
+            xp[r - sl] += top;    /*     + x^(r-s) */
+        }
+        memcpy(P, xp, 4 * (size_t)r);
+        free(xp);
+    }
+    for (int bit = 0; bit < 64 * n_words; bit++) {
+        if (exp_bit(n_le, n_words, bit)) { lfg_mulmod(J, P, T, tmp, r, sl); memcpy(J, T, 4 * (size_t)r); }
+        lfg_mulmod(P, P, T, tmp, r, sl);
+        memcpy(P, T, 4 * (size_t)r);
+    }
+    for (uint64_t g = lo / LFG_W; g < hi / LFG_W; g++) {
+        /* E[k] = x_{n-r+k}, k < 2r - 1: the state, then r - 1 further values */
+        memcpy(E, &X[(uint64_t)r * g], 4 * (size_t)r);
+        for (int k = r; k < 2 * r - 1; k++) E[k] = E[k - r] + E[k - sl];
+        for (int j = 0; j < r; j++) {
+            uint32_t acc = 0;
+            for (int i = 0; i < r; i++) acc += J[i] * E[j + i];
+            X[(uint64_t)r * g + j] = acc;
+        }
+    }
+    free(J); free(P); free(T); free(tmp); free(E);
+    return 0;
+}
+
 int orc_jump(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, const uint64_t *n_le, int n_words)
 {
     if (!kind_ok(kind, S) || lo > hi || hi > S || n_words < 1) return -1;
     if (kind == ORC_XS1024W && (lo % 32 || hi % 32)) return -1;
+    if (IS_LFG(kind)) {
+        if (lo % LFG_W || hi % LFG_W) return -1;
+        return lfg_jump(kind, S, (uint32_t *)st, lo, hi, n_le, n_words);
+    }
     uint8_t *b = (uint8_t *)st;
     uint64_t n_lo = n_le[0]; /* n mod 2^64 */
     if (kind == ORC_LCG32) {
