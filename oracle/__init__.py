@@ -11,7 +11,8 @@ Kinds are named by string so that the oracle does not depend on the product's
 enum values: "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w",
 "philox4x32_7", "lcg32_sub", "lcg64_sub" (sub-stream LCGs sharing one
 sequence), "lfg521", "lfg1279" (additive lagged Fibonacci, lags (521, 353)
-and (1279, 861), 1024 lanes per block-shared instance).
+and (1279, 861), 1024 lanes per block-shared instance), "mwc_diff" (MWC with
+a different safe-prime multiplier per stream).
 """
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ LIB_PATH = os.path.join(HERE, "liborc.so")
 SOURCES = [os.path.join(HERE, "rng_oracle.c")]
 
 KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7", "lcg32_sub", "lcg64_sub",
-         "lfg521", "lfg1279"]
+         "lfg521", "lfg1279", "mwc_diff"]
 LFG_W = 1024  # lanes (streams) of one lagged Fibonacci instance
 LFG_LAGS = {"lfg521": (521, 353), "lfg1279": (1279, 861)}
 _CODE = {k: i + 1 for i, k in enumerate(KINDS)}
@@ -77,6 +78,10 @@ def lib():
         L.orc_xs1024_variant_steps.argtypes = [i32, vp, u64]
         L.orc_xs1024_equidistribution.restype = i32
         L.orc_xs1024_equidistribution.argtypes = [i32, i32, vp]
+        L.orc_is_prime_u64.restype = i32
+        L.orc_is_prime_u64.argtypes = [u64]
+        L.orc_mwc_multipliers.restype = i32
+        L.orc_mwc_multipliers.argtypes = [u64, vp]
         L.orc_philox4x32_block.restype = None
         L.orc_philox4x32_block.argtypes = [vp, vp, i32, vp]
         L.orc_ising_sweeps_hits.restype = i32
@@ -144,6 +149,17 @@ def philox4x32_block(ctr, key, rounds: int = 10) -> list:
     out = np.zeros(4, dtype=np.uint32)
     lib().orc_philox4x32_block(_ptr(c), _ptr(k), rounds, _ptr(out))
     return [int(v) for v in out]
+
+
+def is_prime_u64(n: int) -> bool:
+    return bool(lib().orc_is_prime_u64(n))
+
+
+def mwc_multipliers(n: int) -> np.ndarray:
+    """The n largest a < 2^32 with a*2^32 - 1 a safe prime, decreasing."""
+    out = np.zeros(n, dtype=np.uint32)
+    _check(lib().orc_mwc_multipliers(n, _ptr(out)), "mwc multipliers")
+    return out
 
 
 def step_n(kind: str, S: int, st: np.ndarray, n: int, lo: int = 0, hi: int | None = None):

@@ -41,7 +41,14 @@
 #include <string.h>
 
 enum { ORC_LCG32 = 1, ORC_LCG64, ORC_MWC, ORC_XORWOW, ORC_PHILOX, ORC_XS1024W, ORC_PHILOX7, ORC_LCG32S, ORC_LCG64S,
-       ORC_LFG521, ORC_LFG1279 };
+       ORC_LFG521, ORC_LFG1279, ORC_MWCD };
+/* MWC with a different multiplier per stream (MWC section: multipliers found
+ * by working downward from 4294967118, keeping every a for which a*2^32 - 1
+ * and (a*2^32 - 2)/2 are both prime, tested with Rabin-Miller).  Stream s
+ * uses a_s, the (s+1)-th largest such a below 2^32.  Image: u64 y[S] (carry
+ * << 32 | x, as MWC), then u32 a[S]; seeding as MWC with the carry reduced
+ * mod (a_s - 1).  At most 2^21 streams (all a_s stay above 2^31). */
+#define MWCD_MAX_STREAMS (1ull << 21)
 /* Additive lagged Fibonacci generators (Lagged Fibonacci section, eq.
  * used_fibonacci): u_n = u_{n-r} + u_{n-s} mod 1 with (r, s) = (521, 353) or
  * (1279, 861).  The values are u_n = x_n / 2^32 with 32-bit words x_n, so the
@@ -128,13 +135,15 @@ size_t orc_state_bytes(int kind, uint64_t S)
     case ORC_XS1024W: return 4 * S + 8 * (S / 32) + 4;
     case ORC_LFG521:
     case ORC_LFG1279: return 4 * (uint64_t)LFG_R(kind) * (S / LFG_W);
+    case ORC_MWCD: return 12 * S;
     default: return 0;
     }
 }
 
 static int kind_ok(int kind, uint64_t S)
 {
-    if (kind < ORC_LCG32 || kind > ORC_LFG1279) return 0;
+    if (kind < ORC_LCG32 || kind > ORC_MWCD) return 0;
+    if (kind == ORC_MWCD && S > MWCD_MAX_STREAMS) return 0;
     if (kind == ORC_XS1024W && S % 32 != 0) return 0;
     if (IS_LFG(kind) && S % LFG_W != 0) return 0;
     return 1;
@@ -301,6 +310,70 @@ static void philox4x32(uint32_t k0, uint32_t k1, uint64_t block, int rounds, uin
 }
 
 /* ------------------------------------------------------------------------ */
+/* Rabin-Miller with the first twelve primes as bases: for n < 3.3e24 (all
+ * 64-bit n) a composite passes none of them all (Jaeschke 1993; Sorenson and
+ * Webster 2015), so the test is exact here. */
+static uint64_t mr_mulmod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((unsigned __int128)a * b % m); }
+
+static uint64_t mr_powmod(uint64_t b, uint64_t e, uint64_t m)
+{
+    uint64_t r = 1;
+    b %= m;
+    for (; e; e >>= 1) {
+        if (e & 1) r = mr_mulmod(r, b, m);
+        b = mr_mulmod(b, b, m);
+    }
+    return r;
+}
+
+int orc_is_prime_u64(uint64_t n)
+{
+    static const uint64_t base[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    if (n < 2) return 0;
+    for (int i = 0; i < 12; i++)
+        if (n % base[i] == 0) return n == base[i];
+    uint64_t d = n - 1;
+    int s = 0;
+    while (!(d & 1)) { d >>= 1; s++; }
+    for (int i = 0; i < 12; i++) {
+        uint64_t x = mr_powmod(base[i], d, n);
+        if (x == 1 || x == n - 1) continue;
+        int witness = 1;
+        for (int r = 1; r < s && witness; r++) {
+            x = mr_mulmod(x, x, n);
+            if (x == n - 1) witness = 0;
+        }
+        if (witness) return 0;
+    }
+    return 1;
+}
+
+/* The n largest multipliers a < 2^32 with a*2^32 - 1 and (a*2^32 - 2)/2
+ * prime, in decreasing order (cached between calls); returns 0, or -3. */
+static uint32_t *g_mult = NULL;
+static uint64_t g_mult_n = 0, g_mult_cap = 0;
+static uint64_t g_mult_next = 0xFFFFFFFFull; /* next candidate to test */
+
+int orc_mwc_multipliers(uint64_t n, uint32_t *out)
+{
+    if (n > MWCD_MAX_STREAMS) return -1;
+    if (g_mult_cap < n) {
+        uint32_t *m = (uint32_t *)realloc(g_mult, 4 * n);
+        if (!m) return -3;
+        g_mult = m;
+        g_mult_cap = n;
+    }
+    while (g_mult_n < n && g_mult_next > 1) {
+        uint64_t a = g_mult_next--;
+        uint64_t p = (a << 32) - 1;
+        if (orc_is_prime_u64((p - 1) / 2) && orc_is_prime_u64(p)) g_mult[g_mult_n++] = (uint32_t)a;
+    }
+    if (g_mult_n < n) return -1;
+    memcpy(out, g_mult, 4 * n);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Seeding: every stream's initial state derives from SM(.) of the master
  * seed by fixed indices (project definition). */
 int orc_seed(int kind, uint64_t S, uint64_t seed, void *st)
@@ -350,6 +423,16 @@ int orc_seed(int kind, uint64_t S, uint64_t seed, void *st)
         for (uint64_t s = 0; s < S; s++) {
             uint64_t z = orc_splitmix(seed, 1 + s);
             k0[s] = (uint32_t)z; k1[s] = (uint32_t)(z >> 32); pos[s] = 0;
+        }
+    } else if (kind == ORC_MWCD) {
+        uint64_t *y = (uint64_t *)b;
+        uint32_t *a = (uint32_t *)(b + 8 * S);
+        if (orc_mwc_multipliers(S, a)) return -3;
+        for (uint64_t s = 0; s < S; s++) {
+            uint64_t z = orc_splitmix(seed, 1 + s);
+            uint64_t x = z & 0xFFFFFFFFull, c = (z >> 32) % ((uint64_t)a[s] - 1);
+            if (x == 0 && c == 0) x = 1;
+            y[s] = (c << 32) | x;
         }
     } else if (IS_LFG(kind)) {
         const uint64_t r = LFG_R(kind), H = (r + 1) / 2;
@@ -464,6 +547,16 @@ int orc_generate(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, uint6
                 uint64_t x = y[s] & 0xFFFFFFFFull, c = y[s] >> 32;
                 uint64_t t = MWC_A * x + c; /* < 2^64 since a < 2^32, c < a */
                 y[s] = t;                   /* new carry t>>32, new x t mod 2^32 */
+                emit(mode, out, k, width, s - lo, (uint32_t)t);
+            }
+    } else if (kind == ORC_MWCD) {
+        uint64_t *y = (uint64_t *)b;
+        const uint32_t *a = (const uint32_t *)(b + 8 * S);
+        for (uint64_t s = lo; s < hi; s++)
+            for (uint64_t k = 0; k < count; k++) {
+                uint64_t x = y[s] & 0xFFFFFFFFull, c = y[s] >> 32;
+                uint64_t t = (uint64_t)a[s] * x + c; /* < 2^64: a < 2^32, c < a */
+                y[s] = t;
                 emit(mode, out, k, width, s - lo, (uint32_t)t);
             }
     } else if (kind == ORC_XORWOW) {
@@ -760,6 +853,17 @@ int orc_jump(int kind, uint64_t S, void *st, uint64_t lo, uint64_t hi, const uin
         }
         uint64_t *y = (uint64_t *)b;
         for (uint64_t s = lo; s < hi; s++) y[s] = mulmod64(an, y[s], p);
+    } else if (kind == ORC_MWCD) { /* y -> a_s^n y mod p_s, p_s = a_s 2^32 - 1, per stream */
+        uint64_t *y = (uint64_t *)b;
+        const uint32_t *a = (const uint32_t *)(b + 8 * S);
+        for (uint64_t s = lo; s < hi; s++) {
+            uint64_t p = ((uint64_t)a[s] << 32) - 1, an = 1, sq = a[s];
+            for (int bit = 0; bit < 64 * n_words; bit++) {
+                if (exp_bit(n_le, n_words, bit)) an = mulmod64(an, sq, p);
+                sq = mulmod64(sq, sq, p);
+            }
+            y[s] = mulmod64(an, y[s], p);
+        }
     } else if (kind == ORC_XORWOW) {
         uint32_t *X = (uint32_t *)b, *Y = X + S, *Z = Y + S, *Wd = Z + S, *V = Wd + S, *D = V + S;
         uint64_t m = hi - lo, *v = (uint64_t *)calloc(3 * (m ? m : 1), 8);

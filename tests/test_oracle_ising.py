@@ -60,7 +60,7 @@ def test_infinite_temperature_flips_everything(orc, kind):
 
 
 def test_zero_temperature_ignores_the_generator(orc):
-    L = 32
+    L = 64  # every kind, the lagged Fibonacci ones included (L % 64 == 0)
     ref = None
     for kind in orc.KINDS:
         sp, st = orc.ising_create(L, kind, 9)
@@ -166,7 +166,7 @@ def test_multihit_neel_zero_temperature(orc, hits):
 
 
 def test_multihit_zero_temperature_ignores_the_generator(orc):
-    L = 32
+    L = 64
     for hits in (2, 3):
         ref = None
         for kind in orc.KINDS:
