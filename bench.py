@@ -118,6 +118,8 @@ def bench_ising(rx, kind, L, sweeps, beta=0.4, hits=1):
     tr = torch.zeros(sweeps, dtype=torch.int32, device="cuda")
     durs, _ = time_launches(lambda: rx.ising_sweep_hits(lat, beta, sweeps, hits, tr), 1, 0)
     ms = durs[0]
+    if rx.ising_status(lat):
+        raise RuntimeError(f"Ising {kind} L={L}: a strip gave up waiting; the timed lattice is invalid")
     rec = {"sweeps": sweeps, "ms": round(ms, 3), "flips_per_ns": round(L * L * sweeps * hits / (ms * 1e6), 2),
            "strips": rx.ising_info(lat)["strips"],
            "autotune": {"plans": plans, "ms_per_20_sweeps": [round(m, 3) for m in tune_ms]}}
@@ -127,12 +129,13 @@ def bench_ising(rx, kind, L, sweeps, beta=0.4, hits=1):
     return rec
 
 
-def bench_ising_batch(rx, n=512, sweeps=10000, base_sweeps=1000, seed=1):
+def bench_ising_batch(rx, n=512, sweeps=10000, seed=1):
     """512 XS1024W replicas, L uniform over {16, 32, ..., 1024}, beta uniform in
     [0.3, 0.6], drawn with numpy default_rng(seed): one batched launch for
-    `sweeps` sweeps, then the same replicas one ising_sweep call each for
-    `base_sweeps` sweeps (the per-launch form, scaled down to keep the run
-    short; rates are per flip)."""
+    `sweeps` sweeps, then the same replicas from the same start one
+    ising_sweep call each for the same `sweeps` (the per-launch form), both
+    timed with HIP events on the stream they run on.  Every replica's status
+    is checked after each form, so an invalid lattice fails the bench."""
     import numpy as np
     import torch
     rng = np.random.default_rng(seed)
@@ -143,22 +146,39 @@ def bench_ising_batch(rx, n=512, sweeps=10000, base_sweeps=1000, seed=1):
     batch = rx.ising_batch_create(lats, betas, [sweeps] * n)
     durs, _ = time_launches(lambda: rx.ising_batch_run(batch), 1, 0)
     batched_ms = durs[0]
+    bad = rx.ising_batch_status(batch)
     batch.destroy()
-    t = time.perf_counter()
-    for lat, b in zip(lats, betas):
-        rx.ising_sweep(lat, b, base_sweeps)
-    torch.cuda.synchronize()
-    single_ms = (time.perf_counter() - t) * 1e3
+    if bad:
+        raise RuntimeError(f"Ising batch: {bad} replicas are invalid after the timed run")
+    for lat in lats:
+        lat.destroy()
+    lats = [rx.ising_create(L, "xs1024w", 1000 + i) for i, L in enumerate(Ls)]
+
+    def per_launch():
+        for lat, b in zip(lats, betas):
+            rx.ising_sweep(lat, b, sweeps)
+
+    durs, _ = time_launches(per_launch, 1, 0)
+    single_ms = durs[0]
+    bad = sum(rx.ising_status(lat) for lat in lats)
+    for lat in lats:
+        lat.destroy()
+    if bad:
+        raise RuntimeError(f"Ising per-launch leg: {bad} lattices are invalid after the timed run")
     return {"replicas": n, "sites": sites, "sweeps": sweeps, "batched_ms": round(batched_ms, 2),
             "batched_flips_per_ns": round(sites * sweeps / (batched_ms * 1e6), 2),
-            "per_launch_sweeps": base_sweeps, "per_launch_ms": round(single_ms, 2),
-            "per_launch_flips_per_ns": round(sites * base_sweeps / (single_ms * 1e6), 2)}
+            "per_launch_sweeps": sweeps, "per_launch_ms": round(single_ms, 2),
+            "per_launch_flips_per_ns": round(sites * sweeps / (single_ms * 1e6), 2)}
 
 
-def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_units=64):
+def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_requests=256):
     """10^4 requests with lengths log-uniform in [2^10, 2^22] (numpy
     default_rng(seed)); XS1024W requests are per instance.  One ragged call
-    vs one single-stream launch per request on a subset (rate compared)."""
+    (3 timed after 1 warm-up) vs the plain form, one launch per request: a
+    generator of one stream (XS1024W: one instance) per request, created
+    before the timed region, fills its request at its offset.  The plain form
+    is timed over `baseline_requests` requests drawn at random without
+    replacement (numpy default_rng(seed + 1)); rates are values per second."""
     import numpy as np
     import torch
     rng = np.random.default_rng(seed)
@@ -167,25 +187,36 @@ def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_units=64):
     S = 32 * n if kind == "xs1024w" else n
     g = rx.rng_create(kind, S, 1)
     plan = rx.rng_ragged_create(g, off)
-    out = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
+    out = torch.empty(int(off[-1]) + 32, dtype=torch.int32, device="cuda")
     durs, _ = time_launches(lambda: rx.rng_fill_ragged_u32(plan, out), 3, 1)
     ms = sum(durs) / len(durs)
     total = int(off[-1])
-    # one launch per request: a single-stream (XS1024W: one-instance) generator
-    # per request filling its own length, for the first `baseline_units`
+    plan.destroy()
+    g.destroy()
     width = 32 if kind == "xs1024w" else 1
-    sub = 0
-    t = time.perf_counter()
-    for u in range(baseline_units):
-        gu = rx.rng_create(kind, width, 1 + u)
+    pick = np.sort(np.random.default_rng(seed + 1).choice(n, size=min(baseline_requests, n), replace=False))
+    gens = [rx.rng_create(kind, width, 1 + int(u)) for u in pick]
+    # a request's values start at its offset; XS1024W instances write whole
+    # 32-value rows, so each view starts at a 16-byte aligned position
+    views = []
+    for u in pick:
+        o = int(off[u]) // 4 * 4
         cnt = -(-int(lens[u]) // width)
-        rx.rng_fill_u32(gu, out, cnt)
-        sub += int(lens[u])
-    torch.cuda.synchronize()
-    base_s = time.perf_counter() - t
+        views.append((out[o:o + cnt * width], cnt))
+
+    def per_request():
+        for gu, (v, cnt) in zip(gens, views):
+            rx.rng_fill_u32(gu, v, cnt)
+
+    durs, _ = time_launches(per_request, 1, 0)
+    sub = int(sum(int(lens[u]) for u in pick))
+    for gu in gens:
+        gu.destroy()
     return {"kind": kind, "requests": n, "values": total, "ms": round(ms, 3),
             "gsamples_s": round(total / ms / 1e6, 2), "gbs": round(total * 4 / ms / 1e6, 1),
-            "per_launch_requests": baseline_units, "per_launch_gsamples_s": round(sub / base_s / 1e9, 3)}
+            "hbm_frac": round(total * 4 / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "per_launch_requests": len(pick), "per_launch_values": sub, "per_launch_ms": round(durs[0], 2),
+            "per_launch_gsamples_s": round(sub / durs[0] / 1e6, 3)}
 
 
 def bench_serve(rx, n_req=20000, rate=2000.0, clients=64, slots=8, inflight=32, seed=1, budget=64 << 30):
@@ -258,19 +289,36 @@ def traffic_from_profile():
     return rec.get("bytes_per_launch")
 
 
+def host_threads() -> int:
+    """Host threads for the CPU oracle: every core this process may run on,
+    capped at 16, the CPU share a one-GPU job gets on the GPU hosts."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(target_s: float = 10.0):
     """The CPU oracle (never tuned) on a bounded sample of the same workload:
     XS1024W u32 fill of all 2^20 streams, the first n outputs of each (n sized
-    for about target_s seconds of wall time), streams split over host
-    threads, each thread producing its block 64 outputs per oracle call."""
+    for about target_s seconds of wall time), streams split over the host
+    threads, each thread producing its block 64 outputs per oracle call; the
+    one-thread rate of the same call beside it.  Then the oracle's Ising
+    sweep, which is serial: one independent lattice per host thread, at L = 64
+    (2000 sweeps) and at L = 4096 (3 sweeps; the 10^4-sweep run is
+    extrapolated from that rate)."""
     from concurrent.futures import ThreadPoolExecutor
     import oracle
-    threads = min(16, os.cpu_count() or 1)
+    threads = host_threads()
     S = S_FULL
     st = oracle.seed("xs1024w", S, 1)
+    probe = st.copy()
+    oracle.generate("xs1024w", S, probe, 64, lo=0, hi=32 * 1024)  # warm-up
     t = time.perf_counter()
-    oracle.generate("xs1024w", S, st.copy(), 64, lo=0, hi=32 * 256)
-    rate1 = 32 * 256 * 64 / (time.perf_counter() - t)  # values/s on one thread
+    oracle.generate("xs1024w", S, probe, 64, lo=0, hi=32 * 1024)
+    rate1 = 32 * 1024 * 64 / (time.perf_counter() - t)  # values/s on one thread
+    del probe
     n = max(64, int(rate1 * threads * target_s / S) // 64 * 64)
     chunk = S // threads
 
@@ -283,9 +331,29 @@ def cpu_baseline(target_s: float = 10.0):
     with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(work, range(threads)))
     dt = time.perf_counter() - t
+
+    def ising_rate(L, sweeps):
+        lats = [oracle.ising_create(L, "xs1024w", 1 + i) for i in range(threads)]
+
+        def run(i):
+            sp, stt = lats[i]
+            oracle.ising_sweeps(L, "xs1024w", 0.4, stt, sp, sweeps, trace=True)
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(run, range(threads)))
+        w = time.perf_counter() - t0
+        return {"L": L, "sweeps": sweeps, "lattices": threads, "wall_s": round(w, 2),
+                "flips_per_ns": round(threads * L * L * sweeps / w / 1e9, 5)}
+
+    ising = [ising_rate(64, 2000), ising_rate(4096, 3)]
+    ising[1]["note"] = "rate at L=4096 from 3 sweeps; 10^4 sweeps extrapolated at that rate"
+    ising[1]["extrapolated_1e4_sweeps_s"] = round(4096 * 4096 * 1e4 / (ising[1]["flips_per_ns"] * 1e9), 1)
     return {"value": round(S * n / dt / 1e9, 4), "unit": "Gsamples/s", "cores": threads, "kind": "oracle",
             "sample": f"xs1024w u32 fill of {S} streams x first {n} outputs ({S * n} values, {dt:.1f} s wall, "
-                      f"{threads} threads over stream blocks)"}
+                      f"{threads} threads over stream blocks)",
+            "single_thread_gsamples_s": round(rate1 / 1e9, 4), "host_cpus_visible": os.cpu_count(),
+            "ising_xs1024w_beta0.4": ising}
 
 
 def main():
@@ -327,6 +395,11 @@ def main():
         for _ in range(args.steps):
             rx.ising_sweep(lat, 0.4, 200, tr)
         torch.cuda.synchronize()
+        if rx.ising_status(lat):
+            raise RuntimeError("profile pass: the lattice is invalid")
+        lat.destroy()
+        del tr
+        torch.cuda.synchronize()
         print(f"profile pass done: {args.steps} calls of 200 sweeps at L=4096", flush=True)
         return
     if args.profile_ragged:
@@ -354,6 +427,12 @@ def main():
         batch = rx.ising_batch_create(lats, betas, [1000] * 512)
         for _ in range(args.steps):
             rx.ising_batch_run(batch)
+        torch.cuda.synchronize()
+        if rx.ising_batch_status(batch):
+            raise RuntimeError("profile pass: invalid replicas")
+        batch.destroy()
+        for lat in lats:
+            lat.destroy()
         torch.cuda.synchronize()
         print(f"profile pass done: {args.steps} batch runs of 512 replicas x 1000 sweeps", flush=True)
         return

@@ -303,6 +303,13 @@ rngx_status ising_set_spins(rngx_ising lat, const int8_t *host_spins, void *stre
  * rng_get_state / rng_set_state).  It must not be destroyed by the caller. */
 rngx_status ising_rng(rngx_ising lat, rngx_gen *g);
 
+/* Whether the lattice is valid (waits for `stream`): *invalid receives 0,
+ * or 1 if a strip of a multi-workgroup sweep gave up waiting for a
+ * neighbour's boundary spins (a bounded wait, reached only when the strips
+ * could not run at the same time), after which spins and state are
+ * meaningless until replaced by ising_set_spins and rng_set_state. */
+rngx_status ising_status(rngx_ising lat, uint32_t *invalid, void *stream);
+
 /* Release the lattice, its spins and its streams. */
 rngx_status ising_destroy(rngx_ising lat);
 
@@ -317,10 +324,25 @@ rngx_status ising_destroy(rngx_ising lat);
  * and may be captured in a HIP graph.  The lattices must outlive the batch:
  * ising_destroy returns RNGX_E_BUSY for a lattice that a batch holds.
  * Errors: RNGX_E_INVALID (n = 0, NULL arrays, unknown or repeated handles,
- * mixed kinds or devices, bad beta). */
+ * mixed kinds or devices, bad beta).
+ *
+ * Large replicas run as gangs of strip workgroups that wait on each other
+ * every pass, so all strips of a gang must run at the same time.  Outside
+ * graph capture a run is a cooperative launch, which guarantees that.  A
+ * captured run relies on the grid being no larger than what fits on the
+ * device at once: other kernels running beside it only delay it, unless
+ * they hold the device for longer than a gang member waits for the others
+ * to start (60 s); then that replica is marked invalid (ising_status,
+ * ising_batch_status) rather than left with wrong spins unreported.
+ * ising_batch_status waits for `stream` and counts the invalid replicas. */
 rngx_status ising_batch_create(const rngx_ising *lats, uint32_t n, const double *betas, const uint64_t *n_sweeps,
                                int32_t *const *d_traces, rngx_ising_batch *out);
 rngx_status ising_batch_run(rngx_ising_batch b, void *stream);
+rngx_status ising_batch_status(rngx_ising_batch b, uint32_t *n_invalid, void *stream);
+/* The launch shape of a run: work items (one per single-workgroup replica,
+ * one per strip of a gang) and workgroups of the persistent grid.  Either
+ * pointer may be NULL. */
+rngx_status ising_batch_info(rngx_ising_batch b, uint32_t *n_items, uint32_t *grid);
 rngx_status ising_batch_destroy(rngx_ising_batch b);
 
 /* Served form.  A server admits requests in arrival order as soon as its

@@ -10,6 +10,7 @@ librngx.so is absent the import of the library fails.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -55,10 +56,13 @@ SIGNATURES = {
     "ising_get_spins": (_i32, [_vp, _vp, _vp]),
     "ising_set_spins": (_i32, [_vp, _vp, _vp]),
     "ising_rng": (_i32, [_vp, ctypes.POINTER(_vp)]),
+    "ising_status": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), _vp]),
     "ising_destroy": (_i32, [_vp]),
     "ising_batch_create": (_i32, [ctypes.POINTER(_vp), ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(_u64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "ising_batch_run": (_i32, [_vp, _vp]),
+    "ising_batch_status": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), _vp]),
+    "ising_batch_info": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
     "ising_batch_destroy": (_i32, [_vp]),
     "srv_create": (_i32, [ctypes.c_void_p, ctypes.POINTER(_vp)]),
     "srv_submit_fill": (_i32, [_vp, ctypes.c_uint32, _i32, _u64, _i32, ctypes.POINTER(_u64)]),
@@ -89,6 +93,23 @@ class RngxError(RuntimeError):
 
 
 _lib = None
+# Set when the interpreter starts to exit: handles still alive then are not
+# destroyed by their finalizers (which would call into the HIP runtime while
+# it, torch and any attached profiler are being torn down); the process exit
+# releases their device memory.  Destroy handles explicitly to free it sooner.
+_exiting = False
+
+
+def _mark_exiting():
+    global _exiting
+    _exiting = True
+
+
+atexit.register(_mark_exiting)
+
+
+def _finalizing() -> bool:
+    return _exiting or _lib is None
 
 
 def load():
@@ -151,7 +172,7 @@ class Gen:
         self.n_streams = s.value
 
     def __del__(self):
-        if getattr(self, "owned", False) and self.handle and _lib is not None:
+        if getattr(self, "owned", False) and self.handle and not _finalizing():
             _lib.rng_destroy(self.handle)
             self.handle = None
 
@@ -239,7 +260,7 @@ class Ragged:
         self.total = total
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and not _finalizing():
             _lib.rng_ragged_destroy(self.handle)
             self.handle = None
 
@@ -291,7 +312,7 @@ class Ising:
         self.kind = kind
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and not _finalizing():
             _lib.ising_destroy(self.handle)
             self.handle = None
 
@@ -404,6 +425,13 @@ def ising_set_spins(lat: Ising, spins, stream=None):
     _check(load().ising_set_spins(lat.handle, buf.ctypes.data, _stream(stream)))
 
 
+def ising_status(lat: Ising, stream=None) -> int:
+    """1 if a strip gave up waiting for a neighbour (the lattice is invalid), else 0."""
+    v = ctypes.c_uint32()
+    _check(load().ising_status(lat.handle, ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
 def ising_rng(lat: Ising) -> Gen:
     h = _vp()
     _check(load().ising_rng(lat.handle, ctypes.byref(h)))
@@ -423,7 +451,7 @@ class IsingBatch:
         self.traces = traces
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and not _finalizing():
             _lib.ising_batch_destroy(self.handle)
             self.handle = None
 
@@ -449,6 +477,20 @@ def ising_batch_create(lats, betas, n_sweeps, traces=None) -> IsingBatch:
 
 def ising_batch_run(batch: IsingBatch, stream=None):
     _check(load().ising_batch_run(batch.handle, _stream(stream)))
+
+
+def ising_batch_status(batch: IsingBatch, stream=None) -> int:
+    """Number of replicas of the batch that are invalid (see ising_status)."""
+    v = ctypes.c_uint32()
+    _check(load().ising_batch_status(batch.handle, ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
+def ising_batch_info(batch: IsingBatch) -> dict:
+    """{"items": work items, "grid": workgroups of the persistent launch}."""
+    n, g = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().ising_batch_info(batch.handle, ctypes.byref(n), ctypes.byref(g)))
+    return {"items": n.value, "grid": g.value}
 
 
 def ising_batch_destroy(batch: IsingBatch):
@@ -495,6 +537,6 @@ class Server:
         self.handle = None
 
     def __del__(self):
-        if getattr(self, "handle", None) and _lib is not None:
+        if getattr(self, "handle", None) and not _finalizing():
             _lib.srv_destroy(self.handle)
             self.handle = None

@@ -742,6 +742,21 @@ rngx_status ising_get_spins(rngx_ising h, int8_t *host_spins, void *stream) {
     return RNGX_OK;
 }
 
+rngx_status ising_status(rngx_ising h, uint32_t *invalid, void *stream) {
+    Ising *lat;
+    if (rngx_status s = check_ising(h, &lat)) return s;
+    if (!invalid) return fail(RNGX_E_INVALID, "invalid is NULL");
+    DeviceScope ds(lat->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint32_t err = 0;
+    hipError_t e = hipMemcpyAsync(&err, lat->d_err, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "status copy to host");
+    *invalid = err ? 1 : 0;
+    clear_error();
+    return RNGX_OK;
+}
+
 rngx_status ising_set_spins(rngx_ising h, const int8_t *host_spins, void *stream) {
     Ising *lat;
     if (rngx_status s = check_ising(h, &lat)) return s;
@@ -812,6 +827,34 @@ rngx_status ising_batch_run(rngx_ising_batch h, void *stream) {
     DeviceScope ds(b->device);
     hipError_t e = launch_batch(b, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_batch_status(rngx_ising_batch h, uint32_t *n_invalid, void *stream) {
+    IsingBatch *b;
+    if (rngx_status s = check_batch(h, &b)) return s;
+    if (!n_invalid) return fail(RNGX_E_INVALID, "n_invalid is NULL");
+    DeviceScope ds(b->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<uint32_t> err(b->n, 0);
+    hipError_t e = hipSuccess;
+    for (uint32_t i = 0; i < b->n && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(&err[i], b->lats[i]->d_err, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "status copy to host");
+    uint32_t bad = 0;
+    for (uint32_t v : err) bad += v ? 1 : 0;
+    *n_invalid = bad;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_batch_info(rngx_ising_batch h, uint32_t *n_items, uint32_t *grid) {
+    IsingBatch *b;
+    if (rngx_status s = check_batch(h, &b)) return s;
+    if (n_items) *n_items = b->n_items;
+    if (grid) *grid = b->grid;
     clear_error();
     return RNGX_OK;
 }

@@ -216,6 +216,8 @@ struct ReplicaDesc {
     uint64_t *halo;   // strips: 2 slots x nwg x 2 rows x L/4 tagged words
     uint32_t *err;    // the lattice's error word (a strip gave up waiting)
     uint32_t R_last;  // strips: rows of the last strip (1..R; the others have R)
+    uint32_t *gang;   // strips: arrival counter of the gang's workgroups (zeroed before each run)
+    uint64_t start_ticks;  // strips: wall-clock ticks a gang member waits for the others to start
 };
 
 struct StripArgs {
@@ -808,6 +810,30 @@ __device__ void replica_in_memory(const ReplicaDesc &d, int *red) {
     }
 }
 
+// A gang's strips wait on each other every pass, so none of them may start
+// its sweeps before all of them run.  Items are claimed one at a time, so the
+// first strips of a gang can be claimed long before the last ones (the other
+// workgroups may be busy with long independent items): each member checks in
+// and waits here, bounded by wall-clock time rather than a poll count, until
+// all nwg have arrived.  They always do, as every other claimed item finishes
+// on its own and frees its workgroup for the gang's next strip; if the bound
+// is reached anyway (the device held by other work for that long), the
+// lattice is marked invalid and its strips end quickly.
+__device__ void gang_start(const ReplicaDesc &d) {
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(d.gang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = static_cast<uint64_t>(wall_clock64());
+        while (__hip_atomic_load(d.gang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < d.nwg) {
+            if (static_cast<uint64_t>(wall_clock64()) - t0 > d.start_ticks || __hip_atomic_load(d.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_fetch_or(d.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(127);
+        }
+    }
+    __syncthreads();
+}
+
 // Units per thread of an on-chip replica (at most 16384 four-site or 8192
 // eight-site units, i.e. L <= 256, with 1024 threads).
 template <class Unit>
@@ -839,6 +865,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc
             replica_in_memory<Unit>(d, red_s);
             continue;
         }
+        if (d.mode == kReplicaStrips) gang_start(d);
         const uint32_t R = item.y + 1 == d.nwg ? d.R_last : d.R;
         const uint32_t units = R * (d.L / NB);
         const StripArgs a{d.spins, d.st, d.S, d.L, R, d.nwg, units, d.T4, d.T8, d.n_sweeps, d.trace,
@@ -858,6 +885,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_prologue(const ReplicaDesc *re
     uint32_t *h = reinterpret_cast<uint32_t *>(d.halo);
     const uint64_t words = 2ull * d.nwg * d.L;
     for (uint64_t i = threadIdx.x; i < words; i += kBlock) h[i] = 0;
+    if (threadIdx.x == 0) *d.gang = 0;
     if (d.trace)
         for (uint64_t i = threadIdx.x; i < d.n_sweeps; i += kBlock) d.trace[i] = 0;
 }
@@ -1031,6 +1059,8 @@ hipError_t run(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hi
 
 constexpr uint32_t kBatchLdsCap = 80 * 1024;  // keeps two batch workgroups per CU
 constexpr uint32_t kMaxGang = 64;             // most strips of one batch replica
+constexpr uint64_t kGangWordBytes = 64;       // a gang's arrival counter, after its halo words
+constexpr double kGangStartSeconds = 60.0;    // longest wait of a gang member for the others to start
 
 template <class Unit>
 const void *batch_kernel() { return reinterpret_cast<const void *>(&k_ising_batch<Unit>); }
@@ -1091,7 +1121,7 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
             d.nwg = nwg;
             d.units = static_cast<uint32_t>(units);
             lds = std::max<uint32_t>(lds, static_cast<uint32_t>(strip_lds_bytes(L, R)));
-            if (nwg > 1) halo_bytes += 8ull * nwg * L;
+            if (nwg > 1) halo_bytes += 8ull * nwg * L + kGangWordBytes;
             break;
         }
         reps[i] = d;
@@ -1122,6 +1152,9 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
         items.clear();
         for (uint32_t x : order) items.push_back(make_uint2(x, 0));
     }
+    int clock_khz = 0;  // wall_clock64() rate
+    if ((e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, b->device)) != hipSuccess) return e;
+    const uint64_t start_ticks = static_cast<uint64_t>(kGangStartSeconds * 1e3 * std::max(clock_khz, 1));
     b->lds = lds;
     b->n_items = static_cast<uint32_t>(items.size());
     b->grid = std::min<uint32_t>(b->n_items, resident);
@@ -1131,7 +1164,9 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
         for (auto &d : reps)
             if (d.mode == kReplicaStrips) {
                 d.halo = reinterpret_cast<uint64_t *>(reinterpret_cast<uint8_t *>(b->d_halo) + off);
-                off += 8ull * d.nwg * d.L;
+                d.gang = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(b->d_halo) + off + 8ull * d.nwg * d.L);
+                d.start_ticks = start_ticks;
+                off += 8ull * d.nwg * d.L + kGangWordBytes;
             }
     }
     if ((e = hipMalloc(&b->d_reps, sizeof(ReplicaDesc) * n)) != hipSuccess) return e;
@@ -1146,19 +1181,21 @@ hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
     const auto *reps = static_cast<const ReplicaDesc *>(b->d_reps);
     const auto *items = static_cast<const uint2 *>(b->d_items);
     hipLaunchKernelGGL(k_batch_prologue, dim3(b->n), dim3(kBlock), 0, st, reps, b->d_next);
-    const dim3 grid(b->grid), block(kBatchThreads);
-    switch (b->kind) {
-    case RNGX_LCG32: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg32>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    case RNGX_LCG32_SUB: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg32Sub>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    case RNGX_LCG64: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg64>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    case RNGX_LCG64_SUB: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Lcg64Sub>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    case RNGX_MWC: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Mwc>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    case RNGX_XORWOW: hipLaunchKernelGGL(k_ising_batch<SmallUnit<Xorwow>>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ising_batch<PhiloxUnit>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_ising_batch<PhiloxUnit7>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    case RNGX_XS1024W: hipLaunchKernelGGL(k_ising_batch<XsUnit>, grid, block, b->lds, st, reps, items, b->n_items, b->d_next); break;
-    }
-    return hipGetLastError();
+    const void *fn = batch_kernel_for(b->kind);
+    if (!fn) return hipErrorInvalidValue;
+    uint32_t n_items = b->n_items;
+    uint32_t *next = b->d_next;
+    void *args[] = {&reps, &items, &n_items, &next};
+    // Outside graph capture the launch is cooperative, which makes the whole
+    // grid resident together whatever else runs on the device; a captured
+    // launch relies on the grid fitting (it is sized to what is resident at
+    // once) and on the gang start wait.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cap);
+    if (e != hipSuccess) return e;
+    if (cap == hipStreamCaptureStatusNone)
+        return hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(kBatchThreads), args, b->lds, st);
+    return hipLaunchKernel(fn, dim3(b->grid), dim3(kBatchThreads), args, b->lds, st);
 }
 
 namespace {

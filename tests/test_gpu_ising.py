@@ -101,9 +101,9 @@ def test_checkpoint_resume(rngx):
 
 @pytest.mark.parametrize("kind", KINDS)
 def test_large_lattice_parity(rngx, orc, kind):
-    """L = 4096 (the throughput workload) for 3 sweeps in two calls, bit-exact."""
+    """L = 4096 (the throughput workload) for 10 sweeps in two calls, bit-exact."""
     print(f"case ising L=4096 {kind}", flush=True)
-    lat = _run_both(rngx, orc, 4096, kind, 0.4, 3, chunks=(2, 1))
+    lat = _run_both(rngx, orc, 4096, kind, 0.4, 10, chunks=(6, 4))
     assert rngx.ising_info(lat)["strips"] == 256
 
 
@@ -241,7 +241,7 @@ def test_batch_equals_individual_sweeps(rngx, kind):
 
 
 @pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
-def test_batch_gangs_and_memory_replicas(rngx, kind):
+def test_batch_gangs_and_memory_replicas(rngx, orc, kind):
     """Large replicas run as gangs of strip workgroups or, beyond the largest
     gang, in memory (L = 4096); each equals ising_sweep on the lattice alone.
     XS1024W gangs: 1024 = 16 x 64 rows; 1008 = 15 x 64 + 48; 976 = 15 x 64
@@ -253,10 +253,19 @@ def test_batch_gangs_and_memory_replicas(rngx, kind):
     betas, sweeps = [0.4, 0.35, 0.5, 0.44, 0.41, 0.45, 0.38, 0.3], [3, 2, 4, 3, 2, 3, 2, 5]
     lats = [rngx.ising_create(L, kind, 300 + i) for i, L in enumerate(Ls)]
     twins = [rngx.ising_create(L, kind, 300 + i) for i, L in enumerate(Ls)]
+    refs = [orc.ising_create(L, kind, 300 + i) for i, L in enumerate(Ls)]
     traces = [torch.full((s,), 7, dtype=torch.int32, device="cuda") for s in sweeps]
     batch = rngx.ising_batch_create(lats, betas, sweeps, traces)
     for rep in range(2):
         rngx.ising_batch_run(batch)
+        assert rngx.ising_batch_status(batch) == 0
+        # the oracle directly: every gang (uneven last strips) and the
+        # replica streamed through memory (L = 4096)
+        for i, (sp, st) in enumerate(refs):
+            want = orc.ising_sweeps(Ls[i], kind, betas[i], st, sp, sweeps[i])
+            assert np.array_equal(traces[i].cpu().numpy(), want), (rep, i, Ls[i])
+            assert np.array_equal(rngx.ising_get_spins(lats[i]).ravel(), sp), (rep, i, Ls[i])
+            assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[i])), st), (rep, i, Ls[i])
         for i, tw in enumerate(twins):
             tt = torch.zeros(sweeps[i], dtype=torch.int32, device="cuda")
             rngx.ising_sweep(tw, betas[i], sweeps[i], tt)
@@ -289,6 +298,37 @@ def test_batch_every_size_to_1040(rngx, kind):
         assert np.array_equal(rngx.ising_get_spins(lats[i]), rngx.ising_get_spins(tw)), Ls[i]
         assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[i])),
                               rngx.rng_get_state(rngx.ising_rng(tw))), Ls[i]
+
+
+def test_batch_gang_behind_long_replicas(rngx, orc):
+    """A gang whose first strip is claimed while every other workgroup runs a
+    long on-chip replica: its remaining strips start only when those finish
+    (about a second later), so its members must wait to start together
+    rather than give up.  Regression test for gang members that timed out
+    waiting for strips not yet started; the gang is compared with the
+    oracle and every replica must be valid."""
+    kind = "xs1024w"
+    probe = rngx.ising_batch_create([rngx.ising_create(64, kind, 1)], [0.4], [1])
+    grid = rngx.ising_batch_info(probe)["grid"]
+    probe.destroy()
+    gang_L, gang_sweeps = 1024, 3
+    n_long = max(grid, 2) - 2  # leaves one workgroup for the gang's first strip
+    Ls = [64] * n_long + [gang_L]
+    betas = [0.4] * n_long + [0.44]
+    sweeps = [400_000] * n_long + [gang_sweeps]
+    print(f"case batch gang behind {n_long} long replicas (grid {grid})", flush=True)
+    lats = [rngx.ising_create(L, kind, 900 + i) for i, L in enumerate(Ls)]
+    tr = torch.zeros(gang_sweeps, dtype=torch.int32, device="cuda")
+    batch = rngx.ising_batch_create(lats, betas, sweeps, [None] * n_long + [tr])
+    info = rngx.ising_batch_info(batch)
+    assert info["items"] > info["grid"]  # the gang cannot start in the first wave
+    rngx.ising_batch_run(batch)
+    assert rngx.ising_batch_status(batch) == 0
+    sp, st = orc.ising_create(gang_L, kind, 900 + n_long)
+    want = orc.ising_sweeps(gang_L, kind, 0.44, st, sp, gang_sweeps)
+    assert np.array_equal(tr.cpu().numpy(), want)
+    assert np.array_equal(rngx.ising_get_spins(lats[-1]).ravel(), sp)
+    assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[-1])), st)
 
 
 def test_batch_small_replicas_match_oracle(rngx, orc):
