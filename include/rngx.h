@@ -48,6 +48,11 @@
  *   XS1024W  word i of instance g = low32 (i even) / high32 (i odd) of
  *            SM(1 + 16 g + i/2); Weyl seed y0 = high32(SM(0)) shared by all
  *            instances; step counter 0
+ *   MWC_DIFF stream s uses multiplier a_s, the (s+1)-th largest a < 2^32
+ *            for which a*2^32 - 1 and (a*2^32 - 2)/2 are both prime (the MWC
+ *            section's downward search from 4294967118; a_0 = 4294967118);
+ *            x = low32(SM(1+s)), carry = high32(SM(1+s)) mod (a_s - 1),
+ *            x = 1 if both 0.  At most 2^21 streams (every a_s > 2^31).
  *   LCG32_SUB / LCG64_SUB: one global sequence g_0 = the LCG32 / LCG64
  *            stream-0 value above, g_{n+1} = a g_n + c; stream s starts at
  *            g_s and steps S positions with the S-step map (A_S, C_S), so
@@ -62,6 +67,9 @@
  *   PHILOX   u32 k0[S] k1[S] u64 pos[S]  (pos = outputs consumed)
  *   XS1024W  u32 W[S] (W[32g+i] = word i of instance g, word 0 most
  *            significant) u64 n[S/32] (steps taken) u32 y0
+ *   MWC_DIFF u64 y[S] (as MWC), then u32 a[S] (the multipliers; an image
+ *            whose multipliers differ from the handle's is refused with
+ *            RNGX_E_STATE)
  *   LCG32_SUB u32 x[S], u32 A_S, u32 C_S   LCG64_SUB u64 x[S], u64 A_S, C_S
  *            (rng_set_state refuses an image whose (A_S, C_S) is not the
  *            handle's, with RNGX_E_STATE)
@@ -85,7 +93,8 @@ typedef enum {
     RNGX_XS1024W = 6,       /* the paper's XORShift-1024 (329,347,344) + Weyl (XORShift section)    */
     RNGX_PHILOX4X32_7 = 7,  /* Philox4x32 with 7 rounds (counter-based section); otherwise as 5     */
     RNGX_LCG32_SUB = 8,     /* LCG32 sub-streams of one sequence (eq. lcg_skipping, t = S), below   */
-    RNGX_LCG64_SUB = 9      /* LCG64 sub-streams of one sequence, as 8                              */
+    RNGX_LCG64_SUB = 9,     /* LCG64 sub-streams of one sequence, as 8                              */
+    RNGX_MWC_DIFF = 12      /* MWC as 3 with a different safe-prime multiplier per stream (MWC sec.) */
 } rngx_kind;
 
 typedef enum {
@@ -133,7 +142,9 @@ typedef struct {
  * current device.  Seeding runs on the device; the call returns when it is
  * done.  *out receives the handle.  Errors: RNGX_E_INVALID (kind, S = 0,
  * out NULL), RNGX_E_ALIGN (XS1024W with S % 32 != 0), RNGX_E_OVERFLOW
- * (S > 2^36), RNGX_E_NOMEM.  (No XS1024W instance can be seeded all-zero:
+ * (S > 2^36; MWC_DIFF: S > 2^21), RNGX_E_NOMEM.  MWC_DIFF's multipliers are
+ * found on the device (a Rabin-Miller test of every candidate) once per
+ * process and kept for later handles.  (No XS1024W instance can be seeded all-zero:
  * at most one of its 16 distinct splitmix64 words is 0.) */
 rngx_status rng_create(rngx_kind kind, uint64_t n_streams, uint64_t seed, rngx_gen *out);
 
@@ -170,7 +181,8 @@ rngx_status rng_consume(rngx_gen g, uint32_t *d_xor, uint64_t count_per_stream, 
 
 /* Advance every stream by n outputs without producing them (jump-ahead):
  * LCGs by the n-step affine map (eq. lcg_skipping), MWC by y <- a^n y mod
- * (a 2^32 - 1), XORWOW and XS1024W by the n-th power of the GF(2)
+ * (a 2^32 - 1) (MWC_DIFF: each stream with its own a and modulus), XORWOW
+ * and XS1024W by the n-th power of the GF(2)
  * transition matrix of their xorshift part (the XORShift section's
  * sub-stream seeding multiplies by such a power) plus n steps of the Weyl
  * term, Philox by its counter.  The result equals producing and discarding

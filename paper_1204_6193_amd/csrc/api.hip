@@ -97,6 +97,8 @@ rngx_status alloc_gen(rngx_kind kind, uint64_t S, Gen **out) {
     if (S > kMaxStreams) return fail(RNGX_E_OVERFLOW, "n_streams exceeds 2^36");
     if (kind == RNGX_XS1024W && S % 32 != 0)
         return fail(RNGX_E_ALIGN, "XS1024W needs n_streams % 32 == 0 (32 lanes per 1024-bit instance)");
+    if (kind == RNGX_MWC_DIFF && S > kMwcDiffMaxStreams)
+        return fail(RNGX_E_OVERFLOW, "MWC_DIFF allows at most 2^21 streams (multipliers above 2^31)");
     Gen *g = new Gen{};
     g->magic = kGenMagic;
     g->kind = kind;
@@ -154,6 +156,14 @@ rngx_status validate_image(rngx_kind kind, uint64_t S, const uint8_t *img) {
         for (uint64_t s = 0; s < S; ++s)
             if (y[s] == 0 || y[s] >= kMwcP)
                 return fail(RNGX_E_STATE, "MWC stream " + std::to_string(s) + " is a fixed point (y = 0 or y >= p)");
+    } else if (kind == RNGX_MWC_DIFF) {
+        const uint64_t *y = reinterpret_cast<const uint64_t *>(img);
+        const uint32_t *a = reinterpret_cast<const uint32_t *>(img + 8 * S);
+        if (!mwc_diff_multipliers_match(a, S))
+            return fail(RNGX_E_STATE, "the image's multipliers are not this handle's (MWC_DIFF)");
+        for (uint64_t s = 0; s < S; ++s)
+            if (y[s] == 0 || y[s] >= (static_cast<uint64_t>(a[s]) << 32) - 1)
+                return fail(RNGX_E_STATE, "MWC_DIFF stream " + std::to_string(s) + " is a fixed point (y = 0 or y >= p)");
     }
     return RNGX_OK;
 }
@@ -187,11 +197,12 @@ size_t state_bytes(rngx_kind kind, uint64_t S) {
     case RNGX_LCG32_SUB: return 4 * S + 8;
     case RNGX_LCG64_SUB: return 8 * S + 16;
     case RNGX_XS1024W: return 4 * S + 8 * (S / 32) + 4;
+    case RNGX_MWC_DIFF: return 12 * S;
     }
     return 0;
 }
 
-bool kind_valid(int kind) { return kind >= RNGX_LCG32 && kind <= RNGX_LCG64_SUB; }
+bool kind_valid(int kind) { return (kind >= RNGX_LCG32 && kind <= RNGX_LCG64_SUB) || kind == RNGX_MWC_DIFF; }
 
 rngx_status fail(rngx_status st, const std::string &msg) { g_error = msg; return st; }
 rngx_status hip_fail(hipError_t e, const char *what) {
@@ -907,8 +918,8 @@ rngx_status srv_submit_fill(rngx_server h, uint32_t client, rngx_kind kind, uint
     Server *s;
     if (rngx_status st = check_server(h, &s)) return st;
     if (!ticket) return fail(RNGX_E_INVALID, "ticket is NULL");
-    if (!kind_valid(kind) || is_sub_lcg(kind))
-        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG kinds are not served)");
+    if (!kind_valid(kind) || is_sub_lcg(kind) || kind == RNGX_MWC_DIFF)
+        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG and MWC_DIFF kinds are not served)");
     if (count == 0) return fail(RNGX_E_INVALID, "count must be positive");
     if (count > kMaxServedValues) return fail(RNGX_E_OVERFLOW, "count exceeds 2^28");
     if (rngx_status st = server_submit_fill(s, client, kind, count, as_f32, ticket)) return st;
@@ -921,8 +932,8 @@ rngx_status srv_submit_ising(rngx_server h, uint32_t client, rngx_kind kind, uin
     Server *s;
     if (rngx_status st = check_server(h, &s)) return st;
     if (!ticket) return fail(RNGX_E_INVALID, "ticket is NULL");
-    if (!kind_valid(kind) || is_sub_lcg(kind))
-        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG kinds are not served)");
+    if (!kind_valid(kind) || is_sub_lcg(kind) || kind == RNGX_MWC_DIFF)
+        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG and MWC_DIFF kinds are not served)");
     if (L < 16 || L % 16) return fail(RNGX_E_ALIGN, "L must be a multiple of 16 and at least 16");
     if (L > kMaxL) return fail(RNGX_E_OVERFLOW, "L must not exceed 16384");
     if (!std::isfinite(beta) || beta < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");

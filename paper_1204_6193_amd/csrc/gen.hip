@@ -51,6 +51,14 @@ __global__ __launch_bounds__(kBlock) void k_seed_small(rngx_kind kind, uint8_t *
         u64[s] = (c << 32) | x;
         break;
     }
+    case RNGX_MWC_DIFF: {  // the multipliers are already in place after the states
+        const uint64_t a = reinterpret_cast<const uint32_t *>(st + 8 * S)[s];
+        const uint64_t z = splitmix(seed, 1 + s);
+        uint64_t x = z & 0xFFFFFFFFull, c = (z >> 32) % (a - 1);
+        if (x == 0 && c == 0) x = 1;
+        u64[s] = (c << 32) | x;
+        break;
+    }
     case RNGX_XORWOW: {
         const uint64_t p = splitmix(seed, 1 + 3 * s), q = splitmix(seed, 2 + 3 * s), r = splitmix(seed, 3 + 3 * s);
         uint32_t w[6] = {static_cast<uint32_t>(p), static_cast<uint32_t>(p >> 32), static_cast<uint32_t>(q),
@@ -330,6 +338,7 @@ const void *config_kernel(rngx_kind kind, int mode, const rngx_fill_config &c) {
     case RNGX_LCG32: return config_kernel<Lcg32>(mode, c);
     case RNGX_LCG64: return config_kernel<Lcg64>(mode, c);
     case RNGX_MWC: return config_kernel<Mwc>(mode, c);
+    case RNGX_MWC_DIFF: return config_kernel<MwcDiff>(mode, c);
     case RNGX_XORWOW: return config_kernel<Xorwow>(mode, c);
     case RNGX_PHILOX4X32_10: return config_kernel<Philox>(mode, c);
     case RNGX_PHILOX4X32_7: return config_kernel<Philox7>(mode, c);
@@ -415,6 +424,7 @@ hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
     case RNGX_LCG32: return fill_small<Lcg32, MODE>(g, out, count, st);
     case RNGX_LCG64: return fill_small<Lcg64, MODE>(g, out, count, st);
     case RNGX_MWC: return fill_small<Mwc, MODE>(g, out, count, st);
+    case RNGX_MWC_DIFF: return fill_small<MwcDiff, MODE>(g, out, count, st);
     case RNGX_XORWOW: return fill_small<Xorwow, MODE>(g, out, count, st);
     case RNGX_PHILOX4X32_10: return fill_small<Philox, MODE>(g, out, count, st);
     case RNGX_PHILOX4X32_7: return fill_small<Philox7, MODE>(g, out, count, st);
@@ -433,6 +443,10 @@ hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st) {
         const unsigned blocks = static_cast<unsigned>((pairs + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_seed_xs, dim3(blocks), dim3(kBlock), 0, st, g->d_state, g->S, seed);
     } else {
+        if (g->kind == RNGX_MWC_DIFF) {
+            const hipError_t e = mwc_diff_multipliers(g->S, reinterpret_cast<uint32_t *>(g->d_state + 8 * g->S), st);
+            if (e != hipSuccess) return e;
+        }
         const unsigned blocks = static_cast<unsigned>((g->S + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_seed_small, dim3(blocks), dim3(kBlock), 0, st, g->kind, g->d_state, g->S, seed);
     }

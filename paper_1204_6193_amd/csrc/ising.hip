@@ -1072,6 +1072,7 @@ const void *batch_kernel_for(rngx_kind kind) {
     case RNGX_LCG64: return batch_kernel<SmallUnit<Lcg64>>();
     case RNGX_LCG64_SUB: return batch_kernel<SmallUnit<Lcg64Sub>>();
     case RNGX_MWC: return batch_kernel<SmallUnit<Mwc>>();
+    case RNGX_MWC_DIFF: return batch_kernel<SmallUnit<MwcDiff>>();
     case RNGX_XORWOW: return batch_kernel<SmallUnit<Xorwow>>();
     case RNGX_PHILOX4X32_10: return batch_kernel<PhiloxUnit>();
     case RNGX_PHILOX4X32_7: return batch_kernel<PhiloxUnit7>();
@@ -1222,6 +1223,7 @@ int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int ma
     case RNGX_LCG64: return list_plans<SmallUnit<Lcg64>>(L, 16, n_cu, out, max);
     case RNGX_LCG64_SUB: return list_plans<SmallUnit<Lcg64Sub>>(L, 16, n_cu, out, max);
     case RNGX_MWC: return list_plans<SmallUnit<Mwc>>(L, 16, n_cu, out, max);
+    case RNGX_MWC_DIFF: return list_plans<SmallUnit<MwcDiff>>(L, 16, n_cu, out, max);
     case RNGX_XORWOW: return list_plans<SmallUnit<Xorwow>>(L, 16, n_cu, out, max);
     case RNGX_PHILOX4X32_10: return list_plans<PhiloxUnit>(L, 16, n_cu, out, max);
     case RNGX_PHILOX4X32_7: return list_plans<PhiloxUnit7>(L, 16, n_cu, out, max);
@@ -1237,6 +1239,7 @@ bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
     case RNGX_LCG64: return plan_strips<SmallUnit<Lcg64>>(L, 16, n_cu, out);
     case RNGX_LCG64_SUB: return plan_strips<SmallUnit<Lcg64Sub>>(L, 16, n_cu, out);
     case RNGX_MWC: return plan_strips<SmallUnit<Mwc>>(L, 16, n_cu, out);
+    case RNGX_MWC_DIFF: return plan_strips<SmallUnit<MwcDiff>>(L, 16, n_cu, out);
     case RNGX_XORWOW: return plan_strips<SmallUnit<Xorwow>>(L, 16, n_cu, out);
     case RNGX_PHILOX4X32_10: return plan_strips<PhiloxUnit>(L, 16, n_cu, out);
     case RNGX_PHILOX4X32_7: return plan_strips<PhiloxUnit7>(L, 16, n_cu, out);
@@ -1271,6 +1274,7 @@ hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_t
     case RNGX_LCG64: return run<SmallUnit<Lcg64>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_LCG64_SUB: return run<SmallUnit<Lcg64Sub>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_MWC: return run<SmallUnit<Mwc>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_MWC_DIFF: return run<SmallUnit<MwcDiff>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_XORWOW: return run<SmallUnit<Xorwow>>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_PHILOX4X32_10: return run<PhiloxUnit>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_PHILOX4X32_7: return run<PhiloxUnit7>(lat, T4, T8, n_sweeps, d_trace, st, hits);

@@ -298,7 +298,9 @@ void jump_table(rngx_kind kind, uint64_t step, uint64_t count, std::vector<uint6
     case RNGX_XORWOW: poly_table<160>(xorwow_minpoly(), step, count, u32s); break;
     case RNGX_XS1024W: poly_table<1024>(xs1024_minpoly(), step, count, u32s); break;
     case RNGX_PHILOX4X32_7:
-    case RNGX_PHILOX4X32_10: break;
+    case RNGX_PHILOX4X32_10:
+    case RNGX_MWC_DIFF: break;  // counter; per-stream powers computed on the device
+    default: break;
     }
 }
 
@@ -346,6 +348,7 @@ hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st) {
                            reinterpret_cast<uint64_t *>(g->d_state), S, f.a, f.c);
         break;
     }
+    case RNGX_MWC_DIFF: return launch_skip_mwc_diff(g, n, st);
     case RNGX_MWC:
         hipLaunchKernelGGL(k_skip_mwc, dim3(blocks_for(S)), dim3(kBlock), 0, st,
                            reinterpret_cast<uint64_t *>(g->d_state), S, host_powmod_p(kMwcA, n));

@@ -215,6 +215,13 @@ __global__ __launch_bounds__(kBlock) void k_ragged_start_small(rngx_kind kind, c
         reinterpret_cast<uint64_t *>(scratch)[i] = mwc_mulmod(y, t64[j]);
         break;
     }
+    case RNGX_MWC_DIFF: {  // the stream's own a^(jC) mod p, then its multiplier
+        const uint64_t y = reinterpret_cast<const uint64_t *>(st)[s];
+        const uint32_t a = reinterpret_cast<const uint32_t *>(st + 8 * S)[s];
+        reinterpret_cast<uint64_t *>(scratch)[i] = j ? mwc_jump_mod(y, a, j * chunk) : y;
+        reinterpret_cast<uint32_t *>(scratch + 8 * n_items)[i] = a;
+        break;
+    }
     case RNGX_XORWOW: {
         const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
         uint32_t v[5];
@@ -584,6 +591,7 @@ hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st) {
     case RNGX_LCG32: hipLaunchKernelGGL(k_ragged_gen_small<Lcg32>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_LCG64: hipLaunchKernelGGL(k_ragged_gen_small<Lcg64>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_MWC: hipLaunchKernelGGL(k_ragged_gen_small<Mwc>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
+    case RNGX_MWC_DIFF: hipLaunchKernelGGL(k_ragged_gen_small<MwcDiff>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_XORWOW: hipLaunchKernelGGL(k_ragged_gen_small<Xorwow>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ragged_gen_small<Philox>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;
     case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_ragged_gen_small<Philox7>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, r->d_scratch, g->d_state, g->S, d_out); break;

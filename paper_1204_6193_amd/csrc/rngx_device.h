@@ -103,6 +103,73 @@ struct Mwc {
     }
 };
 
+// Arithmetic modulo an odd n < 2^64 by Montgomery multiplication with
+// R = 2^64: values are kept as x R mod n, and mul(a, b) = a b / R mod n for
+// a, b < n.  Used where the modulus differs per stream (MWC_DIFF) and by the
+// primality test of the multiplier search.
+__device__ __forceinline__ uint64_t mul_hi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+struct Mont64 {
+    uint64_t n, ninv, one;  // ninv = -n^-1 mod 2^64; one = R mod n (the form of 1)
+    __device__ explicit Mont64(uint64_t n_) : n(n_) {
+        uint64_t x = n;                               // n^-1 mod 2^3 (n odd)
+        for (int i = 0; i < 5; ++i) x *= 2 - n * x;  // Newton: 6, 12, 24, 48, 96 bits
+        ninv = 0 - x;
+        one = (0 - n) % n;                            // 2^64 mod n
+    }
+    // a b / R mod n (REDC of the 128-bit product)
+    __device__ uint64_t mul(uint64_t a, uint64_t b) const {
+        const uint64_t lo = a * b, hi = mul_hi64(a, b);
+        const uint64_t m = lo * ninv;
+        const uint64_t mlo = m * n, mhi = mul_hi64(m, n);
+        const uint64_t c = (lo + mlo) < lo ? 1 : 0;  // the low word sums to 0 mod 2^64
+        const uint64_t t1 = hi + mhi, t2 = t1 + c;
+        const bool over = (t1 < hi) || (t2 < t1);     // the sum reached 2^64
+        return (over || t2 >= n) ? t2 - n : t2;
+    }
+    __device__ uint64_t add(uint64_t a, uint64_t b) const {  // a + b mod n, a, b < n
+        const uint64_t t = a + b;
+        return (t < a || t >= n) ? t - n : t;
+    }
+    // Montgomery form of x < n: x R mod n, as x doubled 64 times modulo n
+    __device__ uint64_t to(uint64_t x) const {
+        for (int i = 0; i < 64; ++i) x = add(x, x);
+        return x;
+    }
+    __device__ uint64_t from(uint64_t x) const { return mul(x, 1); }
+    // b^e in Montgomery form, b in Montgomery form
+    __device__ uint64_t pow(uint64_t b, uint64_t e) const {
+        uint64_t r = one;
+        for (; e; e >>= 1) {
+            if (e & 1) r = mul(r, b);
+            b = mul(b, b);
+        }
+        return r;
+    }
+};
+
+// MWC with a multiplier a of its own per stream (image: u64 y[S], u32 a[S]).
+struct MwcDiff {
+    uint64_t y;  // carry << 32 | x
+    uint32_t a;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t s) {
+        y = reinterpret_cast<const uint64_t *>(st)[s];
+        a = reinterpret_cast<const uint32_t *>(st + 8 * S)[s];
+    }
+    __device__ void store(uint8_t *st, uint64_t, uint64_t s) const { reinterpret_cast<uint64_t *>(st)[s] = y; }
+    __device__ uint32_t next() {
+        y = static_cast<uint64_t>(a) * static_cast<uint32_t>(y) + (y >> 32);
+        return static_cast<uint32_t>(y);
+    }
+};
+
+// y <- a^n y mod p with p = a 2^32 - 1: n steps of the MWC as the
+// multiplicative congruential map it is (y = carry 2^32 + x, y' = a y mod p).
+__device__ inline uint64_t mwc_jump_mod(uint64_t y, uint32_t a, uint64_t n) {
+    const Mont64 M((static_cast<uint64_t>(a) << 32) - 1);
+    const uint64_t an = M.pow(M.to(a), n);
+    return M.from(M.mul(an, M.to(y)));
+}
+
 struct Xorwow {
     uint32_t x, y, z, w, v, d;
     __device__ void load(const uint8_t *st, uint64_t S, uint64_t s) {

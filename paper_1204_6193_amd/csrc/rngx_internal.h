@@ -130,6 +130,13 @@ int fill_default(rngx_kind kind);
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st);
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
 hipError_t launch_substreams(Gen *g, hipStream_t st);  // XS1024W: instance g skips g 2^137 steps (synchronous)
+// MWC_DIFF: the first n multipliers (found on the device once per process)
+// copied to device memory d_dst (may be NULL to only extend the list);
+// synchronous on st.
+hipError_t mwc_diff_multipliers(uint64_t n, uint32_t *d_dst, hipStream_t st);
+bool mwc_diff_multipliers_match(const uint32_t *a, uint64_t n);  // a[0..n) = the first n multipliers
+hipError_t launch_skip_mwc_diff(Gen *g, uint64_t n, hipStream_t st);
+constexpr uint64_t kMwcDiffMaxStreams = 1ull << 21;
 
 // Host-side jump tables for j = 0 .. count-1 steps of size `step`:
 //  LCG32/LCG64: (A, C) pairs of the affine map f^(j step), 2 u64 each;
