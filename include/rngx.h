@@ -352,9 +352,10 @@ rngx_status ising_batch_create(const rngx_ising *lats, uint32_t n, const double 
 rngx_status ising_batch_run(rngx_ising_batch b, void *stream);
 rngx_status ising_batch_status(rngx_ising_batch b, uint32_t *n_invalid, void *stream);
 /* The launch shape of a run: work items (one per single-workgroup replica,
- * one per strip of a gang) and workgroups of the persistent grid.  Either
- * pointer may be NULL. */
-rngx_status ising_batch_info(rngx_ising_batch b, uint32_t *n_items, uint32_t *grid);
+ * one per strip of a gang), workgroups that fit on the device at once, and
+ * workgroups of the persistent grid (the smaller of the two).  Any pointer
+ * may be NULL. */
+rngx_status ising_batch_info(rngx_ising_batch b, uint32_t *n_items, uint32_t *resident, uint32_t *grid);
 rngx_status ising_batch_destroy(rngx_ising_batch b);
 
 /* Served form.  A server admits requests in arrival order as soon as its

@@ -62,7 +62,8 @@ SIGNATURES = {
                                   ctypes.POINTER(_u64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "ising_batch_run": (_i32, [_vp, _vp]),
     "ising_batch_status": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), _vp]),
-    "ising_batch_info": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
+    "ising_batch_info": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                ctypes.POINTER(ctypes.c_uint32)]),
     "ising_batch_destroy": (_i32, [_vp]),
     "srv_create": (_i32, [ctypes.c_void_p, ctypes.POINTER(_vp)]),
     "srv_submit_fill": (_i32, [_vp, ctypes.c_uint32, _i32, _u64, _i32, ctypes.POINTER(_u64)]),
@@ -487,10 +488,11 @@ def ising_batch_status(batch: IsingBatch, stream=None) -> int:
 
 
 def ising_batch_info(batch: IsingBatch) -> dict:
-    """{"items": work items, "grid": workgroups of the persistent launch}."""
-    n, g = ctypes.c_uint32(), ctypes.c_uint32()
-    _check(load().ising_batch_info(batch.handle, ctypes.byref(n), ctypes.byref(g)))
-    return {"items": n.value, "grid": g.value}
+    """{"items": work items, "resident": workgroups that fit at once,
+    "grid": workgroups of the persistent launch}."""
+    n, r, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().ising_batch_info(batch.handle, ctypes.byref(n), ctypes.byref(r), ctypes.byref(g)))
+    return {"items": n.value, "resident": r.value, "grid": g.value}
 
 
 def ising_batch_destroy(batch: IsingBatch):

@@ -861,10 +861,11 @@ rngx_status ising_batch_status(rngx_ising_batch h, uint32_t *n_invalid, void *st
     return RNGX_OK;
 }
 
-rngx_status ising_batch_info(rngx_ising_batch h, uint32_t *n_items, uint32_t *grid) {
+rngx_status ising_batch_info(rngx_ising_batch h, uint32_t *n_items, uint32_t *resident, uint32_t *grid) {
     IsingBatch *b;
     if (rngx_status s = check_batch(h, &b)) return s;
     if (n_items) *n_items = b->n_items;
+    if (resident) *resident = b->resident;
     if (grid) *grid = b->grid;
     clear_error();
     return RNGX_OK;

@@ -1158,6 +1158,7 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
     const uint64_t start_ticks = static_cast<uint64_t>(kGangStartSeconds * 1e3 * std::max(clock_khz, 1));
     b->lds = lds;
     b->n_items = static_cast<uint32_t>(items.size());
+    b->resident = resident;
     b->grid = std::min<uint32_t>(b->n_items, resident);
     if (halo_bytes) {
         if ((e = hipMalloc(&b->d_halo, halo_bytes)) != hipSuccess) return e;

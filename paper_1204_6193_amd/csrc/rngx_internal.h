@@ -100,6 +100,7 @@ struct IsingBatch {
     uint32_t *d_next;    // work counter
     void *d_halo;        // tagged halo words of the gang replicas
     uint32_t lds, grid;  // launch shape
+    uint32_t resident;   // workgroups of the batch kernel that fit at once
     Ising **lats;        // host copy of the members
 };
 

@@ -309,10 +309,10 @@ def test_batch_gang_behind_long_replicas(rngx, orc):
     oracle and every replica must be valid."""
     kind = "xs1024w"
     probe = rngx.ising_batch_create([rngx.ising_create(64, kind, 1)], [0.4], [1])
-    grid = rngx.ising_batch_info(probe)["grid"]
+    grid = rngx.ising_batch_info(probe)["resident"]
     probe.destroy()
     gang_L, gang_sweeps = 1024, 3
-    n_long = max(grid, 2) - 2  # leaves one workgroup for the gang's first strip
+    n_long = max(grid, 2) - 2  # leaves two workgroups for the gang's first strips
     Ls = [64] * n_long + [gang_L]
     betas = [0.4] * n_long + [0.44]
     sweeps = [400_000] * n_long + [gang_sweeps]
