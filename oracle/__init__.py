@@ -82,6 +82,10 @@ def lib():
         L.orc_is_prime_u64.argtypes = [u64]
         L.orc_mwc_multipliers.restype = i32
         L.orc_mwc_multipliers.argtypes = [u64, vp]
+        L.orc_mwc_candidates.restype = i32
+        L.orc_mwc_candidates.argtypes = [ctypes.c_uint32, u64, vp]
+        L.orc_seed_mwcd.restype = i32
+        L.orc_seed_mwcd.argtypes = [u64, u64, vp, vp]
         L.orc_philox4x32_block.restype = None
         L.orc_philox4x32_block.argtypes = [vp, vp, i32, vp]
         L.orc_ising_sweeps_hits.restype = i32
@@ -118,8 +122,14 @@ def state_bytes(kind: str, S: int) -> int:
 
 
 def seed(kind: str, S: int, seed_: int) -> np.ndarray:
-    """Canonical state image (uint8) of S freshly seeded streams."""
+    """Canonical state image (uint8) of S freshly seeded streams.
+    mwc_diff with many streams takes its multipliers from the threaded
+    enumeration below (the sequential search would take minutes)."""
     st = np.zeros(state_bytes(kind, S), dtype=np.uint8)
+    if kind == "mwc_diff" and S > 8192:
+        a = mwc_multipliers(S, threads=os.cpu_count() or 1)
+        _check(lib().orc_seed_mwcd(S, seed_, _ptr(a), _ptr(st)), "seed")
+        return st
     _check(lib().orc_seed(_CODE[kind], S, seed_, _ptr(st)), "seed")
     return st
 
@@ -155,11 +165,37 @@ def is_prime_u64(n: int) -> bool:
     return bool(lib().orc_is_prime_u64(n))
 
 
-def mwc_multipliers(n: int) -> np.ndarray:
-    """The n largest a < 2^32 with a*2^32 - 1 a safe prime, decreasing."""
-    out = np.zeros(n, dtype=np.uint32)
-    _check(lib().orc_mwc_multipliers(n, _ptr(out)), "mwc multipliers")
-    return out
+_MULT_CACHE = np.zeros(0, dtype=np.uint32)
+_MULT_BLOCK = 1 << 22  # candidates per enumeration block
+
+
+def mwc_multipliers(n: int, threads: int = 1) -> np.ndarray:
+    """The n largest a < 2^32 with a*2^32 - 1 a safe prime, decreasing.
+    threads = 1: the oracle's downward search.  threads > 1: the same test
+    applied to blocks of consecutive candidates (from 2^32 - 1 down) on that
+    many threads, the qualifying ones concatenated block by block in
+    decreasing order; kept for later calls of the process."""
+    global _MULT_CACHE
+    if threads <= 1:
+        out = np.zeros(n, dtype=np.uint32)
+        _check(lib().orc_mwc_multipliers(n, _ptr(out)), "mwc multipliers")
+        return out
+    if _MULT_CACHE.size < n:
+        from concurrent.futures import ThreadPoolExecutor
+
+        def block(top):
+            flags = np.zeros(_MULT_BLOCK, dtype=np.uint8)
+            _check(lib().orc_mwc_candidates(top, _MULT_BLOCK, _ptr(flags)), "mwc candidates")
+            return top - np.nonzero(flags)[0].astype(np.int64)
+
+        found, top = [], (1 << 32) - 1
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            while sum(len(f) for f in found) < n:
+                tops = [top - i * _MULT_BLOCK for i in range(threads)]
+                found.extend(ex.map(block, tops))
+                top -= threads * _MULT_BLOCK
+        _MULT_CACHE = np.concatenate(found).astype(np.uint32)
+    return _MULT_CACHE[:n].copy()
 
 
 def step_n(kind: str, S: int, st: np.ndarray, n: int, lo: int = 0, hi: int | None = None):

@@ -373,6 +373,41 @@ int orc_mwc_multipliers(uint64_t n, uint32_t *out)
     return 0;
 }
 
+/* flags[i] = 1 iff a = top - i (i < count, a > 1) qualifies: the same test
+ * as above, one candidate at a time (orc_mwc_multipliers takes the
+ * qualifying candidates in exactly this order). */
+int orc_mwc_candidates(uint32_t top, uint64_t count, uint8_t *flags)
+{
+    if (count > top) return -1;
+    for (uint64_t i = 0; i < count; i++) {
+        uint64_t a = (uint64_t)top - i, p = (a << 32) - 1;
+        flags[i] = (uint8_t)(a > 1 && orc_is_prime_u64((p - 1) / 2) && orc_is_prime_u64(p));
+    }
+    return 0;
+}
+
+/* MWC_DIFF states from a given multiplier list a[0..S): as MWC, with the
+ * carry reduced mod (a_s - 1). */
+static void seed_mwcd_from(uint64_t S, uint64_t seed, const uint32_t *a, uint8_t *b)
+{
+    uint64_t *y = (uint64_t *)b;
+    uint32_t *ad = (uint32_t *)(b + 8 * S);
+    for (uint64_t s = 0; s < S; s++) {
+        uint64_t z = orc_splitmix(seed, 1 + s);
+        uint64_t x = z & 0xFFFFFFFFull, c = (z >> 32) % ((uint64_t)a[s] - 1);
+        if (x == 0 && c == 0) x = 1;
+        y[s] = (c << 32) | x;
+        ad[s] = a[s];
+    }
+}
+
+int orc_seed_mwcd(uint64_t S, uint64_t seed, const uint32_t *a, void *st)
+{
+    if (!kind_ok(ORC_MWCD, S)) return -1;
+    seed_mwcd_from(S, seed, a, (uint8_t *)st);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Seeding: every stream's initial state derives from SM(.) of the master
  * seed by fixed indices (project definition). */
@@ -425,15 +460,9 @@ int orc_seed(int kind, uint64_t S, uint64_t seed, void *st)
             k0[s] = (uint32_t)z; k1[s] = (uint32_t)(z >> 32); pos[s] = 0;
         }
     } else if (kind == ORC_MWCD) {
-        uint64_t *y = (uint64_t *)b;
         uint32_t *a = (uint32_t *)(b + 8 * S);
         if (orc_mwc_multipliers(S, a)) return -3;
-        for (uint64_t s = 0; s < S; s++) {
-            uint64_t z = orc_splitmix(seed, 1 + s);
-            uint64_t x = z & 0xFFFFFFFFull, c = (z >> 32) % ((uint64_t)a[s] - 1);
-            if (x == 0 && c == 0) x = 1;
-            y[s] = (c << 32) | x;
-        }
+        seed_mwcd_from(S, seed, a, b);
     } else if (IS_LFG(kind)) {
         const uint64_t r = LFG_R(kind), H = (r + 1) / 2;
         uint32_t *X = (uint32_t *)b;

@@ -1159,6 +1159,7 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
     b->lds = lds;
     b->n_items = static_cast<uint32_t>(items.size());
     b->resident = resident;
+    b->gangs = halo_bytes != 0;
     b->grid = std::min<uint32_t>(b->n_items, resident);
     if (halo_bytes) {
         if ((e = hipMalloc(&b->d_halo, halo_bytes)) != hipSuccess) return e;
@@ -1188,14 +1189,16 @@ hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
     uint32_t n_items = b->n_items;
     uint32_t *next = b->d_next;
     void *args[] = {&reps, &items, &n_items, &next};
-    // Outside graph capture the launch is cooperative, which makes the whole
-    // grid resident together whatever else runs on the device; a captured
-    // launch relies on the grid fitting (it is sized to what is resident at
-    // once) and on the gang start wait.
+    // With gangs, and outside graph capture, the launch is cooperative, which
+    // makes the whole grid resident together whatever else runs on the
+    // device; a captured launch relies on the grid fitting (it is sized to
+    // what is resident at once) and on the gang start wait.  Without gangs no
+    // workgroup waits for another, and a plain launch can overlap with other
+    // work.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(st, &cap);
     if (e != hipSuccess) return e;
-    if (cap == hipStreamCaptureStatusNone)
+    if (b->gangs && cap == hipStreamCaptureStatusNone)
         return hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(kBatchThreads), args, b->lds, st);
     return hipLaunchKernel(fn, dim3(b->grid), dim3(kBatchThreads), args, b->lds, st);
 }

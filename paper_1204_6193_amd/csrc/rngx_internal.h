@@ -101,6 +101,7 @@ struct IsingBatch {
     void *d_halo;        // tagged halo words of the gang replicas
     uint32_t lds, grid;  // launch shape
     uint32_t resident;   // workgroups of the batch kernel that fit at once
+    bool gangs;          // some replica runs as a gang of strips
     Ising **lats;        // host copy of the members
 };
 

@@ -10,7 +10,8 @@ import torch
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7", "lcg32_sub", "lcg64_sub"]
+KINDS = ["lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "xs1024w", "philox4x32_7", "lcg32_sub", "lcg64_sub",
+         "mwc_diff"]
 
 
 def _sizes(kind):
@@ -114,6 +115,56 @@ def test_set_state_rejects_fixed_points(rngx, orc):
         rngx.rng_set_state(m, mb)
     with pytest.raises(rngx.RngxError):
         rngx.rng_set_state(m, mi[:-1])
+
+
+def test_mwc_diff_image_checks(rngx, orc):
+    """MWC_DIFF refuses an image whose multipliers are not the handle's, or
+    with a stream at a fixed point, and more than 2^21 streams."""
+    S = 16
+    g = rngx.rng_create("mwc_diff", S, 1)
+    img = rngx.rng_get_state(g)
+    other = img.copy()
+    other[8 * S: 8 * S + 4] = np.array([4294966893], dtype=np.uint32).view(np.uint8)  # stream 0 takes a_1
+    fixed = img.copy()
+    fixed[8:16] = 0  # stream 1: y = 0
+    for bad in (other, fixed):
+        with pytest.raises(rngx.RngxError) as e:
+            rngx.rng_set_state(g, bad)
+        assert e.value.status == -6
+    assert np.array_equal(rngx.rng_get_state(g), img)
+    with pytest.raises(rngx.RngxError) as e:
+        rngx.rng_create("mwc_diff", (1 << 21) + 1, 1)
+    assert e.value.status == -5
+
+
+def test_mwc_diff_multipliers_at_the_maximum(rngx, orc):
+    """The device search at the largest stream count, 2^21: the image's
+    multipliers equal the oracle's list (its first 8192 by the oracle's own
+    sequential search, all 2^21 and the 2^20 prefix by the digests of the
+    oracle's list in tests/golden); the streams seed from them as the
+    oracle does."""
+    import hashlib
+    import json
+    import os
+    S = 1 << 21
+    print("case mwc_diff multipliers 2^21", flush=True)
+    g = rngx.rng_create("mwc_diff", S, 1)
+    img = rngx.rng_get_state(g)
+    a = img[8 * S:].view(np.uint32)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "mwc_diff_multipliers.json")) as f:
+        gold = json.load(f)
+    for n in (1 << 20, 1 << 21):
+        assert hashlib.sha256(a[:n].astype("<u4").tobytes()).hexdigest() == gold[str(n)]["sha256"], n
+        assert int(a[n - 1]) == gold[str(n)]["last"]
+    assert np.array_equal(a[:8192], orc.mwc_multipliers(8192))
+    y = img[: 8 * S].view(np.uint64)
+    assert np.array_equal(img[: 8 * 4096], orc.seed("mwc_diff", 4096, 1)[: 8 * 4096])
+    # the last streams follow the seeding rule with their (digest-checked) multipliers
+    for s in range(S - 64, S):
+        z = orc.splitmix(1, 1 + s)
+        x, c = z & 0xFFFFFFFF, (z >> 32) % (int(a[s]) - 1)
+        assert int(y[s]) == (c << 32) | (x if (x or c) else 1), s
+    del img, a, y
 
 
 def test_count_zero_and_argument_errors(rngx):

@@ -88,3 +88,23 @@ def test_period_and_jump(orc, s):
     orc.jump("mwc_diff", S, c, 777)
     orc.step_n("mwc_diff", S, d, 777)
     assert np.array_equal(c, d)
+
+
+def test_threaded_enumeration_equals_the_downward_search(orc, monkeypatch):
+    """The per-candidate test over blocks on several threads gives the same
+    list as the sequential downward search (small blocks, so that the list
+    spans many blocks and threads)."""
+    monkeypatch.setattr(orc, "_MULT_CACHE", np.zeros(0, dtype=np.uint32))
+    monkeypatch.setattr(orc, "_MULT_BLOCK", 4096)
+    assert np.array_equal(orc.mwc_multipliers(3000, threads=4), orc.mwc_multipliers(3000))
+    flags = np.zeros(1000, dtype=np.uint8)
+    assert orc.lib().orc_mwc_candidates(4294967118, 1000, flags.ctypes.data) == 0
+    assert flags[0] == 1 and int(flags.sum()) == int(np.sum(orc.mwc_multipliers(40) > 4294967118 - 1000))
+
+
+def test_seeding_from_a_given_list(orc):
+    S = 300
+    a = orc.mwc_multipliers(S)
+    st = np.zeros(orc.state_bytes("mwc_diff", S), dtype=np.uint8)
+    assert orc.lib().orc_seed_mwcd(S, 5, a.ctypes.data, st.ctypes.data) == 0
+    assert np.array_equal(st, orc.seed("mwc_diff", S, 5))
