@@ -27,10 +27,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 S_FULL, COUNT_FULL = 1 << 20, 4096
-KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7"]
-# state bytes read + written once per launch, per stream
+KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7", "mwc_diff"]
+# kinds whose L = 4096 lattice fits their stream count (MWC_DIFF: at most 2^21 streams)
+ISING_KINDS = [k for k in KINDS if k != "mwc_diff"]
+# state bytes read + written once per launch, per stream (MWC_DIFF: y read and
+# written, the multiplier read only)
 STATE_BYTES = {"lcg32": 4, "lcg64": 8, "mwc": 8, "xorwow": 24, "philox4x32_10": 16, "philox4x32_7": 16,
-               "xs1024w": 4 + 8 / 32}
+               "xs1024w": 4 + 8 / 32, "mwc_diff": 10}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "xs1024w_fill_u32_2p20x4096_hbm_traffic.md")
 KERNEL_SOURCES = ["paper_1204_6193_amd/csrc/gen.hip", "paper_1204_6193_amd/csrc/rngx_device.h"]
 
@@ -227,7 +230,7 @@ def bench_serve(rx, n_req=20000, rate=2000.0, clients=64, slots=8, inflight=32, 
     import threading
     import numpy as np
     rng = np.random.default_rng(seed)
-    kinds = [k for k in rx.KINDS if not k.endswith("_sub")]  # sub-stream LCGs are not served
+    kinds = [k for k in rx.KINDS if not k.endswith("_sub") and k != "mwc_diff"]  # kinds the server takes
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     reqs = []
     for i in range(n_req):
@@ -363,6 +366,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--parts", default="all", help="all | none: per-kind parts and Ising")
     ap.add_argument("--ising-sweeps", type=int, default=10000)
+    ap.add_argument("--kinds", default=None, help="comma-separated kinds for the parts (default: all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
@@ -451,6 +455,8 @@ def main():
               flush=True)
         return
 
+    kinds = args.kinds.split(",") if args.kinds else KINDS
+    ising_kinds = [k for k in kinds if k in ISING_KINDS]
     head = bench_fill(rx, "xs1024w", "u32", out, args.steps, args.warmup)
     print(f"# headline xs1024w u32 fill: {head}", file=sys.stderr, flush=True)
     parts = {}
@@ -459,7 +465,7 @@ def main():
         ceiling = parts["write_ceiling"]["gbs"]
         head["ceiling_frac"] = round(head["gbs"] / ceiling, 4)
         print(f"# write ceiling {parts['write_ceiling']}", file=sys.stderr, flush=True)
-        for kind in KINDS:
+        for kind in kinds:
             rec = {}
             for mode in ("u32", "f32", "consume"):
                 rec[mode] = bench_fill(rx, kind, mode, out, max(5, args.steps // 2), 2)
@@ -471,7 +477,7 @@ def main():
         del out
         torch.cuda.empty_cache()
         ising = {}
-        for kind in KINDS:
+        for kind in ising_kinds:
             sweeps = args.ising_sweeps if kind == "xs1024w" else max(100, args.ising_sweeps // 10)
             ising[kind] = bench_ising(rx, kind, 4096, sweeps)
             print(f"# ising L=4096 {kind}: {ising[kind]}", file=sys.stderr, flush=True)
@@ -479,17 +485,17 @@ def main():
         beta_c = math.log(1 + math.sqrt(2)) / 2
         parts["ising_L4096_betac"] = {
             kind: bench_ising(rx, kind, 4096, args.ising_sweeps if kind == "xs1024w" else max(100, args.ising_sweeps // 10),
-                              beta_c) for kind in KINDS}
+                              beta_c) for kind in ising_kinds}
         print(f"# ising L=4096 xs1024w beta_c: {parts['ising_L4096_betac']}", file=sys.stderr, flush=True)
-        mh = {"k2": {k: bench_ising(rx, k, 4096, 200, hits=2) for k in KINDS},
-              "k100": {k: bench_ising(rx, k, 4096, 10, hits=100) for k in KINDS}}
+        mh = {"k2": {k: bench_ising(rx, k, 4096, 200, hits=2) for k in ising_kinds},
+              "k100": {k: bench_ising(rx, k, 4096, 10, hits=100) for k in ising_kinds}}
         parts["ising_L4096_multihit"] = mh
         print(f"# ising L=4096 multi-hit: " + json.dumps({h: {k: v["flips_per_ns"] for k, v in r.items()}
                                                          for h, r in mh.items()}), file=sys.stderr, flush=True)
         if not args.skip_batched:
             parts["ising_batch"] = bench_ising_batch(rx)
             print(f"# ising batch: {parts['ising_batch']}", file=sys.stderr, flush=True)
-            parts["ragged"] = [bench_ragged(rx, k) for k in KINDS]
+            parts["ragged"] = [bench_ragged(rx, k) for k in kinds]
             print(f"# ragged: {parts['ragged']}", file=sys.stderr, flush=True)
         if not args.skip_serve:
             parts["serve"] = {"continuous": bench_serve(rx), "fifo_one_at_a_time": bench_serve(rx, slots=1, inflight=1)}
