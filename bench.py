@@ -27,13 +27,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 S_FULL, COUNT_FULL = 1 << 20, 4096
-KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7", "mwc_diff"]
+KINDS = ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7", "mwc_diff", "lfg521",
+         "lfg1279"]
 # kinds whose L = 4096 lattice fits their stream count (MWC_DIFF: at most 2^21 streams)
 ISING_KINDS = [k for k in KINDS if k != "mwc_diff"]
+RAGGED_KINDS = [k for k in KINDS if not k.startswith("lfg")]  # ragged fills take no LFG kind
 # state bytes read + written once per launch, per stream (MWC_DIFF: y read and
-# written, the multiplier read only)
+# written, the multiplier read only; LFG: r words per 1024-stream instance)
 STATE_BYTES = {"lcg32": 4, "lcg64": 8, "mwc": 8, "xorwow": 24, "philox4x32_10": 16, "philox4x32_7": 16,
-               "xs1024w": 4 + 8 / 32, "mwc_diff": 10}
+               "xs1024w": 4 + 8 / 32, "mwc_diff": 10, "lfg521": 4 * 521 / 1024, "lfg1279": 4 * 1279 / 1024}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "xs1024w_fill_u32_2p20x4096_hbm_traffic.md")
 KERNEL_SOURCES = ["paper_1204_6193_amd/csrc/gen.hip", "paper_1204_6193_amd/csrc/rngx_device.h"]
 
@@ -495,7 +497,7 @@ def main():
         if not args.skip_batched:
             parts["ising_batch"] = bench_ising_batch(rx)
             print(f"# ising batch: {parts['ising_batch']}", file=sys.stderr, flush=True)
-            parts["ragged"] = [bench_ragged(rx, k) for k in kinds]
+            parts["ragged"] = [bench_ragged(rx, k) for k in kinds if k in RAGGED_KINDS]
             print(f"# ragged: {parts['ragged']}", file=sys.stderr, flush=True)
         if not args.skip_serve:
             parts["serve"] = {"continuous": bench_serve(rx), "fifo_one_at_a_time": bench_serve(rx, slots=1, inflight=1)}

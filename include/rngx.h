@@ -36,6 +36,13 @@
  *   - FP32 uniforms are f = (u >> 8) * 2^-24, exact, in [0, 1).
  *   - XS1024W: a stream is one 32-bit lane of a 1024-bit instance; stream s
  *     is lane s % 32 of instance s / 32, so S must be a multiple of 32.
+ *   - LFG521 / LFG1279: the values u_n = x_n / 2^32 follow the section's
+ *     u_n = u_{n-r} + u_{n-s} mod 1 exactly.  One sequence (instance) is
+ *     shared by 1024 streams, as by the threads of a block: stream s is lane
+ *     s % 1024 of instance s / 1024, and output k of lane i is the instance's
+ *     value 1024 k + i (warp order), so S must be a multiple of 1024.  Fills,
+ *     consume, skip, state images and Ising sweeps (L a multiple of 64) take
+ *     these kinds; ragged fills, batches and the server do not.
  *
  * Seeding (the paper seeds instances "with another RNG"; the exact indices
  * are this library's definition), with SM(k) = splitmix64 output k of
@@ -48,6 +55,10 @@
  *   XS1024W  word i of instance g = low32 (i even) / high32 (i odd) of
  *            SM(1 + 16 g + i/2); Weyl seed y0 = high32(SM(0)) shared by all
  *            instances; step counter 0
+ *   LFG521 / LFG1279 (lags (r, s) = (521, 353) / (1279, 861)): instance g
+ *            holds the last r values of its sequence; word j of instance g =
+ *            low32 (j even) / high32 (j odd) of SM(1 + H g + j/2), H = (r+1)/2,
+ *            and if all r words are even, word 0 gets its low bit set
  *   MWC_DIFF stream s uses multiplier a_s, the (s+1)-th largest a < 2^32
  *            for which a*2^32 - 1 and (a*2^32 - 2)/2 are both prime (the MWC
  *            section's downward search from 4294967118; a_0 = 4294967118);
@@ -67,6 +78,8 @@
  *   PHILOX   u32 k0[S] k1[S] u64 pos[S]  (pos = outputs consumed)
  *   XS1024W  u32 W[S] (W[32g+i] = word i of instance g, word 0 most
  *            significant) u64 n[S/32] (steps taken) u32 y0
+ *   LFG521 / LFG1279  u32 X[S/1024][r]: X[g][j] = x_{n-r+j} of instance g,
+ *            oldest first (an instance whose r words are all even is refused)
  *   MWC_DIFF u64 y[S] (as MWC), then u32 a[S] (the multipliers; an image
  *            whose multipliers differ from the handle's is refused with
  *            RNGX_E_STATE)
@@ -94,6 +107,9 @@ typedef enum {
     RNGX_PHILOX4X32_7 = 7,  /* Philox4x32 with 7 rounds (counter-based section); otherwise as 5     */
     RNGX_LCG32_SUB = 8,     /* LCG32 sub-streams of one sequence (eq. lcg_skipping, t = S), below   */
     RNGX_LCG64_SUB = 9,     /* LCG64 sub-streams of one sequence, as 8                              */
+    RNGX_LFG521 = 10,       /* additive lagged Fibonacci x_n = x_{n-521} + x_{n-353} mod 2^32, an   */
+                            /* instance shared by 1024 streams (Lagged Fibonacci section), below     */
+    RNGX_LFG1279 = 11,      /* as 10 with lags (1279, 861)                                          */
     RNGX_MWC_DIFF = 12      /* MWC as 3 with a different safe-prime multiplier per stream (MWC sec.) */
 } rngx_kind;
 
@@ -141,7 +157,7 @@ typedef struct {
 /* Create S = n_streams streams of `kind` seeded from `seed` as above, on the
  * current device.  Seeding runs on the device; the call returns when it is
  * done.  *out receives the handle.  Errors: RNGX_E_INVALID (kind, S = 0,
- * out NULL), RNGX_E_ALIGN (XS1024W with S % 32 != 0), RNGX_E_OVERFLOW
+ * out NULL), RNGX_E_ALIGN (XS1024W with S % 32 != 0, LFG with S % 1024 != 0), RNGX_E_OVERFLOW
  * (S > 2^36; MWC_DIFF: S > 2^21), RNGX_E_NOMEM.  MWC_DIFF's multipliers are
  * found on the device (a Rabin-Miller test of every candidate) once per
  * process and kept for later handles.  (No XS1024W instance can be seeded all-zero:
@@ -185,7 +201,9 @@ rngx_status rng_consume(rngx_gen g, uint32_t *d_xor, uint64_t count_per_stream, 
  * and XS1024W by the n-th power of the GF(2)
  * transition matrix of their xorshift part (the XORShift section's
  * sub-stream seeding multiplies by such a power) plus n steps of the Weyl
- * term, Philox by its counter.  The result equals producing and discarding
+ * term, Philox by its counter, LFG instances (1024 n values each) by
+ * J(x) = x^(1024 n) mod (x^r - x^(r-s) - 1) over Z/2^32 applied to the
+ * window.  The result equals producing and discarding
  * n outputs. */
 rngx_status rng_skip(rngx_gen g, uint64_t n, void *stream);
 
@@ -267,7 +285,12 @@ rngx_status rng_set_state(rngx_gen g, const void *host_buf, size_t bytes, void *
  * of splitmix64 output i+1 of (seed ^ 0xD1B54A32D192ED03) is set.  It owns
  * S = L*L/4 streams of `kind` seeded from `seed` as rng_create would; stream
  * s = y*(L/4) + x/4 drives the four sites x0..x0+3 (x0 = 4*(x/4)) of row y.
- * Synchronous.  Errors: RNGX_E_ALIGN unless L % 16 == 0 and L >= 16. */
+ * Synchronous.  Errors: RNGX_E_ALIGN unless L % 16 == 0 and L >= 16 (LFG
+ * kinds: L % 64 == 0, whole 1024-stream instances), RNGX_E_OVERFLOW when
+ * the kind cannot hold L*L/4 streams (MWC_DIFF: L > 2896).  LFG lattices
+ * are swept one launch per colour pass, a workgroup per instance: it loads
+ * the instance's window into LDS, generates the pass's values there row by
+ * row and writes the window back. */
 rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *out);
 
 /* Run n_sweeps checkerboard Metropolis sweeps at inverse temperature beta

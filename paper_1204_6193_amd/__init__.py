@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librngx.so")
 
 KINDS = {"lcg32": 1, "lcg64": 2, "mwc": 3, "xorwow": 4, "philox4x32_10": 5, "xs1024w": 6, "philox4x32_7": 7,
-         "lcg32_sub": 8, "lcg64_sub": 9, "mwc_diff": 12}
+         "lcg32_sub": 8, "lcg64_sub": 9, "lfg521": 10, "lfg1279": 11, "mwc_diff": 12}
 KIND_NAMES = {v: k for k, v in KINDS.items()}
 STATUS = {0: "RNGX_OK", -1: "RNGX_E_INVALID", -2: "RNGX_E_ALIGN", -3: "RNGX_E_NOMEM", -4: "RNGX_E_HIP",
           -5: "RNGX_E_OVERFLOW", -6: "RNGX_E_STATE", -7: "RNGX_E_BUSY"}

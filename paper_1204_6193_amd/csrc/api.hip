@@ -99,6 +99,8 @@ rngx_status alloc_gen(rngx_kind kind, uint64_t S, Gen **out) {
         return fail(RNGX_E_ALIGN, "XS1024W needs n_streams % 32 == 0 (32 lanes per 1024-bit instance)");
     if (kind == RNGX_MWC_DIFF && S > kMwcDiffMaxStreams)
         return fail(RNGX_E_OVERFLOW, "MWC_DIFF allows at most 2^21 streams (multipliers above 2^31)");
+    if (is_lfg(kind) && S % kLfgLanes != 0)
+        return fail(RNGX_E_ALIGN, "lagged Fibonacci kinds need n_streams % 1024 == 0 (1024 lanes per instance)");
     Gen *g = new Gen{};
     g->magic = kGenMagic;
     g->kind = kind;
@@ -119,10 +121,12 @@ rngx_status alloc_gen(rngx_kind kind, uint64_t S, Gen **out) {
     int n_cu = 0;
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess) n_cu = 0;
     e = fill_setup(g, n_cu);
+    if (e == hipSuccess && is_lfg(kind)) e = hipMalloc(&g->d_aux, 4ull * lfg_lag_r(kind));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(g->d_state);
         (void)hipFree(g->d_ring);
+        (void)hipFree(g->d_aux);
         delete g;
         return fail(RNGX_E_NOMEM, std::string("fill set-up failed: ") + hipGetErrorString(e));
     }
@@ -134,6 +138,7 @@ void free_gen(Gen *g) {
     if (!g) return;
     (void)hipFree(g->d_state);
     (void)hipFree(g->d_ring);
+    (void)hipFree(g->d_aux);
     g->magic = 0;
     delete g;
 }
@@ -156,6 +161,16 @@ rngx_status validate_image(rngx_kind kind, uint64_t S, const uint8_t *img) {
         for (uint64_t s = 0; s < S; ++s)
             if (y[s] == 0 || y[s] >= kMwcP)
                 return fail(RNGX_E_STATE, "MWC stream " + std::to_string(s) + " is a fixed point (y = 0 or y >= p)");
+    } else if (is_lfg(kind)) {
+        const uint64_t r = lfg_lag_r(kind);
+        const uint32_t *X = reinterpret_cast<const uint32_t *>(img);
+        for (uint64_t g = 0; g < S / kLfgLanes; ++g) {
+            uint32_t odd = 0;
+            for (uint64_t j = 0; j < r; ++j) odd |= X[r * g + j] & 1u;
+            if (!odd)
+                return fail(RNGX_E_STATE, "lagged Fibonacci instance " + std::to_string(g) +
+                                              " has only even words (its low bits would stay zero)");
+        }
     } else if (kind == RNGX_MWC_DIFF) {
         const uint64_t *y = reinterpret_cast<const uint64_t *>(img);
         const uint32_t *a = reinterpret_cast<const uint32_t *>(img + 8 * S);
@@ -198,11 +213,13 @@ size_t state_bytes(rngx_kind kind, uint64_t S) {
     case RNGX_LCG64_SUB: return 8 * S + 16;
     case RNGX_XS1024W: return 4 * S + 8 * (S / 32) + 4;
     case RNGX_MWC_DIFF: return 12 * S;
+    case RNGX_LFG521: return 4 * 521 * (S / kLfgLanes);
+    case RNGX_LFG1279: return 4 * 1279 * (S / kLfgLanes);
     }
     return 0;
 }
 
-bool kind_valid(int kind) { return (kind >= RNGX_LCG32 && kind <= RNGX_LCG64_SUB) || kind == RNGX_MWC_DIFF; }
+bool kind_valid(int kind) { return kind >= RNGX_LCG32 && kind <= RNGX_MWC_DIFF; }
 
 rngx_status fail(rngx_status st, const std::string &msg) { g_error = msg; return st; }
 rngx_status hip_fail(hipError_t e, const char *what) {
@@ -386,6 +403,7 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
     Gen *g;
     if (rngx_status s = check_gen(h, &g)) return s;
     if (!offsets || !out) return fail(RNGX_E_INVALID, "NULL argument");
+    if (is_lfg(g->kind)) return fail(RNGX_E_INVALID, "ragged fills do not take lagged Fibonacci kinds");
     const uint64_t units = g->kind == RNGX_XS1024W ? g->S / 32 : g->S;
     if (n_offsets != units + 1)
         return fail(RNGX_E_INVALID, "need " + std::to_string(units + 1) + " offsets, got " + std::to_string(n_offsets));
@@ -528,6 +546,8 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
     if (!out) return fail(RNGX_E_INVALID, "out is NULL");
     if (!kind_valid(kind)) return fail(RNGX_E_INVALID, "invalid generator kind " + std::to_string(kind));
     if (L < 16 || L % 16) return fail(RNGX_E_ALIGN, "L must be a multiple of 16 and at least 16");
+    if (is_lfg(kind) && L % 64)
+        return fail(RNGX_E_ALIGN, "lagged Fibonacci lattices need L % 64 == 0 (whole 1024-stream instances)");
     if (L > kMaxL) return fail(RNGX_E_OVERFLOW, "L must not exceed 16384 (int32 energies)");
     const uint64_t S = static_cast<uint64_t>(L) * L / 4;
     Gen *g;
@@ -804,6 +824,7 @@ rngx_status ising_batch_create(const rngx_ising *lats, uint32_t n, const double 
         if (rngx_status s = check_ising(lats[i], &members[i])) return s;
         if (!seen.insert(members[i]).second) return fail(RNGX_E_INVALID, "lattice " + std::to_string(i) + " repeats");
         if (members[i]->gen->kind != members[0]->gen->kind) return fail(RNGX_E_INVALID, "mixed generator kinds");
+        if (is_lfg(members[i]->gen->kind)) return fail(RNGX_E_INVALID, "lagged Fibonacci lattices are not batched");
         if (members[i]->device != members[0]->device) return fail(RNGX_E_INVALID, "lattices on different devices");
         if (!std::isfinite(betas[i]) || betas[i] < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");
         if (d_traces && d_traces[i] && reinterpret_cast<uintptr_t>(d_traces[i]) % 4)
@@ -919,8 +940,8 @@ rngx_status srv_submit_fill(rngx_server h, uint32_t client, rngx_kind kind, uint
     Server *s;
     if (rngx_status st = check_server(h, &s)) return st;
     if (!ticket) return fail(RNGX_E_INVALID, "ticket is NULL");
-    if (!kind_valid(kind) || is_sub_lcg(kind) || kind == RNGX_MWC_DIFF)
-        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG and MWC_DIFF kinds are not served)");
+    if (!kind_valid(kind) || is_sub_lcg(kind) || kind == RNGX_MWC_DIFF || is_lfg(kind))
+        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG, MWC_DIFF and LFG kinds are not served)");
     if (count == 0) return fail(RNGX_E_INVALID, "count must be positive");
     if (count > kMaxServedValues) return fail(RNGX_E_OVERFLOW, "count exceeds 2^28");
     if (rngx_status st = server_submit_fill(s, client, kind, count, as_f32, ticket)) return st;
@@ -933,8 +954,8 @@ rngx_status srv_submit_ising(rngx_server h, uint32_t client, rngx_kind kind, uin
     Server *s;
     if (rngx_status st = check_server(h, &s)) return st;
     if (!ticket) return fail(RNGX_E_INVALID, "ticket is NULL");
-    if (!kind_valid(kind) || is_sub_lcg(kind) || kind == RNGX_MWC_DIFF)
-        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG and MWC_DIFF kinds are not served)");
+    if (!kind_valid(kind) || is_sub_lcg(kind) || kind == RNGX_MWC_DIFF || is_lfg(kind))
+        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG, MWC_DIFF and LFG kinds are not served)");
     if (L < 16 || L % 16) return fail(RNGX_E_ALIGN, "L must be a multiple of 16 and at least 16");
     if (L > kMaxL) return fail(RNGX_E_OVERFLOW, "L must not exceed 16384");
     if (!std::isfinite(beta) || beta < 0) return fail(RNGX_E_INVALID, "beta must be finite and >= 0");

@@ -304,6 +304,9 @@ __global__ __launch_bounds__(kBlock) void k_zero_ring(uint32_t *ring) {
 constexpr rngx_fill_config kSmallConfigs[] = {{1, 4, 512}, {1, 4, 1024}, {1, 4, 256}, {1, 2, 1024},
                                               {1, 2, 512}, {1, 2, 256},  {0, 4, 256}};
 constexpr rngx_fill_config kXsConfigs[] = {{1, 2, 1024}, {1, 2, 512}, {0, 2, 1024}, {0, 2, 256}};
+// Lagged Fibonacci kinds: one wave per 1024-stream instance (16 streams per
+// lane), four waves per workgroup, free-running.
+constexpr rngx_fill_config kLfgConfigs[] = {{0, 16, 256}};
 constexpr int kNumSmall = sizeof(kSmallConfigs) / sizeof(kSmallConfigs[0]);
 constexpr int kNumXs = sizeof(kXsConfigs) / sizeof(kXsConfigs[0]);
 static_assert(kNumSmall <= kMaxFillConfigs && kNumXs <= kMaxFillConfigs, "Gen::resident too small");
@@ -345,6 +348,7 @@ const void *config_kernel(rngx_kind kind, int mode, const rngx_fill_config &c) {
     case RNGX_LCG32_SUB: return config_kernel<Lcg32Sub>(mode, c);
     case RNGX_LCG64_SUB: return config_kernel<Lcg64Sub>(mode, c);
     case RNGX_XS1024W: return mode == kOutU32 ? xs_kernel<kOutU32>(c.block) : xs_kernel<kOutF32>(c.block);
+    default: break;  // lagged Fibonacci kinds have their own kernel
     }
     return nullptr;
 }
@@ -431,6 +435,7 @@ hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
     case RNGX_LCG32_SUB: return fill_small<Lcg32Sub, MODE>(g, out, count, st);
     case RNGX_LCG64_SUB: return fill_small<Lcg64Sub, MODE>(g, out, count, st);
     case RNGX_XS1024W: return fill_xs<MODE>(g, out, count, st);
+    default: break;
     }
     return hipErrorInvalidValue;
 }
@@ -438,6 +443,7 @@ hipError_t fill_mode(Gen *g, void *out, uint64_t count, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st) {
+    if (is_lfg(g->kind)) return launch_seed_lfg(g, seed, st);
     if (g->kind == RNGX_XS1024W) {
         const uint64_t pairs = g->S / 2;
         const unsigned blocks = static_cast<unsigned>((pairs + kBlock - 1) / kBlock);
@@ -462,6 +468,7 @@ hipError_t fill_setup(Gen *g, int n_cu) {
 }
 
 int fill_configs(rngx_kind kind, const rngx_fill_config **list) {
+    if (is_lfg(kind)) { *list = kLfgConfigs; return 1; }
     *list = kind == RNGX_XS1024W ? kXsConfigs : kSmallConfigs;
     return kind == RNGX_XS1024W ? kNumXs : kNumSmall;
 }
@@ -469,6 +476,7 @@ int fill_configs(rngx_kind kind, const rngx_fill_config **list) {
 int fill_default(rngx_kind kind) { return default_config(kind); }
 
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st) {
+    if (is_lfg(g->kind)) return launch_fill_lfg(g, d_out, count, mode, st);
     if (mode == kOutU32) return fill_mode<kOutU32>(g, d_out, count, st);
     if (mode == kOutF32) return fill_mode<kOutF32>(g, d_out, count, st);
     return fill_mode<kOutXor>(g, d_out, count, st);

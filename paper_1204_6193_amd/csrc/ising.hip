@@ -258,13 +258,6 @@ __device__ __forceinline__ void put_word(uint64_t *p, uint32_t spins, uint32_t t
     __hip_atomic_store(p, (static_cast<uint64_t>(tag) << 32) | spins, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// n bytes, n a multiple of 16 and both ends 16-byte aligned (rows are L
-// bytes with L a multiple of 16).
-__device__ __forceinline__ void copy_bytes(uint8_t *dst, const uint8_t *src, uint32_t n, uint32_t t, uint32_t nt) {
-    for (uint32_t i = 16 * t; i < n; i += 16 * nt)
-        *reinterpret_cast<uint4 *>(dst + i) = *reinterpret_cast<const uint4 *>(src + i);
-}
-
 // Two rows of L bytes (src0 -> dst0, src1 -> dst1) by the whole block: all
 // loads are issued before the first LDS write, one round trip in all.
 __device__ __forceinline__ void copy_rows(uint8_t *dst0, const uint8_t *src0, uint8_t *dst1, const uint8_t *src1,
@@ -518,7 +511,6 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
     const uint32_t P = lds_pitch(L);
     const uint64_t row0 = static_cast<uint64_t>(r) * a.R0;
     const uint32_t upr = L / NB;             // units per row
-    const uint32_t last0 = a.units - upr;    // first unit of the bottom row
     const uint32_t W = L / 4;                // halo words per row
     int *wave_e = reinterpret_cast<int *>(lds + (R + 4) * P);
     uint32_t *zero_word = reinterpret_cast<uint32_t *>(lds + (R + 4) * P + 64);
@@ -711,8 +703,21 @@ struct PassArgs {
 // the sum of s*h over the updated sites.  A unit reads only other-colour
 // bytes of its neighbour runs, which no thread writes during the pass.
 template <class Unit, bool MH = false>
+__device__ __forceinline__ int unit_in_memory_with(Unit &u, uint8_t *sp, uint8_t *st, uint64_t S, uint32_t L,
+                                                   uint64_t k, int c, uint64_t T4, uint64_t T8, uint32_t hits);
+
+template <class Unit, bool MH = false>
 __device__ __forceinline__ int unit_in_memory(uint8_t *sp, uint8_t *st, uint64_t S, uint32_t L, uint64_t k, int c,
                                               uint64_t T4, uint64_t T8, uint32_t hits = 1) {
+    Unit u;
+    u.load(st, S, k);
+    return unit_in_memory_with<Unit, MH>(u, sp, st, S, L, k, c, T4, T8, hits);
+}
+
+// The update with the unit's generator already loaded (it stores it back).
+template <class Unit, bool MH>
+__device__ __forceinline__ int unit_in_memory_with(Unit &u, uint8_t *sp, uint8_t *st, uint64_t S, uint32_t L,
+                                                   uint64_t k, int c, uint64_t T4, uint64_t T8, uint32_t hits) {
     constexpr int NB = Unit::kNB;
     const uint32_t upr = L / NB;
     const uint64_t y = k / upr;
@@ -725,8 +730,6 @@ __device__ __forceinline__ int unit_in_memory(uint8_t *sp, uint8_t *st, uint64_t
     const uint32_t rb = sp[row + (x0 + NB == L ? 0 : x0 + NB)];
     const uint64_t m = mismatches<NB>(w, upw, dnw, lb, rb);
     const int p = static_cast<int>((c + y) & 1);
-    Unit u;
-    u.load(st, S, k);
     int sh = 0;
     if constexpr (MH) {
         // byte p + 2h is site h; the same draw order as the on-chip update
@@ -782,6 +785,90 @@ __global__ __launch_bounds__(kBlock) void k_ising_pass(PassArgs a, uint64_t n_un
         const int tot = block_sum(sh, red);
         if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
     }
+}
+
+// ---------------------------------------------------------------- lagged Fibonacci
+// A lagged Fibonacci instance is shared by 1024 streams, i.e. 1024
+// consecutive units (L a multiple of 64), so a lattice is swept one launch
+// per colour pass with one 1024-thread workgroup per instance: it loads the
+// instance's last r values into an LDS ring, and each draw of the pass is a
+// row of 1024 new values made by the whole workgroup (runs of at most s
+// values, one barrier each; thread i then takes value i of the row), after
+// which the window goes back to memory.  Every thread has a unit, so all
+// reach each row's barriers together.
+template <int R, int SL>
+struct LfgPassUnit {
+    static constexpr int kNB = 4;
+    static constexpr uint32_t B = R + 1024 <= 2048 ? 2048 : 4096;  // a row plus the r values before it
+    uint32_t *ring;  // LDS: value q at ring[q mod B]
+    uint32_t q;      // index of the next row's first value
+    __device__ void load(const uint8_t *, uint64_t, uint64_t) {}
+    __device__ void store(uint8_t *, uint64_t, uint64_t, uint64_t) const {}
+    __device__ uint32_t next() {
+        const uint32_t t = threadIdx.x;
+        for (uint32_t b = 0; b < 1024; b += SL) {
+            const uint32_t len = min(static_cast<uint32_t>(SL), 1024 - b);
+            const uint32_t qq = q + b + t;
+            if (t < len) ring[qq & (B - 1)] = ring[(qq - R) & (B - 1)] + ring[(qq - SL) & (B - 1)];
+            __syncthreads();
+        }
+        const uint32_t v = ring[(q + t) & (B - 1)];
+        q += 1024;
+        return v;
+    }
+    __device__ void draw(uint32_t (&r)[2]) { r[0] = next(); r[1] = next(); }
+    template <class F0, class F1>
+    __device__ void draws2(uint32_t n, F0 &&f0, F1 &&f1) {
+        for (uint32_t i = 0; i < n; ++i) f0(next());
+        for (uint32_t i = 0; i < n; ++i) f1(next());
+    }
+};
+
+template <int R, int SL, bool MH>
+__global__ __launch_bounds__(1024) void k_ising_pass_lfg(PassArgs a) {
+    using U = LfgPassUnit<R, SL>;
+    __shared__ uint32_t ring[U::B];
+    __shared__ int red[16];
+    uint32_t *X = reinterpret_cast<uint32_t *>(a.st) + static_cast<uint64_t>(blockIdx.x) * R;
+    for (uint32_t j = threadIdx.x; j < R; j += blockDim.x) ring[U::B - R + j] = X[j];
+    __syncthreads();
+    U u{ring, 0};
+    const uint64_t k = static_cast<uint64_t>(blockIdx.x) * 1024 + threadIdx.x;
+    const int sh = unit_in_memory_with<U, MH>(u, reinterpret_cast<uint8_t *>(a.spins), a.st, a.S, a.L, k, a.c,
+                                              a.T4, a.T8, a.hits);
+    // the last row's barrier has passed and no thread writes the ring again
+    for (uint32_t j = threadIdx.x; j < R; j += blockDim.x) X[j] = ring[(u.q - R + j) & (U::B - 1)];
+    if (a.partial) {
+        const int tot = block_sum(sh, red);
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
+    }
+}
+
+// L = 64: the lattice is one instance, so one workgroup runs every sweep of
+// the call in one launch, the window staying in LDS throughout; the spins
+// stay in memory and a barrier separates the passes.
+template <int R, int SL, bool MH>
+__global__ __launch_bounds__(1024) void k_ising_lfg_one(PassArgs a, uint64_t n_sweeps, int32_t *trace) {
+    using U = LfgPassUnit<R, SL>;
+    __shared__ uint32_t ring[U::B];
+    __shared__ int red[16];
+    uint32_t *X = reinterpret_cast<uint32_t *>(a.st);
+    for (uint32_t j = threadIdx.x; j < R; j += blockDim.x) ring[U::B - R + j] = X[j];
+    __syncthreads();
+    U u{ring, 0};
+    uint8_t *sp = reinterpret_cast<uint8_t *>(a.spins);
+    for (uint64_t t = 0; t < n_sweeps; ++t) {
+        int sh = 0;
+        for (int c = 0; c < 2; ++c) {
+            sh = unit_in_memory_with<U, MH>(u, sp, a.st, a.S, a.L, threadIdx.x, c, a.T4, a.T8, a.hits);
+            __syncthreads();  // this pass's spins before the next pass reads them
+        }
+        if (trace) {
+            const int tot = block_sum(sh, red);
+            if (threadIdx.x == 0) trace[t] = -tot;
+        }
+    }
+    for (uint32_t j = threadIdx.x; j < R; j += blockDim.x) X[j] = ring[(u.q - R + j) & (U::B - 1)];
 }
 
 // ---------------------------------------------------------------- batches
@@ -1077,6 +1164,7 @@ const void *batch_kernel_for(rngx_kind kind) {
     case RNGX_PHILOX4X32_10: return batch_kernel<PhiloxUnit>();
     case RNGX_PHILOX4X32_7: return batch_kernel<PhiloxUnit7>();
     case RNGX_XS1024W: return batch_kernel<XsUnit>();
+    default: break;  // lagged Fibonacci: per-pass kernels only
     }
     return nullptr;
 }
@@ -1232,6 +1320,7 @@ int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int ma
     case RNGX_PHILOX4X32_10: return list_plans<PhiloxUnit>(L, 16, n_cu, out, max);
     case RNGX_PHILOX4X32_7: return list_plans<PhiloxUnit7>(L, 16, n_cu, out, max);
     case RNGX_XS1024W: return list_plans<XsUnit>(L, 16, n_cu, out, max);
+    default: break;  // lagged Fibonacci: per-pass kernels only
     }
     return 0;
 }
@@ -1248,9 +1337,46 @@ bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
     case RNGX_PHILOX4X32_10: return plan_strips<PhiloxUnit>(L, 16, n_cu, out);
     case RNGX_PHILOX4X32_7: return plan_strips<PhiloxUnit7>(L, 16, n_cu, out);
     case RNGX_XS1024W: return plan_strips<XsUnit>(L, 16, n_cu, out);
+    default: break;  // lagged Fibonacci: per-pass kernels only
     }
     return false;
 }
+
+namespace {
+template <int R, int SL, bool MH>
+hipError_t run_passes_lfg(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st,
+                          uint32_t hits) {
+    const uint64_t G = lat->gen->S / kLfgLanes;
+    PassArgs pa{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, 0, T4, T8, nullptr, hits};
+    for (uint64_t t = 0; t < n; ++t) {
+        for (int c = 0; c < 2; ++c) {
+            pa.c = c;
+            pa.partial = (c == 1 && tr) ? lat->d_partial : nullptr;
+            hipLaunchKernelGGL((k_ising_pass_lfg<R, SL, MH>), dim3(static_cast<unsigned>(G)), dim3(1024), 0, st, pa);
+        }
+        if (tr) hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, st, lat->d_partial, G, tr + t);
+    }
+    return hipGetLastError();
+}
+
+template <int R, int SL, bool MH>
+hipError_t run_one_lfg(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st, uint32_t hits) {
+    PassArgs pa{lat->d_spins, lat->gen->d_state, lat->gen->S, lat->L, 0, T4, T8, nullptr, hits};
+    hipLaunchKernelGGL((k_ising_lfg_one<R, SL, MH>), dim3(1), dim3(1024), 0, st, pa, n, tr);
+    return hipGetLastError();
+}
+
+template <int R, int SL>
+hipError_t run_lfg(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st, uint32_t hits) {
+    if (n == 0) return hipSuccess;
+    if (lat->gen->S == kLfgLanes) {
+        if (hits == 1) return run_one_lfg<R, SL, false>(lat, T4, T8, n, tr, st, 1);
+        return run_one_lfg<R, SL, true>(lat, T4, T8, n, tr, st, hits);
+    }
+    if (hits == 1) return run_passes_lfg<R, SL, false>(lat, T4, T8, n, tr, st, 1);
+    return run_passes_lfg<R, SL, true>(lat, T4, T8, n, tr, st, hits);
+}
+}  // namespace
 
 uint64_t ising_partials(uint32_t L) { return (static_cast<uint64_t>(L) * L / 4 + kBlock - 1) / kBlock; }
 
@@ -1283,6 +1409,9 @@ hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_t
     case RNGX_PHILOX4X32_10: return run<PhiloxUnit>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_PHILOX4X32_7: return run<PhiloxUnit7>(lat, T4, T8, n_sweeps, d_trace, st, hits);
     case RNGX_XS1024W: return run<XsUnit>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_LFG521: return run_lfg<521, 353>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    case RNGX_LFG1279: return run_lfg<1279, 861>(lat, T4, T8, n_sweeps, d_trace, st, hits);
+    default: break;
     }
     return hipErrorInvalidValue;
 }

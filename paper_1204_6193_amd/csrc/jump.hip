@@ -349,6 +349,8 @@ hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st) {
         break;
     }
     case RNGX_MWC_DIFF: return launch_skip_mwc_diff(g, n, st);
+    case RNGX_LFG521:
+    case RNGX_LFG1279: return launch_skip_lfg(g, n, st);
     case RNGX_MWC:
         hipLaunchKernelGGL(k_skip_mwc, dim3(blocks_for(S)), dim3(kBlock), 0, st,
                            reinterpret_cast<uint64_t *>(g->d_state), S, host_powmod_p(kMwcA, n));

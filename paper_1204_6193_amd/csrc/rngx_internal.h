@@ -32,8 +32,11 @@ struct Gen {
     int fill_cfg;       // fill configuration (index into the kind's list), -1: default
     int resident[8];    // per configuration: workgroups that fit at once, -1: not known yet
     uint64_t sub_a, sub_c;  // sub-stream LCG kinds: the S-step map (A_S, C_S) of the image header
+    uint32_t *d_aux;        // LFG kinds: r words staging a jump polynomial
 };
 inline bool is_sub_lcg(rngx_kind k) { return k == RNGX_LCG32_SUB || k == RNGX_LCG64_SUB; }
+inline bool is_lfg(rngx_kind k) { return k == RNGX_LFG521 || k == RNGX_LFG1279; }
+constexpr uint64_t kLfgLanes = 1024;  // streams of one lagged Fibonacci instance
 constexpr int kMaxFillConfigs = 8;
 
 // One chunk of one stream's (XS1024W: one instance's) ragged request.
@@ -139,6 +142,12 @@ hipError_t mwc_diff_multipliers(uint64_t n, uint32_t *d_dst, hipStream_t st);
 bool mwc_diff_multipliers_match(const uint32_t *a, uint64_t n);  // a[0..n) = the first n multipliers
 hipError_t launch_skip_mwc_diff(Gen *g, uint64_t n, hipStream_t st);
 constexpr uint64_t kMwcDiffMaxStreams = 1ull << 21;
+// Lagged Fibonacci kinds (lfg.hip): lags, seeding, fills, jump-ahead.
+int lfg_lag_r(rngx_kind kind);
+int lfg_lag_s(rngx_kind kind);
+hipError_t launch_seed_lfg(Gen *g, uint64_t seed, hipStream_t st);
+hipError_t launch_fill_lfg(Gen *g, void *out, uint64_t count, int mode, hipStream_t st);
+hipError_t launch_skip_lfg(Gen *g, uint64_t n, hipStream_t st);  // synchronous
 
 // Host-side jump tables for j = 0 .. count-1 steps of size `step`:
 //  LCG32/LCG64: (A, C) pairs of the affine map f^(j step), 2 u64 each;

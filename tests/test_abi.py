@@ -45,9 +45,12 @@ def test_create_validation(rngx):
     lib = rngx.load()
     h = ctypes.c_void_p()
     assert lib.rng_create(0, 16, 1, ctypes.byref(h)) == -1
-    assert lib.rng_create(10, 16, 1, ctypes.byref(h)) == -1
+    assert lib.rng_create(13, 16, 1, ctypes.byref(h)) == -1
     assert lib.rng_create(1, 0, 1, ctypes.byref(h)) == -1
     assert lib.rng_create(6, 48, 1, ctypes.byref(h)) == -2 and "% 32" in _err(lib)
+    for lfg in (10, 11):  # lagged Fibonacci: whole 1024-stream instances
+        assert lib.rng_create(lfg, 1000, 1, ctypes.byref(h)) == -2 and "% 1024" in _err(lib)
+    assert lib.rng_create(12, (1 << 21) + 1, 1, ctypes.byref(h)) == -5  # MWC_DIFF: multipliers above 2^31
     assert lib.rng_create(1, (1 << 36) + 1, 1, ctypes.byref(h)) == -5
     assert lib.rng_create(1, 16, 1, None) == -1
     assert h.value is None  # nothing was written
@@ -59,6 +62,14 @@ def test_ising_create_rejects_bad_L(rngx, L):
     h = ctypes.c_void_p()
     assert lib.ising_create(L, 1, 1, ctypes.byref(h)) == -2
     assert lib.ising_create(32768, 1, 1, ctypes.byref(h)) == -5
+
+
+@pytest.mark.parametrize("L", [16, 48, 80, 96])
+def test_ising_create_rejects_lfg_lattices_of_partial_instances(rngx, L):
+    lib = rngx.load()
+    h = ctypes.c_void_p()
+    for lfg in (10, 11):
+        assert lib.ising_create(L, lfg, 1, ctypes.byref(h)) == -2 and "% 64" in _err(lib)
 
 
 def test_unknown_handles_are_rejected(rngx):
@@ -79,14 +90,16 @@ def test_fill_configuration_lists(rngx):
     lib = rngx.load()
     small = rngx.rng_fill_configs("lcg32")
     assert len(small) == 7 and small[0] == (1, 4, 512) and (0, 4, 256) in small
-    for kind in ("lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7", "lcg32_sub", "lcg64_sub"):
+    for kind in ("lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7", "lcg32_sub", "lcg64_sub", "mwc_diff"):
         assert rngx.rng_fill_configs(kind) == small
+    for kind in ("lfg521", "lfg1279"):  # one wave per 1024-stream instance
+        assert rngx.rng_fill_configs(kind) == [(0, 16, 256)]
     xs = rngx.rng_fill_configs("xs1024w")
     assert len(xs) == 4 and all(v == 2 for _, v, _ in xs) and xs[0] == (1, 2, 1024)
     for paced, v, block in small + xs:
         assert paced in (0, 1) and v in (2, 4) and block in (256, 512, 1024)
     n = ctypes.c_int()
-    assert lib.rng_fill_configs(10, None, ctypes.byref(n)) == -1
+    assert lib.rng_fill_configs(13, None, ctypes.byref(n)) == -1
     assert lib.rng_fill_configs(1, None, None) == -1
     bogus = ctypes.c_void_p(0x1234560)
     assert lib.rng_set_fill_config(bogus, 0) == -1

@@ -1,0 +1,213 @@
+"""GPU <-> oracle parity of the block-shared additive lagged Fibonacci
+generators (lags (521, 353) and (1279, 861)): seeding, fills in warp order,
+consume, jump-ahead, state images and their checkerboard Ising consumer, all
+bit-exact; Ising statistics against the exact finite-lattice values."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import isingstats
+from oracle import exact_ising as ex
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["lfg521", "lfg1279"]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _fill(rx, g, count, f32=False):
+    out = torch.empty(g.n_streams * count + 4, dtype=torch.float32 if f32 else torch.int32, device="cuda")
+    (rx.rng_fill_f32 if f32 else rx.rng_fill_u32)(g, out, count)
+    host = out[: g.n_streams * count].cpu().numpy()
+    return host.reshape(count, g.n_streams) if f32 else host.view(np.uint32).reshape(count, g.n_streams)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_seed_image_matches_oracle(rngx, orc, kind):
+    for S in (1024, 5 * 1024):
+        g = rngx.rng_create(kind, S, 0xC0FFEE)
+        assert np.array_equal(rngx.rng_get_state(g), orc.seed(kind, S, 0xC0FFEE)), (kind, S)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_fill_parity_and_continuation(rngx, orc, kind):
+    """u32 in three calls of uneven length, then FP32; the state image after
+    every call.  Five instances: one workgroup of four waves and a partial
+    one."""
+    S = 5 * 1024
+    print(f"case lfg fill {kind}", flush=True)
+    g = rngx.rng_create(kind, S, 1)
+    st = orc.seed(kind, S, 1)
+    for count in (37, 1, 300):
+        assert np.array_equal(_fill(rngx, g, count), orc.generate(kind, S, st, count)), (kind, count)
+        assert np.array_equal(rngx.rng_get_state(g), st), (kind, count)
+    got = _fill(rngx, g, 19, f32=True)
+    want = orc.generate(kind, S, st, 19, mode=orc.OUT_F32)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    assert np.array_equal(rngx.rng_get_state(g), st)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_consume_parity(rngx, orc, kind):
+    S = 3 * 1024
+    g = rngx.rng_create(kind, S, 9)
+    st = orc.seed(kind, S, 9)
+    acc = torch.zeros(S, dtype=torch.int32, device="cuda")
+    rngx.rng_consume(g, acc, 301)
+    assert np.array_equal(acc.cpu().numpy().view(np.uint32), orc.generate(kind, S, st, 301, mode=orc.OUT_XOR))
+    assert np.array_equal(rngx.rng_get_state(g), st)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_skip_parity(rngx, orc, kind):
+    S = 2048
+    g = rngx.rng_create(kind, S, 3)
+    st = orc.seed(kind, S, 3)
+    for n in (1, 2, 1000, 4097, (1 << 40) + 7, (1 << 64) - 1):
+        print(f"case lfg skip {kind} n={n}", flush=True)
+        rngx.rng_skip(g, n)
+        orc.jump(kind, S, st, n)
+        assert np.array_equal(rngx.rng_get_state(g), st), (kind, n)
+        assert np.array_equal(_fill(rngx, g, 3), orc.generate(kind, S, st, 3)), (kind, n)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_state_images(rngx, orc, kind):
+    """A foreign image is taken and continued exactly; an instance with only
+    even words (its low bits would stay zero) is refused and nothing changes."""
+    S = 2048
+    r = orc.LFG_LAGS[kind][0]
+    g = rngx.rng_create(kind, S, 1)
+    st = orc.seed(kind, S, 77)
+    orc.generate(kind, S, st, 11)
+    rngx.rng_set_state(g, st)
+    assert np.array_equal(rngx.rng_get_state(g), st)
+    assert np.array_equal(_fill(rngx, g, 13), orc.generate(kind, S, st, 13))
+    bad = st.copy()
+    words = bad.view(np.uint32)
+    words[r: 2 * r] &= np.uint32(0xFFFFFFFE)  # instance 1: all even
+    with pytest.raises(rngx.RngxError) as e:
+        rngx.rng_set_state(g, bad)
+    assert e.value.status == -6
+    assert np.array_equal(rngx.rng_get_state(g), st)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_full_size_sampled_parity(rngx, orc, kind):
+    """2^20 streams (1024 instances) x 4096 outputs, as the benchmark fills
+    them: three sampled instances equal the oracle over all 4096 rows; the
+    consume variant on a twin equals the XOR of the whole output; a skip of
+    4096 on a third handle lands on the same state."""
+    S, count = 1 << 20, 4096
+    print(f"case lfg full-size {kind}", flush=True)
+    g = rngx.rng_create(kind, S, 1)
+    out = torch.empty(S * count, dtype=torch.int32, device="cuda")
+    rngx.rng_fill_u32(g, out, count)
+    view = out.view(count, S)
+    st = orc.seed(kind, S, 1)
+    for inst in (0, 511, 1023):
+        lo, hi = 1024 * inst, 1024 * inst + 1024
+        want = orc.generate(kind, S, st, count, lo=lo, hi=hi)
+        assert np.array_equal(view[:, lo:hi].contiguous().cpu().numpy().view(np.uint32), want), (kind, inst)
+    xor_all = view[0].clone()
+    for k in range(1, count):
+        xor_all ^= view[k]
+    del out, view
+    g2 = rngx.rng_create(kind, S, 1)
+    acc = torch.empty(S, dtype=torch.int32, device="cuda")
+    rngx.rng_consume(g2, acc, count)
+    assert torch.equal(acc, xor_all)
+    g3 = rngx.rng_create(kind, S, 1)
+    rngx.rng_skip(g3, count)
+    assert np.array_equal(rngx.rng_get_state(g3), rngx.rng_get_state(g))
+    assert np.array_equal(rngx.rng_get_state(g2), rngx.rng_get_state(g))
+    torch.cuda.empty_cache()
+
+
+def _run_both(rx, orc, L, kind, beta, chunks, hits=1, seed=1):
+    lat = rx.ising_create(L, kind, seed)
+    assert rx.ising_info(lat)["strips"] == 0  # one launch per colour pass
+    sp, st = orc.ising_create(L, kind, seed)
+    for n in chunks:
+        tr = torch.zeros(n, dtype=torch.int32, device="cuda")
+        rx.ising_sweep_hits(lat, beta, n, hits, tr)
+        want = orc.ising_sweeps(L, kind, beta, st, sp, n, hits=hits)
+        assert np.array_equal(tr.cpu().numpy(), want), (L, kind, beta, hits)
+        assert np.array_equal(rx.ising_get_spins(lat).ravel(), sp), (L, kind, beta, hits)
+        assert np.array_equal(rx.rng_get_state(rx.ising_rng(lat)), st), (L, kind, beta, hits)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("L", [64, 128, 192, 1024])
+def test_ising_parity(rngx, orc, kind, L):
+    """Spins, energies and instance windows bit-exact: one instance (L = 64,
+    an instance spans 64 rows), several, an odd number of instances per row
+    band (192: 9 instances), and L = 1024 (256 instances of 4 rows)."""
+    print(f"case lfg ising {kind} L={L}", flush=True)
+    for beta in (0.4, ex.BETA_C):
+        _run_both(rngx, orc, L, kind, beta, (5, 1, 4) if L < 1024 else (2, 1))
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_ising_multihit_and_extremes(rngx, orc, kind):
+    """k = 2 and 3 updates per visited site, k = 100 (200 rows per pass made
+    row by row), and beta = 0 (every flip accepted) and a frozen beta."""
+    print(f"case lfg ising multihit {kind}", flush=True)
+    _run_both(rngx, orc, 128, kind, 0.4, (3, 2), hits=2)
+    _run_both(rngx, orc, 64, kind, ex.BETA_C, (2,), hits=3)
+    _run_both(rngx, orc, 64, kind, 0.4, (2,), hits=100)
+    for beta in (0.0, 1e9):
+        _run_both(rngx, orc, 64, kind, beta, (3,))
+
+
+def test_ising_rejections(rngx):
+    with pytest.raises(rngx.RngxError) as e:
+        rngx.ising_create(96, "lfg521", 1)
+    assert e.value.status == -2
+    lat = rngx.ising_create(64, "lfg521", 1)
+    assert rngx.ising_plans(lat) == [0]
+    with pytest.raises(rngx.RngxError):
+        rngx.ising_batch_create([lat], [0.4], [1])
+    g = rngx.rng_create("lfg1279", 1024, 1)
+    with pytest.raises(rngx.RngxError):
+        rngx.rng_ragged_create(g, [0] * 1025)
+    srv = rngx.Server(slots=1, max_inflight=1, memory_budget=64 << 20, seed=1)
+    with pytest.raises(rngx.RngxError):
+        srv.submit_fill(0, "lfg521", 100, False)
+    with pytest.raises(rngx.RngxError):
+        srv.submit_ising(0, "lfg1279", 64, 0.4, 1)
+    srv.destroy()
+
+
+def _exact(L, beta):
+    with open(os.path.join(GOLDEN, "exact_ising.json")) as f:
+        for rec in json.load(f)["values"]:
+            if rec["L"] == L and abs(rec["beta"] - beta) < 1e-15:
+                return rec["e"], rec["C_V"]
+    raise KeyError((L, beta))
+
+
+def test_ising_statistics(rngx):
+    """e and C_V at L = 64, beta = 0.4 and beta_c (10^5 + 10^6 sweeps, 20
+    bins, jackknife) against the exact values.  r = 1279 is gated at 3
+    standard errors; r = 521, which the paper finds biased in the energy at
+    L = 1024, is printed."""
+    L, n_eq, n_meas = 64, 100_000, 1_000_000
+    bad = []
+    for kind in KINDS:
+        for beta in (0.4, ex.BETA_C):
+            lat = rngx.ising_create(L, kind, 1)
+            rngx.ising_sweep(lat, beta, n_eq)
+            tr = torch.zeros(n_meas, dtype=torch.int32, device="cuda")
+            rngx.ising_sweep(lat, beta, n_meas, tr)
+            e, se, c, sc = isingstats.estimates(tr.cpu().numpy(), L * L, beta)
+            ee, ce = _exact(L, beta)
+            ze, zc = (e - ee) / se, (c - ce) / sc
+            print(f"stat {kind:8s} L={L} beta={beta:.5f} e={e:.6f}+-{se:.6f} z={ze:+.2f} "
+                  f"C={c:.5f}+-{sc:.5f} z={zc:+.2f}", flush=True)
+            if kind == "lfg1279" and (abs(ze) > 3 or abs(zc) > 3):
+                bad.append((kind, beta, round(ze, 2), round(zc, 2)))
+    assert not bad, bad
