@@ -268,6 +268,22 @@ rngx_status rng_ragged_create(rngx_gen g, const uint64_t *offsets, uint64_t n_of
 rngx_status rng_fill_ragged_u32(rngx_ragged r, uint32_t *d_out, void *stream);
 rngx_status rng_ragged_destroy(rngx_ragged r);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid it): the same fill
+ * as rng_ragged_create(g, offsets, n_offsets) followed by
+ * rng_fill_ragged_u32 -- same values, same final stream states -- made in
+ * one call that allocates nothing.  The plan is made on the host for every
+ * call and staged, with the chunk states, in a fixed 64 MiB device array
+ * that each device running the library holds until the process ends.
+ * Synchronous: returns when the fill is done.  Calls are serialised within
+ * the process (they share the array); calls from other processes use their
+ * own.  Not for graph capture.  Errors: those of rng_ragged_create, and
+ * RNGX_E_OVERFLOW when the plan needs more than the 64 MiB (about a million
+ * chunks of 4096 values for the small-state kinds, far more values for the
+ * LCGs and XS1024W), before anything is modified. */
+rngx_status rng_fill_ragged_u32_noalloc(rngx_gen g, const uint64_t *offsets, uint64_t n_offsets, uint32_t *d_out,
+                                        void *stream);
+
 /* Copy the handle's state image (layout above) to host memory.  If host_buf
  * is NULL only *bytes is set to the image size.  Otherwise *bytes must be at
  * least that size; the call waits for `stream` and then copies. */

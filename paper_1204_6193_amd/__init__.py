@@ -46,6 +46,7 @@ SIGNATURES = {
     "rng_ragged_create": (_i32, [_vp, _vp, _u64, ctypes.POINTER(_vp)]),
     "rng_fill_ragged_u32": (_i32, [_vp, _vp, _vp]),
     "rng_ragged_destroy": (_i32, [_vp]),
+    "rng_fill_ragged_u32_noalloc": (_i32, [_vp, _vp, _u64, _vp, _vp]),
     "rng_get_state": (_i32, [_vp, _vp, ctypes.POINTER(_sz), _vp]),
     "rng_set_state": (_i32, [_vp, _vp, _sz, _vp]),
     "ising_create": (_i32, [ctypes.c_uint32, _i32, _u64, ctypes.POINTER(_vp)]),
@@ -286,6 +287,17 @@ def rng_fill_ragged_u32(r: Ragged, out, stream=None):
 
 def rng_ragged_destroy(r: Ragged):
     r.destroy()
+
+
+def rng_fill_ragged_u32_noalloc(g: Gen, offsets, out, stream=None):
+    """rng_ragged_create + rng_fill_ragged_u32 in one synchronous call that
+    allocates no device memory (the plan is staged in the library's static
+    device scratch)."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    total = int(off[-1]) if off.size else 0
+    _check(load().rng_fill_ragged_u32_noalloc(g.handle, off.ctypes.data, off.size, _dptr(out, total, 4),
+                                              _stream(stream)))
 
 
 def rng_get_state(g: Gen, stream=None):

@@ -430,12 +430,8 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
     if (!items.empty()) {
         e = hipMalloc(&r->d_items, sizeof(RaggedItem) * items.size());
         if (e == hipSuccess && ragged_affine(g->kind)) {
-            // entry i: the (i+1)-step map (a lane whose first position is i); entry 256: the 256-step advance
-            uint64_t a = g->kind == RNGX_LCG32 ? kLcg32A : g->kind == RNGX_LCG64 ? kLcg64A : g->sub_a;
-            uint64_t c = g->kind == RNGX_LCG32 ? kLcg32C : g->kind == RNGX_LCG64 ? kLcg64C : g->sub_c;
-            std::vector<uint64_t> lane(514);
-            for (int i = 0; i < 256; ++i) affine_power(a, c, i + 1, &lane[2 * i], &lane[2 * i + 1]);
-            affine_power(a, c, 256, &lane[512], &lane[513]);
+            std::vector<uint64_t> lane;
+            ragged_lane_maps(g, &lane);
             e = hipMalloc(&r->d_lane, 8 * lane.size());
             if (e == hipSuccess) e = hipMemcpy(r->d_lane, lane.data(), 8 * lane.size(), hipMemcpyHostToDevice);
         }
@@ -458,6 +454,27 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
     ++g->plans;
     reg(r);
     *out = reinterpret_cast<rngx_ragged>(r);
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_fill_ragged_u32_noalloc(rngx_gen h, const uint64_t *offsets, uint64_t n_offsets, uint32_t *d_out,
+                                        void *stream) {
+    Gen *g;
+    if (rngx_status s = check_gen(h, &g)) return s;
+    if (!offsets) return fail(RNGX_E_INVALID, "offsets is NULL");
+    if (is_lfg(g->kind)) return fail(RNGX_E_INVALID, "ragged fills do not take lagged Fibonacci kinds");
+    const uint64_t units = g->kind == RNGX_XS1024W ? g->S / 32 : g->S;
+    if (n_offsets != units + 1)
+        return fail(RNGX_E_INVALID, "need " + std::to_string(units + 1) + " offsets, got " + std::to_string(n_offsets));
+    for (uint64_t u = 0; u < units; ++u)
+        if (offsets[u + 1] < offsets[u]) return fail(RNGX_E_INVALID, "offsets decrease at " + std::to_string(u));
+    uint64_t bytes;
+    if (mul_overflows(offsets[units], 4, &bytes)) return fail(RNGX_E_OVERFLOW, "output size overflows");
+    if (!d_out && offsets[units]) return fail(RNGX_E_INVALID, "output pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(d_out) % 4) return fail(RNGX_E_ALIGN, "output must be 4-byte aligned");
+    DeviceScope ds(g->device);
+    if (rngx_status s = ragged_fill_noalloc(g, offsets, units, d_out, static_cast<hipStream_t>(stream))) return s;
     clear_error();
     return RNGX_OK;
 }

@@ -552,6 +552,15 @@ void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu
     if (plan->slots.back() != items.size()) plan->slots.push_back(static_cast<uint32_t>(items.size()));
 }
 
+void ragged_lane_maps(const Gen *g, std::vector<uint64_t> *lane) {
+    // entry i: the (i+1)-step map (a lane whose first position is i); entry 256: the 256-step advance
+    const uint64_t a = g->kind == RNGX_LCG32 ? kLcg32A : g->kind == RNGX_LCG64 ? kLcg64A : g->sub_a;
+    const uint64_t c = g->kind == RNGX_LCG32 ? kLcg32C : g->kind == RNGX_LCG64 ? kLcg64C : g->sub_c;
+    lane->assign(514, 0);
+    for (int i = 0; i < 256; ++i) affine_power(a, c, i + 1, &(*lane)[2 * i], &(*lane)[2 * i + 1]);
+    affine_power(a, c, 256, &(*lane)[512], &(*lane)[513]);
+}
+
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items) {
     if (ragged_affine(kind)) return 8 * n_items;  // final states
     return kind == RNGX_XS1024W ? 136 * n_items : state_bytes(kind, n_items);

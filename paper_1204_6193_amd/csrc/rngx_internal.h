@@ -184,6 +184,10 @@ uint64_t ragged_chunk(rngx_kind kind);
 bool ragged_affine(rngx_kind kind);  // LCG32/LCG64 and sub-stream forms: one wave per chunk
 void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan);
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items);
+void ragged_lane_maps(const Gen *g, std::vector<uint64_t> *lane);  // affine kinds: lane start and advance maps
+// The one-call ragged fill of rng_fill_ragged_u32_noalloc (noalloc.hip):
+// plans on the host and stages the plan in the device's static scratch.
+rngx_status ragged_fill_noalloc(Gen *g, const uint64_t *offsets, uint64_t units, uint32_t *d_out, hipStream_t st);
 hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st);
 uint64_t stream_fill_chunk(rngx_kind kind);
 hipError_t launch_stream_fill(rngx_kind kind, const uint8_t *st_in, uint8_t *st_out, uint64_t N, int f32,
