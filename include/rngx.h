@@ -408,7 +408,9 @@ rngx_status ising_batch_destroy(rngx_ising_batch b);
  * requests, not on what else is served.  The server allocates its budget
  * once; no request allocates device memory.
  *   (kinds: every kind but the sub-stream LCGs, whose streams only exist as
- *   parts of one S-stream sequence: RNGX_E_INVALID)
+ *   parts of one S-stream sequence, MWC_DIFF, whose multiplier is a
+ *   property of a stream index, and the LFG kinds, whose instances are
+ *   1024 streams: RNGX_E_INVALID)
  *   srv_submit_fill:  the next `count` (<= 2^28) outputs of the (client, kind)
  *     stream, contiguous (XS1024W: the instance's values in warp order), as
  *     uint32 or as FP32 (u >> 8) * 2^-24 if as_f32.  Long requests are cut
@@ -426,7 +428,26 @@ rngx_status ising_batch_destroy(rngx_ising_batch b);
  * srv_wait_any blocks likewise until some request finishes that no
  * srv_wait_any call has returned yet (completion order) and reports it;
  * srv_release returns the output memory to the budget.  srv_destroy waits
- * for the device and frees everything. */
+ * for the device and frees everything.
+ *
+ * Admission: a request that does not fit in the free budget yet is passed
+ * by later requests of other (client, kind) pairs that do fit -- never by a
+ * later request of its own pair, whose stream order it fixes -- until 64
+ * later requests have passed it; from then on nothing is admitted before
+ * it, so a large request cannot be starved.
+ *
+ * srv_cancel withdraws a request that has not been admitted yet (the
+ * ticket becomes unknown, its (client, kind) stream does not advance, an
+ * Ising job's number stays used); RNGX_E_BUSY once it is on the device.
+ *
+ * srv_get_client_state / srv_set_client_state export and import the state
+ * of one (client, kind) stream in the checkpoint image of rng_get_state for
+ * 1 stream (XS1024W: 32), so that a new server (same or other seed) can
+ * continue a client exactly where an old one stopped.  Both are synchronous
+ * and return RNGX_E_BUSY while requests of that (client, kind) are queued or
+ * running; get with host_buf NULL reports the size in *bytes; set refuses an
+ * image of the wrong size or a fixed point (RNGX_E_STATE).  A pair that has
+ * not served yet is seeded first. */
 rngx_status srv_create(const rngx_server_config *cfg, rngx_server *out);
 rngx_status srv_submit_fill(rngx_server s, uint32_t client, rngx_kind kind, uint64_t count, int as_f32,
                             uint64_t *ticket);
@@ -435,6 +456,9 @@ rngx_status srv_submit_ising(rngx_server s, uint32_t client, rngx_kind kind, uin
 rngx_status srv_wait(rngx_server s, uint64_t ticket, double timeout_s, rngx_request_result *res);
 rngx_status srv_wait_any(rngx_server s, double timeout_s, uint64_t *ticket, rngx_request_result *res);
 rngx_status srv_release(rngx_server s, uint64_t ticket);
+rngx_status srv_cancel(rngx_server s, uint64_t ticket);
+rngx_status srv_get_client_state(rngx_server s, uint32_t client, rngx_kind kind, void *host_buf, size_t *bytes);
+rngx_status srv_set_client_state(rngx_server s, uint32_t client, rngx_kind kind, const void *host_buf, size_t bytes);
 rngx_status srv_destroy(rngx_server s);
 
 /* Description of the calling thread's most recent error ("" if none). */

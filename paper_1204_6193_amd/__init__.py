@@ -73,6 +73,9 @@ SIGNATURES = {
     "srv_wait": (_i32, [_vp, _u64, ctypes.c_double, ctypes.c_void_p]),
     "srv_wait_any": (_i32, [_vp, ctypes.c_double, ctypes.POINTER(_u64), ctypes.c_void_p]),
     "srv_release": (_i32, [_vp, _u64]),
+    "srv_cancel": (_i32, [_vp, _u64]),
+    "srv_get_client_state": (_i32, [_vp, ctypes.c_uint32, _i32, _vp, ctypes.POINTER(_sz)]),
+    "srv_set_client_state": (_i32, [_vp, ctypes.c_uint32, _i32, _vp, _sz]),
     "srv_destroy": (_i32, [_vp]),
     "rngx_last_error": (ctypes.c_char_p, []),
 }
@@ -544,6 +547,24 @@ class Server:
 
     def release(self, ticket: int):
         _check(load().srv_release(self.handle, ticket))
+
+    def cancel(self, ticket: int):
+        """Withdraw a request that has not been admitted yet."""
+        _check(load().srv_cancel(self.handle, ticket))
+
+    def get_client_state(self, client: int, kind):
+        """State image (numpy uint8) of the (client, kind) stream."""
+        import numpy as np
+        n = _sz()
+        _check(load().srv_get_client_state(self.handle, client, _kind(kind), None, ctypes.byref(n)))
+        buf = np.zeros(n.value, dtype=np.uint8)
+        _check(load().srv_get_client_state(self.handle, client, _kind(kind), buf.ctypes.data, ctypes.byref(n)))
+        return buf
+
+    def set_client_state(self, client: int, kind, image):
+        import numpy as np
+        buf = np.ascontiguousarray(image, dtype=np.uint8)
+        _check(load().srv_set_client_state(self.handle, client, _kind(kind), buf.ctypes.data, buf.size))
 
     def destroy(self):
         if self.handle:

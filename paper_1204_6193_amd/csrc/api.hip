@@ -1007,6 +1007,51 @@ rngx_status srv_release(rngx_server h, uint64_t ticket) {
     return RNGX_OK;
 }
 
+rngx_status srv_cancel(rngx_server h, uint64_t ticket) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    if (rngx_status st = server_cancel(s, ticket)) return st;
+    clear_error();
+    return RNGX_OK;
+}
+
+static rngx_status check_served_kind(rngx_kind kind) {
+    if (!kind_valid(kind) || is_sub_lcg(kind) || kind == RNGX_MWC_DIFF || is_lfg(kind))
+        return fail(RNGX_E_INVALID, "invalid generator kind (sub-stream LCG, MWC_DIFF and LFG kinds are not served)");
+    return RNGX_OK;
+}
+
+rngx_status srv_get_client_state(rngx_server h, uint32_t client, rngx_kind kind, void *host_buf, size_t *bytes) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    if (rngx_status st = check_served_kind(kind)) return st;
+    if (!bytes) return fail(RNGX_E_INVALID, "bytes is NULL");
+    const size_t need = server_client_state_bytes(kind);
+    if (!host_buf) { *bytes = need; clear_error(); return RNGX_OK; }
+    if (*bytes < need) return fail(RNGX_E_INVALID, "host buffer smaller than the client's state image");
+    DeviceScope ds(server_device(s));
+    if (rngx_status st = server_get_client_state(s, client, kind, host_buf)) return st;
+    *bytes = need;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status srv_set_client_state(rngx_server h, uint32_t client, rngx_kind kind, const void *host_buf, size_t bytes) {
+    Server *s;
+    if (rngx_status st = check_server(h, &s)) return st;
+    if (rngx_status st = check_served_kind(kind)) return st;
+    if (!host_buf) return fail(RNGX_E_INVALID, "host buffer is NULL");
+    const size_t need = server_client_state_bytes(kind);
+    if (bytes != need)
+        return fail(RNGX_E_STATE, "state image has " + std::to_string(bytes) + " bytes, expected " + std::to_string(need));
+    const uint64_t S = kind == RNGX_XS1024W ? 32 : 1;
+    if (rngx_status st = validate_image(kind, S, static_cast<const uint8_t *>(host_buf))) return st;
+    DeviceScope ds(server_device(s));
+    if (rngx_status st = server_set_client_state(s, client, kind, host_buf)) return st;
+    clear_error();
+    return RNGX_OK;
+}
+
 rngx_status srv_destroy(rngx_server h) {
     Server *s;
     if (rngx_status st = check_server(h, &s)) return st;

@@ -152,6 +152,39 @@ struct PhiloxUnitR {
 using PhiloxUnit = PhiloxUnitR<10>;
 using PhiloxUnit7 = PhiloxUnitR<7>;
 
+// Philox in a strip whose streams all stand at the same block boundary at
+// the start of a call (the usual case: seeded at 0, and every call advances
+// every stream by the same multiple of 4).  A sweep takes the four words of
+// one block: the colour-0 pass makes block blk0 + t, uses words 0 and 1 and
+// keeps 2 and 3 for the colour-1 pass, so each block is made once rather
+// than once per pass, and the position, the same for all units, is not held
+// per unit.
+template <int ROUNDS>
+struct PhiloxSweepUnitR {
+    static constexpr int kNB = 4;
+    uint32_t k0, k1, c2, c3;
+    __device__ void load(const uint8_t *st, uint64_t S, uint64_t u) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(st);
+        k0 = p[u]; k1 = p[S + u];
+        c2 = c3 = 0;
+    }
+    __device__ void store_at(uint8_t *st, uint64_t S, uint64_t u, uint64_t pos) const {
+        reinterpret_cast<uint64_t *>(st + 8 * S)[u] = pos;
+    }
+    __device__ void draw_at(uint32_t (&r)[2], uint64_t blk, int c) {
+        if (c == 0) {
+            philox_block<ROUNDS>(k0, k1, blk, r[0], r[1], c2, c3);
+        } else {
+            r[0] = c2;
+            r[1] = c3;
+        }
+    }
+};
+template <class Unit> struct SweepCounter : std::false_type {};  // units that take the block index per pass
+template <int ROUNDS> struct SweepCounter<PhiloxSweepUnitR<ROUNDS>> : std::true_type {};
+template <class Unit> struct PhiloxSweepOf { using type = void; };  // the sweep form of a Philox unit
+template <int ROUNDS> struct PhiloxSweepOf<PhiloxUnitR<ROUNDS>> { using type = PhiloxSweepUnitR<ROUNDS>; };
+
 // XS1024W lane pair u: lane u%16 of instance u/16 of the handle (words 2u,
 // 2u+1 = streams 2u and 2u+1).  Two instance steps per pass; the draws are
 // ordered stream 2u first, stream 2u+1 second, each in step order.
@@ -232,6 +265,7 @@ struct StripArgs {
     uint32_t *err;
     uint32_t hits;              // Metropolis updates per visited site (multi-hit kernels)
     uint32_t R0;                // rows of every strip but the last: strip r starts at row r*R0
+    uint64_t blk0;              // sweep-form Philox units: the common block index at the start
 };
 
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -374,7 +408,8 @@ __device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint32_t 
 // of both streams of the lane pair, steps hits+1..2 hits the second).
 template <class Unit, bool E, bool MH>
 __device__ __forceinline__ uint64_t update_unit(uint8_t *lds, uint32_t pl, uint32_t P, uint32_t up_add, uint32_t dn_add,
-                                                int c, Unit &u, const Accept &A, uint32_t &esum, uint32_t hits) {
+                                                int c, Unit &u, const Accept &A, uint32_t &esum, uint32_t hits,
+                                                uint64_t blk = 0) {
     constexpr int NB = Unit::kNB;
     const uint32_t off = pl & kOffMask;
     const uint32_t sh0 = ((pl >> 31) ^ static_cast<uint32_t>(c)) << 3;  // bit offset of the first colour-c byte
@@ -420,7 +455,8 @@ __device__ __forceinline__ uint64_t update_unit(uint8_t *lds, uint32_t pl, uint3
         }
     }
     uint32_t rr[NB / 2];
-    u.draw(rr);
+    if constexpr (SweepCounter<Unit>::value) u.draw_at(rr, blk, c);
+    else u.draw(rr);
     if constexpr (NB == 4) {
         const uint32_t w = l32[0];
         const uint32_t m2 = mismatch2(w, l32[-1], l32[1], *reinterpret_cast<const uint32_t *>(lds + off - P + up_add),
@@ -601,7 +637,7 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
                 else pl = place[i] + zero;
                 const bool top = bslot && ((pl >> 27) & 1), bot = bslot && ((pl >> 28) & 1);
                 const uint64_t nw = update_unit<Unit, E, MH>(lds, pl, P, top ? up_add : 0u, bot ? dn_add : 0u, c, u[i], A, esum,
-                                                                   a.hits);
+                                                                   a.hits, a.blk0 + sweep);
                 const uint32_t off = pl & kOffMask;
                 const uint32_t yrow = top ? 1 : bot ? R : 0;   // only used for boundary units
                 const uint32_t x0 = off - kPad - yrow * P;
@@ -663,8 +699,23 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
         const uint32_t k = t + i * nt;
-        if (k < a.units) u[i].store(a.st, a.S, ubase + k, 4 * a.n_sweeps * (MH ? a.hits : 1));
+        if (k < a.units) {
+            if constexpr (SweepCounter<Unit>::value) u[i].store_at(a.st, a.S, ubase + k, 4 * (a.blk0 + a.n_sweeps));
+            else u[i].store(a.st, a.S, ubase + k, 4 * a.n_sweeps * (MH ? a.hits : 1));
+        }
     }
+}
+
+// Whether every stream of strip r stands at the same position, a multiple of
+// 4 (Philox): then *blk0 is that position's block.
+__device__ inline bool strip_positions_aligned(const StripArgs &a, uint32_t r, uint64_t *blk0) {
+    const uint64_t ubase = static_cast<uint64_t>(r) * a.R0 * (a.L / 4);
+    const uint64_t *pos = reinterpret_cast<const uint64_t *>(a.st + 8 * a.S) + ubase;
+    const uint64_t p0 = pos[0];
+    int ok = (p0 & 3) == 0;
+    for (uint32_t k = threadIdx.x; k < a.units; k += blockDim.x) ok &= pos[k] == p0;
+    *blk0 = p0 >> 2;
+    return __syncthreads_and(ok) != 0;
 }
 
 // EARLY: the strip's top row lies in slot 0 and its bottom row in slot SPT-1.
@@ -683,6 +734,15 @@ __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
     if (early_slots<SPT>(a.L / Unit::kNB, a.units, blockDim.x) != EARLY) {  // plan and kernel disagree
         if (threadIdx.x == 0) __hip_atomic_fetch_or(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
+    }
+    using Sweep = typename PhiloxSweepOf<Unit>::type;
+    if constexpr (!std::is_void<Sweep>::value && !MH) {
+        static_assert(place_in_lds<Sweep, SPT>() == place_in_lds<Unit, SPT>(), "the two forms share the LDS plan");
+        StripArgs b2 = a;
+        if (strip_positions_aligned(a, r, &b2.blk0)) {
+            strip_body<Sweep, SPT, EARLY, place_in_lds<Sweep, SPT>(), false>(b2, r, lds);
+            return;
+        }
     }
     strip_body<Unit, SPT, EARLY, place_in_lds<Unit, SPT>(), MH>(a, r, lds);
 }

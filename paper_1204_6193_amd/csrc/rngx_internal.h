@@ -117,6 +117,11 @@ rngx_status server_submit_ising(Server *s, uint32_t client, rngx_kind kind, uint
 rngx_status server_wait(Server *s, uint64_t ticket, double timeout_s, rngx_request_result *res);
 rngx_status server_wait_any(Server *s, double timeout_s, uint64_t *ticket, rngx_request_result *res);
 rngx_status server_release(Server *s, uint64_t ticket);
+rngx_status server_cancel(Server *s, uint64_t ticket);
+int server_device(const Server *s);
+size_t server_client_state_bytes(rngx_kind kind);
+rngx_status server_get_client_state(Server *s, uint32_t client, rngx_kind kind, void *host_buf);
+rngx_status server_set_client_state(Server *s, uint32_t client, rngx_kind kind, const void *host_buf);
 void server_destroy(Server *s);
 
 size_t state_bytes(rngx_kind kind, uint64_t S);

@@ -2,7 +2,10 @@
 //
 // Requests (random-number fills and Ising jobs) are submitted from any host
 // thread and stamped on arrival.  A worker thread admits them in arrival
-// order as soon as the device-memory pool and the in-flight limit allow,
+// order as soon as the device-memory pool and the in-flight limit allow (a
+// request that does not fit yet is passed by later ones of other (client,
+// kind) pairs, at most kMaxBypass times, after which admission waits for
+// memory to come back to it),
 // launches their work on one of `slots` HIP streams, and detects completion
 // with events, so requests that arrive while others run are started at once
 // and overlap on the device.  Each (client, kind) keeps a resident generator
@@ -14,6 +17,7 @@
 // one pool allocated at creation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -79,6 +83,8 @@ class Pool {
 
 uint64_t round16(uint64_t x) { return (x + 15) / 16 * 16; }
 
+constexpr uint32_t kMaxBypass = 64;  // later requests that may pass one waiting for memory
+
 }  // namespace
 
 struct ServerRequest {
@@ -96,6 +102,7 @@ struct ServerRequest {
     uint64_t n_values = 0;
     hipEvent_t ev = nullptr;
     int state = 0;  // 0 pending, 1 in flight, 2 done, 3 failed
+    uint32_t bypassed = 0;  // later requests admitted while this one waited for memory
     // Ising job scratch descriptors (point into the pool)
     Gen job_gen{};
     Ising job_lat{};
@@ -119,6 +126,7 @@ struct Server {
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<ServerRequest>> pending;
     std::vector<std::shared_ptr<ServerRequest>> inflight;
+    std::vector<std::shared_ptr<ServerRequest>> launching;  // admitted, being launched (lock released)
     std::unordered_map<uint64_t, std::shared_ptr<ServerRequest>> all;
     std::map<std::pair<uint32_t, int>, ClientGen *> gens;
     const uint64_t *t64[8] = {};  // per-kind jump tables for chunks of stream_fill_chunk(kind)
@@ -247,17 +255,35 @@ void worker_loop(Server *s) {
             progress = true;
         }
         if (progress) s->cv_done.notify_all();
-        // admissions, in arrival order
+        // admissions: the first pending request that fits, in arrival order,
+        // never ahead of an earlier one of its own (client, kind) (its
+        // stream's order) nor past one that has been passed kMaxBypass times
         while (!s->pending.empty() && s->inflight.size() < s->cfg.max_inflight) {
-            auto r = s->pending.front();
-            const uint64_t off = s->pool.alloc(r->bytes);
-            if (off == UINT64_MAX) break;  // wait for memory to come back
-            r->pool_off = off;
-            s->pending.pop_front();
+            std::shared_ptr<ServerRequest> r;
+            std::vector<std::pair<uint32_t, int>> blocked;
+            for (size_t i = 0; i < s->pending.size(); ++i) {
+                auto &c = s->pending[i];
+                const auto key = std::make_pair(c->client, static_cast<int>(c->kind));
+                if (std::find(blocked.begin(), blocked.end(), key) != blocked.end()) continue;
+                const uint64_t off = s->pool.alloc(c->bytes);
+                if (off == UINT64_MAX) {
+                    if (c->bypassed >= kMaxBypass) break;  // its turn: wait for memory
+                    blocked.push_back(key);
+                    continue;
+                }
+                c->pool_off = off;
+                r = c;
+                for (size_t j = 0; j < i; ++j) ++s->pending[j]->bypassed;
+                s->pending.erase(s->pending.begin() + static_cast<std::ptrdiff_t>(i));
+                break;
+            }
+            if (!r) break;  // nothing fits: wait for memory to come back
             ClientGen *g = r->type == 0 ? client_gen(s, r->client, r->kind, stream_for(s, r->client, r->kind)) : nullptr;
+            s->launching.push_back(r);
             lk.unlock();  // launches can take a while (an Ising job is many kernels)
             const bool ok = (r->type != 0 || g) && launch_request(s, *r, g);
             lk.lock();
+            s->launching.erase(std::find(s->launching.begin(), s->launching.end(), r));
             if (ok) {
                 r->state = 1;
                 s->inflight.push_back(r);
@@ -433,6 +459,58 @@ rngx_status server_release(Server *s, uint64_t ticket) {
         s->all.erase(it);
     }
     s->cv_work.notify_one();
+    return RNGX_OK;
+}
+
+int server_device(const Server *s) { return s->device; }
+
+rngx_status server_cancel(Server *s, uint64_t ticket) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(RNGX_E_INVALID, "unknown or released ticket");
+    if (it->second->state != 0) return fail(RNGX_E_BUSY, "the request was already admitted");
+    for (auto p = s->pending.begin(); p != s->pending.end(); ++p)
+        if ((*p)->ticket == ticket) { s->pending.erase(p); break; }
+    s->all.erase(it);
+    return RNGX_OK;
+}
+
+namespace {
+// No request of (client, kind) pending or on the device.  Caller holds mu.
+bool idle(const Server *s, uint32_t client, rngx_kind kind) {
+    for (const auto &r : s->pending)
+        if (r->client == client && r->kind == kind) return false;
+    for (const auto &r : s->inflight)
+        if (r->client == client && r->kind == kind) return false;
+    for (const auto &r : s->launching)
+        if (r->client == client && r->kind == kind) return false;
+    return true;
+}
+}  // namespace
+
+size_t server_client_state_bytes(rngx_kind kind) { return state_bytes(kind, unit_streams(kind)); }
+
+rngx_status server_get_client_state(Server *s, uint32_t client, rngx_kind kind, void *host_buf) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!idle(s, client, kind)) return fail(RNGX_E_BUSY, "requests of this client and kind are still queued or running");
+    const hipStream_t st = stream_for(s, client, kind);
+    ClientGen *c = client_gen(s, client, kind, st);  // seeds it if it has not served yet
+    if (!c) return fail(RNGX_E_NOMEM, "no memory for the client's generator");
+    hipError_t e = hipMemcpyAsync(host_buf, c->buf[c->cur], server_client_state_bytes(kind), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "client state copy to host");
+    return RNGX_OK;
+}
+
+rngx_status server_set_client_state(Server *s, uint32_t client, rngx_kind kind, const void *host_buf) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!idle(s, client, kind)) return fail(RNGX_E_BUSY, "requests of this client and kind are still queued or running");
+    const hipStream_t st = stream_for(s, client, kind);
+    ClientGen *c = client_gen(s, client, kind, st);
+    if (!c) return fail(RNGX_E_NOMEM, "no memory for the client's generator");
+    hipError_t e = hipMemcpyAsync(c->buf[c->cur], host_buf, server_client_state_bytes(kind), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "client state copy to device");
     return RNGX_OK;
 }
 

@@ -466,3 +466,36 @@ def test_substream_lcg32_fails_the_ising_test(rngx):
               f"C={c:.5f}+-{sc:.5f} z={z[kind][1]:+.1f}", flush=True)
     assert abs(z["lcg32_sub"][0]) > 20
     assert abs(z["lcg32"][0]) < 4 and abs(z["lcg32"][1]) < 4
+
+
+@pytest.mark.parametrize("kind", ["philox4x32_10", "philox4x32_7"])
+def test_philox_strips_with_uneven_positions(rngx, orc, kind):
+    """The strip kernel makes each Philox block once per sweep when all
+    streams of a strip stand at one block boundary, and falls back to the
+    per-stream form otherwise: positions that are equal but not a multiple of
+    4, positions that differ in the lower half of the lattice only (its
+    strips take the fallback, the others the sweep form), and all equal
+    again -- bit-exact with the oracle every time."""
+    L = 512
+    print(f"case philox positions {kind}", flush=True)
+    lat = rngx.ising_create(L, kind, 4)
+    assert rngx.ising_info(lat)["strips"] > 1
+    g = rngx.ising_rng(lat)
+    sp, st = orc.ising_create(L, kind, 4)
+    S = L * L // 4
+    rngx.rng_skip(g, 1)  # every stream at position 1
+    orc.jump(kind, S, st, 1)
+    pos = st[8 * S:].view(np.uint64)
+    for rep in range(3):
+        if rep == 1:  # uneven in the lower half
+            pos[S // 2:] += np.arange(S - S // 2, dtype=np.uint64) % np.uint64(7)
+            rngx.rng_set_state(g, st)
+        if rep == 2:
+            pos[:] = np.uint64(4 * 1000)  # even and aligned again
+            rngx.rng_set_state(g, st)
+        tr = torch.zeros(3, dtype=torch.int32, device="cuda")
+        rngx.ising_sweep(lat, 0.42, 3, tr)
+        want = orc.ising_sweeps(L, kind, 0.42, st, sp, 3)
+        assert np.array_equal(tr.cpu().numpy(), want), rep
+        assert np.array_equal(rngx.ising_get_spins(lat).ravel(), sp), rep
+        assert np.array_equal(rngx.rng_get_state(g), st), rep

@@ -125,3 +125,126 @@ def test_server_wait_any_reports_each_request_once(rngx):
         srv.wait_any(0.01)
     assert e.value.status == -7
     srv.destroy()
+
+
+def _oracle_client_values(orc, rngx, kind, client, start, n, seed=SEED):
+    """Values start .. start+n-1 of the (client, kind) stream from the oracle:
+    stream 0 (XS1024W: instance 0, warp order) of the client seed, reached by
+    the oracle's jump-ahead."""
+    width = _unit(kind)
+    st = orc.seed(kind, width, orc.splitmix(seed, 16 * client + rngx.KINDS[kind]))
+    first = start // width
+    if first:
+        orc.jump(kind, width, st, first)
+    steps = -(-(start + n) // width) - first
+    vals = orc.generate(kind, width, st, steps).ravel()
+    return vals[start - first * width: start - first * width + n]
+
+
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7"])
+def test_served_fill_near_the_maximum_matches_the_oracle(rngx, orc, kind):
+    """A served fill of 2^28 - 5 values (the largest size, every chunk
+    jump of the stream fill), then a second one that continues the stream:
+    sampled ranges -- the start, the middle, the last chunk -- equal the
+    oracle's stream of the client seed; the second request starts where the
+    first ended; both as uint32, the second also as FP32."""
+    client, n = 11, (1 << 28) - 5
+    print(f"case served 2^28 {kind}", flush=True)
+    srv = rngx.Server(slots=2, max_inflight=2, memory_budget=(1 << 30) + (64 << 20), seed=SEED)
+    t = srv.submit_fill(client, kind, n, False)
+    r = srv.wait(t, 120.0)
+    assert r.status == 0 and r.n_values == n
+    for lo in (0, n // 2 - 1000, n - 5000):
+        got = rngx.copy_to_host(r.d_output + 4 * lo, 4 * 5000, "uint32")
+        want = _oracle_client_values(orc, rngx, kind, client, lo, 5000)
+        assert np.array_equal(got, want), (kind, lo)
+    srv.release(t)
+    t = srv.submit_fill(client, kind, 3001, True)
+    r = srv.wait(t, 60.0)
+    got = rngx.copy_to_host(r.d_output, 4 * 3001, "float32")
+    want = _oracle_client_values(orc, rngx, kind, client, n, 3001)
+    assert np.array_equal(got.view(np.uint32), ((want >> 8).astype(np.float32) * np.float32(2.0 ** -24)).view(np.uint32))
+    srv.release(t)
+    srv.destroy()
+
+
+def test_server_cancel(rngx, orc):
+    """A request that waits for memory can be withdrawn: its ticket is gone
+    and its (client, kind) stream does not advance."""
+    srv = rngx.Server(slots=1, max_inflight=4, memory_budget=24 << 20, seed=SEED)
+    hold = srv.submit_fill(1, "lcg32", 4 << 20)  # 16 MiB, kept unreleased
+    assert srv.wait(hold, 30.0).status == 0
+    blocked = srv.submit_fill(2, "lcg64", 4 << 20)  # cannot fit beside it
+    with pytest.raises(rngx.RngxError) as e:
+        srv.wait(blocked, 0.2)
+    assert e.value.status == -7
+    srv.cancel(blocked)
+    with pytest.raises(rngx.RngxError):
+        srv.wait(blocked, 0.0)
+    srv.release(hold)
+    t = srv.submit_fill(2, "lcg64", 1000)
+    r = srv.wait(t, 30.0)
+    got = rngx.copy_to_host(r.d_output, 4000, "uint32")
+    assert np.array_equal(got, _oracle_client_values(orc, rngx, "lcg64", 2, 0, 1000))
+    srv.release(t)
+    with pytest.raises(rngx.RngxError) as e:
+        srv.cancel(t)  # released: unknown
+    assert e.value.status == -1
+    srv.destroy()
+
+
+def test_server_kill_and_restore(rngx):
+    """Client states exported from a server, which is then destroyed, and
+    imported into a new server with another seed: the clients continue
+    exactly as on a server that served all their requests."""
+    reqs = [(3, "xs1024w", 7000), (3, "philox4x32_10", 4001), (8, "mwc", 999), (8, "xorwow", 5000)]
+    ref = rngx.Server(slots=2, max_inflight=4, memory_budget=64 << 20, seed=SEED)
+    a = rngx.Server(slots=2, max_inflight=4, memory_budget=64 << 20, seed=SEED)
+    for srv in (ref, a):
+        for c, k, n in reqs:
+            t = srv.submit_fill(c, k, n)
+            assert srv.wait(t, 30.0).status == 0
+            srv.release(t)
+    images = {(c, k): a.get_client_state(c, k) for c, k, _ in reqs}
+    a.destroy()
+    b = rngx.Server(slots=3, max_inflight=4, memory_budget=64 << 20, seed=SEED + 1)
+    for (c, k), img in images.items():
+        b.set_client_state(c, k, img)
+    for c, k, n in reqs:
+        outs = []
+        for srv in (ref, b):
+            t = srv.submit_fill(c, k, n + 13, True)
+            r = srv.wait(t, 30.0)
+            outs.append(rngx.copy_to_host(r.d_output, 4 * (n + 13)))
+            srv.release(t)
+        assert np.array_equal(outs[0], outs[1]), (c, k)
+    with pytest.raises(rngx.RngxError) as e:
+        b.set_client_state(3, "xs1024w", np.zeros(8, dtype=np.uint8))  # wrong size
+    assert e.value.status == -6
+    ref.destroy()
+    b.destroy()
+
+
+def test_server_small_requests_pass_a_blocked_one(rngx, orc):
+    """A request that waits for memory does not hold back later small ones
+    of other clients, but does hold back later ones of its own (client,
+    kind), whose values must follow its own."""
+    srv = rngx.Server(slots=4, max_inflight=8, memory_budget=40 << 20, seed=SEED)
+    hold = srv.submit_fill(1, "lcg32", 6 << 20)  # 24 MiB, kept
+    assert srv.wait(hold, 30.0).status == 0
+    big = srv.submit_fill(2, "xorwow", 4 << 20)  # 16 MiB: does not fit yet
+    same = srv.submit_fill(2, "xorwow", 1000)    # same pair: must wait behind it
+    small = [srv.submit_fill(c, "lcg64", 2000) for c in (3, 4, 5)]
+    for t in small:  # admitted while `big` waits
+        assert srv.wait(t, 30.0).status == 0
+        srv.release(t)
+    with pytest.raises(rngx.RngxError):
+        srv.wait(same, 0.2)
+    srv.release(hold)
+    rb = srv.wait(big, 30.0)
+    rs = srv.wait(same, 30.0)
+    got = rngx.copy_to_host(rs.d_output, 4000, "uint32")
+    assert np.array_equal(got, _oracle_client_values(orc, rngx, "xorwow", 2, 4 << 20, 1000))
+    srv.release(big)
+    srv.release(same)
+    srv.destroy()
