@@ -146,48 +146,6 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
     }
 }
 
-// Pacing of a fill's workgroups in bands of kBand rows (see k_fill_xs).
-// before(b): wait (bounded) until every workgroup has finished band
-// b - kSlack; after(b): count this workgroup's band b.  A workgroup whose wait
-// times out stops waiting for the rest of the launch but keeps counting.
-// Every thread of the workgroup must call both (they contain barriers).
-struct Pacer {
-    uint32_t *ring;  // null: not paced (before() and after() do nothing)
-    bool waiting;    // false once a wait timed out, and always without a ring
-    __device__ explicit Pacer(uint32_t *r) : ring(r), waiting(r != nullptr) {}
-    __device__ void before(uint64_t band, uint32_t *s_free) {
-        if (!ring || !waiting || band < kSlack) return;
-        const uint32_t nblk = gridDim.x;
-        if (threadIdx.x < 64) {
-            const uint64_t prev = band - kSlack;
-            const uint32_t *e = ring + (prev % kRing) * kPaceSlots;
-            const uint32_t use = static_cast<uint32_t>(prev / kRing) + 1;
-            uint32_t it = 0;
-            for (; it < kPollLimit; ++it) {
-                bool ok = true;
-#pragma unroll
-                for (uint32_t m = 0; m < kPaceSlots / 64; ++m) {
-                    const uint32_t j = m * 64 + threadIdx.x;
-                    const uint32_t want = (nblk / kPaceSlots + (j < nblk % kPaceSlots ? 1u : 0u)) * use;
-                    ok &= __hip_atomic_load(e + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
-                }
-                if (__all(ok)) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
-            if (threadIdx.x == 0) *s_free = it == kPollLimit;
-        }
-        __syncthreads();
-        if (*s_free) waiting = false;
-    }
-    __device__ void after(uint64_t band) {
-        if (!ring) return;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(ring + (band % kRing) * kPaceSlots + blockIdx.x % kPaceSlots, 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    }
-};
-
 // Small-state kinds, paced: V consecutive streams per thread, BLK threads
 // per workgroup (S % V == 0; threads past the last stream stay in the loop
 // with their stores masked, since they take part in the barriers).
@@ -306,7 +264,7 @@ constexpr rngx_fill_config kSmallConfigs[] = {{1, 4, 512}, {1, 4, 1024}, {1, 4, 
 constexpr rngx_fill_config kXsConfigs[] = {{1, 2, 1024}, {1, 2, 512}, {0, 2, 1024}, {0, 2, 256}};
 // Lagged Fibonacci kinds: one wave per 1024-stream instance (16 streams per
 // lane), four waves per workgroup, free-running.
-constexpr rngx_fill_config kLfgConfigs[] = {{0, 16, 256}};
+constexpr rngx_fill_config kLfgConfigs[] = {{1, 16, 256}, {0, 16, 256}};
 constexpr int kNumSmall = sizeof(kSmallConfigs) / sizeof(kSmallConfigs[0]);
 constexpr int kNumXs = sizeof(kXsConfigs) / sizeof(kXsConfigs[0]);
 static_assert(kNumSmall <= kMaxFillConfigs && kNumXs <= kMaxFillConfigs, "Gen::resident too small");
@@ -459,6 +417,11 @@ hipError_t launch_seed(Gen *g, uint64_t seed, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_clear_ring(Gen *g, hipStream_t st) {
+    clear_ring(g, st);
+    return hipGetLastError();
+}
+
 hipError_t fill_setup(Gen *g, int n_cu) {
     g->d_ring = nullptr;
     g->n_cu = n_cu;
@@ -468,7 +431,7 @@ hipError_t fill_setup(Gen *g, int n_cu) {
 }
 
 int fill_configs(rngx_kind kind, const rngx_fill_config **list) {
-    if (is_lfg(kind)) { *list = kLfgConfigs; return 1; }
+    if (is_lfg(kind)) { *list = kLfgConfigs; return 2; }
     *list = kind == RNGX_XS1024W ? kXsConfigs : kSmallConfigs;
     return kind == RNGX_XS1024W ? kNumXs : kNumSmall;
 }

@@ -14,6 +14,7 @@
 // instances), runs of 64 V values (V per lane), wave-synchronous with no
 // barrier.  Seeding and jump-ahead are plain per-instance kernels.  The
 // Ising consumer is in ising.hip.
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -45,55 +46,68 @@ struct LfgFill {
 };
 
 // `count` rows (1024 values) of every instance; MODE as the other fills.
+// With a ring the workgroups are paced in bands of kBand rows like the other
+// fills (Pacer); waves past the last instance stay for the barriers.
 template <int R, int SL, int MODE>
-__global__ __launch_bounds__(64 * kWaves) void k_fill_lfg(uint8_t *st, uint64_t S, uint64_t count, void *out) {
+__global__ __launch_bounds__(64 * kWaves) void k_fill_lfg(uint8_t *st, uint64_t S, uint64_t count, void *out,
+                                                         uint32_t *ring) {
     using F = LfgFill<R, SL>;
     constexpr int V = F::V, P = F::P, B = F::B, RUNS = 1024 / P;
     __shared__ uint32_t rings[kWaves][B];
+    __shared__ uint32_t s_free;
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * kWaves + w;
     const uint64_t G = S / 1024;
-    if (g >= G) return;  // whole waves only
-    uint32_t *ring = rings[w];
-    uint32_t *X = reinterpret_cast<uint32_t *>(st) + g * R;
-    for (int j = lane; j < R; j += 64) ring[B - R + j] = X[j];  // x_{j-r} at (j - r) mod B
+    const bool live = g < G;
+    if (!ring && !live) return;  // whole waves; without pacing there are no barriers
+    uint32_t *rg = rings[w];
+    uint32_t *X = reinterpret_cast<uint32_t *>(st) + (live ? g : 0) * R;
+    if (live)
+        for (int j = lane; j < R; j += 64) rg[B - R + j] = X[j];  // x_{j-r} at (j - r) mod B
     wave_lds_sync();
     uint32_t acc[RUNS * V];
 #pragma unroll
     for (int i = 0; i < RUNS * V; ++i) acc[i] = 0;
     uint32_t q = 0;  // value index modulo 2^32 (only q mod B is used)
-    for (uint64_t k = 0; k < count; ++k) {
+    Pacer pc(ring);
+    for (uint64_t k0 = 0, band = 0; k0 < count; k0 += kBand, ++band) {
+        pc.before(band, &s_free);
+        const uint64_t k1 = k0 + kBand < count ? k0 + kBand : count;
+        for (uint64_t k = k0; k < k1; ++k) {
 #pragma unroll
-        for (int f = 0; f < RUNS; ++f) {
-            uint32_t v[V];
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                const uint32_t qq = q + 64 * j + lane;
-                v[j] = ring[(qq - R) & (B - 1)] + ring[(qq - SL) & (B - 1)];
-            }
-#pragma unroll
-            for (int j = 0; j < V; ++j) ring[(q + 64 * j + lane) & (B - 1)] = v[j];
-            if constexpr (MODE == kOutXor) {
-#pragma unroll
-                for (int j = 0; j < V; ++j) acc[f * V + j] ^= v[j];
-            } else {
-                uint32_t *o = static_cast<uint32_t *>(out) + k * S + g * 1024 + f * P + lane;
+            for (int f = 0; f < RUNS; ++f) {
+                uint32_t v[V];
 #pragma unroll
                 for (int j = 0; j < V; ++j) {
-                    const uint32_t word = MODE == kOutU32 ? v[j] : __float_as_uint(to_unit_lfg(v[j]));
-                    __builtin_nontemporal_store(word, o + 64 * j);
+                    const uint32_t qq = q + 64 * j + lane;
+                    v[j] = rg[(qq - R) & (B - 1)] + rg[(qq - SL) & (B - 1)];
                 }
+#pragma unroll
+                for (int j = 0; j < V; ++j) rg[(q + 64 * j + lane) & (B - 1)] = v[j];
+                if constexpr (MODE == kOutXor) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) acc[f * V + j] ^= v[j];
+                } else if (live) {
+                    uint32_t *o = static_cast<uint32_t *>(out) + k * S + g * 1024 + f * P + lane;
+#pragma unroll
+                    for (int j = 0; j < V; ++j) {
+                        const uint32_t word = MODE == kOutU32 ? v[j] : __float_as_uint(to_unit_lfg(v[j]));
+                        __builtin_nontemporal_store(word, o + 64 * j);
+                    }
+                }
+                q += P;
+                wave_lds_sync();
             }
-            q += P;
-            wave_lds_sync();
         }
+        pc.after(band);
     }
+    if (!live) return;
     if constexpr (MODE == kOutXor) {
         uint32_t *o = static_cast<uint32_t *>(out) + g * 1024 + lane;
 #pragma unroll
         for (int i = 0; i < RUNS * V; ++i) o[64 * i] = acc[i];  // stream lane f P + 64 j + lane
     }
-    for (int j = lane; j < R; j += 64) X[j] = ring[(q - R + j) & (B - 1)];
+    for (int j = lane; j < R; j += 64) X[j] = rg[(q - R + j) & (B - 1)];
 }
 
 // Seeding: word j of instance g from SM(1 + H g + j/2), H = (r + 1)/2.
@@ -197,9 +211,25 @@ template <int R, int SL>
 hipError_t fill_lfg(Gen *g, void *out, uint64_t count, int mode, hipStream_t st) {
     const unsigned blocks = static_cast<unsigned>((g->S / 1024 + kWaves - 1) / kWaves);
     const dim3 block(64 * kWaves);
-    if (mode == kOutU32) hipLaunchKernelGGL((k_fill_lfg<R, SL, kOutU32>), dim3(blocks), block, 0, st, g->d_state, g->S, count, out);
-    else if (mode == kOutF32) hipLaunchKernelGGL((k_fill_lfg<R, SL, kOutF32>), dim3(blocks), block, 0, st, g->d_state, g->S, count, out);
-    else hipLaunchKernelGGL((k_fill_lfg<R, SL, kOutXor>), dim3(blocks), block, 0, st, g->d_state, g->S, count, out);
+    // paced (the default configuration) when large enough and every
+    // workgroup fits on the device at once
+    uint32_t *ring = nullptr;
+    if (mode != kOutXor && g->fill_cfg <= 0 && g->d_ring && count >= 4 * kBand && blocks >= 128) {
+        int occ = 0;
+        const void *fn = mode == kOutU32 ? reinterpret_cast<const void *>(&k_fill_lfg<R, SL, kOutU32>)
+                                         : reinterpret_cast<const void *>(&k_fill_lfg<R, SL, kOutF32>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 64 * kWaves, 0) == hipSuccess &&
+            static_cast<uint64_t>(occ) * std::max(g->n_cu, 0) >= blocks)
+            ring = g->d_ring;
+        (void)hipGetLastError();
+    }
+    if (ring) {
+        const hipError_t e = launch_clear_ring(g, st);
+        if (e != hipSuccess) return e;
+    }
+    if (mode == kOutU32) hipLaunchKernelGGL((k_fill_lfg<R, SL, kOutU32>), dim3(blocks), block, 0, st, g->d_state, g->S, count, out, ring);
+    else if (mode == kOutF32) hipLaunchKernelGGL((k_fill_lfg<R, SL, kOutF32>), dim3(blocks), block, 0, st, g->d_state, g->S, count, out, ring);
+    else hipLaunchKernelGGL((k_fill_lfg<R, SL, kOutXor>), dim3(blocks), block, 0, st, g->d_state, g->S, count, out, static_cast<uint32_t *>(nullptr));
     return hipGetLastError();
 }
 

@@ -32,6 +32,49 @@ constexpr uint32_t kPollLimit = 4096; // polls before a workgroup stops waiting
 
 enum { kOutU32 = 0, kOutF32 = 1, kOutXor = 2 };
 
+// Pacing of a fill's workgroups in bands of kBand rows (see k_fill_xs).
+// before(b): wait (bounded) until every workgroup has finished band
+// b - kSlack; after(b): count this workgroup's band b.  A workgroup whose wait
+// times out stops waiting for the rest of the launch but keeps counting.
+// Every thread of the workgroup must call both (they contain barriers).
+struct Pacer {
+    uint32_t *ring;  // null: not paced (before() and after() do nothing)
+    bool waiting;    // false once a wait timed out, and always without a ring
+    __device__ explicit Pacer(uint32_t *r) : ring(r), waiting(r != nullptr) {}
+    __device__ void before(uint64_t band, uint32_t *s_free) {
+        if (!ring || !waiting || band < kSlack) return;
+        const uint32_t nblk = gridDim.x;
+        if (threadIdx.x < 64) {
+            const uint64_t prev = band - kSlack;
+            const uint32_t *e = ring + (prev % kRing) * kPaceSlots;
+            const uint32_t use = static_cast<uint32_t>(prev / kRing) + 1;
+            uint32_t it = 0;
+            for (; it < kPollLimit; ++it) {
+                bool ok = true;
+#pragma unroll
+                for (uint32_t m = 0; m < kPaceSlots / 64; ++m) {
+                    const uint32_t j = m * 64 + threadIdx.x;
+                    const uint32_t want = (nblk / kPaceSlots + (j < nblk % kPaceSlots ? 1u : 0u)) * use;
+                    ok &= __hip_atomic_load(e + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want;
+                }
+                if (__all(ok)) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (threadIdx.x == 0) *s_free = it == kPollLimit;
+        }
+        __syncthreads();
+        if (*s_free) waiting = false;
+    }
+    __device__ void after(uint64_t band) {
+        if (!ring) return;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(ring + (band % kRing) * kPaceSlots + blockIdx.x % kPaceSlots, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+
 // ---------------------------------------------------------------------------
 // Device-side helpers.
 __host__ __device__ inline uint64_t mix64(uint64_t z) {

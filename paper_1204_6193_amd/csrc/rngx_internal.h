@@ -138,6 +138,7 @@ hipError_t fill_setup(Gen *g, int n_cu);  // pacing counters, default configurat
 int fill_configs(rngx_kind kind, const rngx_fill_config **list);  // autotuner candidates of a kind
 int fill_default(rngx_kind kind);
 hipError_t launch_fill(Gen *g, void *d_out, uint64_t count, int mode, hipStream_t st);
+hipError_t launch_clear_ring(Gen *g, hipStream_t st);  // zero the pacing counters before a paced launch
 hipError_t launch_skip(Gen *g, uint64_t n, hipStream_t st);
 hipError_t launch_substreams(Gen *g, hipStream_t st);  // XS1024W: instance g skips g 2^137 steps (synchronous)
 // MWC_DIFF: the first n multipliers (found on the device once per process)
