@@ -92,8 +92,8 @@ def test_fill_configuration_lists(rngx):
     assert len(small) == 7 and small[0] == (1, 4, 512) and (0, 4, 256) in small
     for kind in ("lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7", "lcg32_sub", "lcg64_sub", "mwc_diff"):
         assert rngx.rng_fill_configs(kind) == small
-    for kind in ("lfg521", "lfg1279"):  # one wave per 1024-stream instance
-        assert rngx.rng_fill_configs(kind) == [(0, 16, 256)]
+    for kind in ("lfg521", "lfg1279"):  # one wave per 1024-stream instance, paced or not
+        assert rngx.rng_fill_configs(kind) == [(1, 16, 256), (0, 16, 256)]
     xs = rngx.rng_fill_configs("xs1024w")
     assert len(xs) == 4 and all(v == 2 for _, v, _ in xs) and xs[0] == (1, 2, 1024)
     for paced, v, block in small + xs:
