@@ -377,8 +377,12 @@ def main():
                     help="for rocprofv3: the headline fill `steps` times, then a plain 4 GiB device-to-device "
                          "copy `steps` times as the reference for scaling HBM byte counters; prints no JSON")
     ap.add_argument("--profile-ising", action="store_true",
-                    help="for rocprofv3: `steps` XS1024W Ising calls of 200 sweeps each at L=4096, beta=0.4 "
-                         "(energy trace on); prints no JSON")
+                    help="for rocprofv3: `steps` Ising calls of 200 sweeps each at L=4096, beta=0.4 "
+                         "(energy trace on) of --profile-kind (default xs1024w); prints no JSON")
+    ap.add_argument("--profile-fill", action="store_true",
+                    help="for rocprofv3: `steps` u32 fills of 2^20 x 4096 of --profile-kind, then `steps` "
+                         "consume calls of the same size; prints no JSON")
+    ap.add_argument("--profile-kind", default="xs1024w")
     ap.add_argument("--profile-batch", action="store_true",
                     help="for rocprofv3: `steps` runs of the 512-replica XS1024W batch (L in 16..1024, "
                          "numpy default_rng(1)) at 1000 sweeps each; prints no JSON")
@@ -395,8 +399,21 @@ def main():
     import paper_1204_6193_amd as rx
     rx.load()
     torch.cuda.set_device(0)
+    if args.profile_fill:
+        kind = args.profile_kind
+        g = rx.rng_create(kind, S_FULL, 1)
+        out = torch.empty(S_FULL * COUNT_FULL, dtype=torch.int32, device="cuda")
+        for _ in range(args.steps):
+            rx.rng_fill_u32(g, out, COUNT_FULL)
+        acc = torch.empty(S_FULL, dtype=torch.int32, device="cuda")
+        for _ in range(args.steps):
+            rx.rng_consume(g, acc, COUNT_FULL)
+        torch.cuda.synchronize()
+        g.destroy()
+        print(f"profile pass done: {args.steps} fills and consumes of {S_FULL}x{COUNT_FULL}, {kind}", flush=True)
+        return
     if args.profile_ising:
-        lat = rx.ising_create(4096, "xs1024w", 1)
+        lat = rx.ising_create(4096, args.profile_kind, 1)
         tr = torch.zeros(200, dtype=torch.int32, device="cuda")
         for _ in range(args.steps):
             rx.ising_sweep(lat, 0.4, 200, tr)
@@ -406,7 +423,7 @@ def main():
         lat.destroy()
         del tr
         torch.cuda.synchronize()
-        print(f"profile pass done: {args.steps} calls of 200 sweeps at L=4096", flush=True)
+        print(f"profile pass done: {args.steps} calls of 200 sweeps at L=4096, {args.profile_kind}", flush=True)
         return
     if args.profile_ragged:
         import numpy as np
