@@ -429,7 +429,7 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
     hipError_t e = hipSuccess;
     if (!items.empty()) {
         e = hipMalloc(&r->d_items, sizeof(RaggedItem) * items.size());
-        if (e == hipSuccess && ragged_affine(g->kind)) {
+        if (e == hipSuccess && ragged_lane_table(g->kind)) {
             std::vector<uint64_t> lane;
             ragged_lane_maps(g, &lane);
             e = hipMalloc(&r->d_lane, 8 * lane.size());

@@ -70,7 +70,7 @@ rngx_status ragged_fill_noalloc(Gen *g, const uint64_t *offsets, uint64_t units,
     std::vector<uint64_t> t64, lane;
     std::vector<uint32_t> t32;
     jump_table_gen(g, plan.step, plan.max_j + 1, &t64, &t32);
-    if (ragged_affine(g->kind)) ragged_lane_maps(g, &lane);
+    if (ragged_lane_table(g->kind)) ragged_lane_maps(g, &lane);
     // layout: items | chunk states | t64 | t32 | lane maps | slots
     const size_t b_items = up(sizeof(RaggedItem) * items.size());
     const size_t b_state = up(ragged_scratch_bytes(g->kind, items.size()));

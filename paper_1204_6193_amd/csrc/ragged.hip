@@ -165,6 +165,154 @@ __global__ __launch_bounds__(kBlock) void k_ragged_affine(const RaggedItem *item
     for (; k < kend; ++k) checked(k);
 }
 
+// MWC and MWC_DIFF the same way: the MWC is y -> a y mod p (y = carry 2^32 +
+// x, p = a 2^32 - 1), so a lane's first state is a^(pf+1) times the chunk's
+// start state, the next three come by plain MWC steps and a store advances
+// the lane by a^256.  MWC: the powers of its one a are in lane_maps (a^(i+1)
+// mod p, i < 256, then a^256) and the chunk starts in t64 (a^(j C));
+// MWC_DIFF: each chunk computes its stream's powers with Montgomery
+// arithmetic (a product by a power kept in Montgomery form returns a plain
+// residue).
+template <bool DIFF>
+__global__ __launch_bounds__(kBlock) void k_ragged_mwc(const RaggedItem *items, uint64_t n_items, const uint64_t *t64,
+                                                        const uint64_t *lane_maps, const uint8_t *st, uint64_t S,
+                                                        uint64_t chunk, uint64_t *scratch, uint32_t *out) {
+    const uint64_t q = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    if (q >= n_items) return;  // whole waves
+    const RaggedItem it = items[q];
+    const uint64_t y0 = reinterpret_cast<const uint64_t *>(st)[it.unit];
+    const uint32_t a = DIFF ? reinterpret_cast<const uint32_t *>(st + 8 * S)[it.unit] : static_cast<uint32_t>(kMwcA);
+    const uint32_t mis = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out) >> 2) + it.out) & (kAffSpan - 1);
+    const uint32_t pf = 4 * lane >= mis ? 4 * lane - mis : kAffSpan + 4 * lane - mis;
+    uint64_t yc, x, a_span_m = 0;
+    const Mont64 M(DIFF ? (static_cast<uint64_t>(a) << 32) - 1 : 3);  // (unused for MWC)
+    if constexpr (DIFF) {
+        yc = it.j ? mwc_jump_mod(y0, a, it.j * chunk) : y0;
+        const uint64_t am = M.to(a);
+        x = M.mul(yc, M.pow(am, pf + 1));
+        a_span_m = M.pow(am, kAffSpan);
+    } else {
+        yc = mwc_mulmod(y0, t64[it.j]);
+        x = mwc_mulmod(yc, lane_maps[pf]);
+    }
+    auto step = [=](uint64_t y) { return static_cast<uint64_t>(a) * static_cast<uint32_t>(y) + (y >> 32); };
+    auto advance = [&](uint64_t y) { return DIFF ? M.mul(y, a_span_m) : mwc_mulmod(y, lane_maps[kAffSpan]); };
+    const uint64_t s0 = step(yc);  // state of position 0
+    const int64_t len = it.len;
+    const uint32_t kend = static_cast<uint32_t>((len + mis + kAffSpan - 1) / kAffSpan);
+    const uint32_t kb = mis ? 1u : 0u;
+    const uint32_t kw = static_cast<uint32_t>((len + mis) / kAffSpan);
+    const uint32_t kl = kend ? (kw < kend - 1 ? kw : kend - 1) : 0u;
+    const uint32_t body_end = kl > kb ? kl : kb;
+    uint32_t *o = out + (it.out - mis) + 4 * lane;
+    auto checked = [&](uint32_t k) {
+        const int64_t b = static_cast<int64_t>(kAffSpan) * k + 4 * lane - mis;
+        uint64_t y = b >= 0 ? x : s0;
+        for (int j = 0; j < 4; ++j) {
+            const int64_t p = b + j;
+            if (p < 0) continue;
+            if (p < len) o[j] = static_cast<uint32_t>(y);
+            if (it.last && p == len - 1) scratch[q] = y;
+            y = step(y);
+        }
+        if (b >= 0) x = advance(x);
+        o += kAffSpan;
+    };
+    uint32_t k = 0;
+    for (; k < kb && k < kend; ++k) checked(k);
+    for (; k < body_end; ++k) {
+        const uint64_t y1 = step(x), y2 = step(y1), y3 = step(y2);
+        const u32x4 v = {static_cast<uint32_t>(x), static_cast<uint32_t>(y1), static_cast<uint32_t>(y2),
+                         static_cast<uint32_t>(y3)};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(o));
+        x = advance(x);
+        o += kAffSpan;
+    }
+    for (; k < kend; ++k) checked(k);
+}
+
+// Philox, counter-based, in the same span layout: lane i of step k makes
+// the block holding positions P + 256 k + 4 i - mis .. +3 (P: the chunk's
+// first stream position); when those are not block-aligned (d = (P - mis)
+// mod 4 != 0) a slot's value comes from the lane's own block or, for its
+// last d slots, from the next lane's (lane 63: lane 0's block of the next
+// step, made one step ahead).  One block per lane per store.
+__device__ __forceinline__ uint32_t pick4(const uint32_t (&v)[4], uint32_t i) {
+    return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
+}
+template <int ROUNDS>
+__global__ __launch_bounds__(kBlock) void k_ragged_philox(const RaggedItem *items, uint64_t n_items, const uint8_t *st,
+                                                           uint64_t S, uint64_t chunk, uint64_t *scratch,
+                                                           uint32_t *out) {
+    const uint64_t q = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    if (q >= n_items) return;  // whole waves
+    const RaggedItem it = items[q];
+    const uint32_t *key = reinterpret_cast<const uint32_t *>(st);
+    const uint32_t k0 = key[it.unit], k1 = key[S + it.unit];
+    const uint64_t P = reinterpret_cast<const uint64_t *>(st + 8 * S)[it.unit] + it.j * chunk;
+    const uint32_t mis = static_cast<uint32_t>((reinterpret_cast<uintptr_t>(out) >> 2) + it.out) & (kAffSpan - 1);
+    const uint64_t base = P - mis + 4 * lane;  // stream position of the lane's slot 0 in step 0 (mod 2^64)
+    const uint32_t d = static_cast<uint32_t>(P - mis) & 3;
+    const int64_t len = it.len;
+    const uint32_t kend = static_cast<uint32_t>((len + mis + kAffSpan - 1) / kAffSpan);
+    const uint32_t kb = mis ? 1u : 0u;
+    const uint32_t kw = static_cast<uint32_t>((len + mis) / kAffSpan);
+    const uint32_t kl = kend ? (kw < kend - 1 ? kw : kend - 1) : 0u;
+    const uint32_t body_end = kl > kb ? kl : kb;
+    uint32_t *o = out + (it.out - mis) + 4 * lane;
+    uint32_t cur[4], nxt[4];
+    philox_block<ROUNDS>(k0, k1, base >> 2, cur[0], cur[1], cur[2], cur[3]);
+    // the four slot values of this step; every lane takes part (shuffles)
+    auto values = [&](uint32_t k, uint32_t (&v)[4]) {
+        philox_block<ROUNDS>(k0, k1, (base + kAffSpan * (static_cast<uint64_t>(k) + 1)) >> 2, nxt[0], nxt[1], nxt[2],
+                             nxt[3]);
+        uint32_t nb[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t down = static_cast<uint32_t>(__shfl_down(static_cast<int>(cur[w]), 1));
+            const uint32_t first = static_cast<uint32_t>(__shfl(static_cast<int>(nxt[w]), 0));
+            nb[w] = lane == 63 ? first : down;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) v[j] = d + j < 4 ? pick4(cur, d + j) : pick4(nb, d + j - 4);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) cur[w] = nxt[w];
+    };
+    auto checked = [&](uint32_t k) {
+        uint32_t v[4];
+        values(k, v);
+        const int64_t b = static_cast<int64_t>(kAffSpan) * k + 4 * lane - mis;
+        for (int j = 0; j < 4; ++j) {
+            const int64_t p = b + j;
+            if (p < 0) continue;
+            if (p < len) o[j] = v[j];
+            if (it.last && p == len - 1) scratch[q] = P + static_cast<uint64_t>(len);
+        }
+        o += kAffSpan;
+    };
+    uint32_t k = 0;
+    for (; k < kb && k < kend; ++k) checked(k);
+    for (; k < body_end; ++k) {
+        uint32_t v[4];
+        values(k, v);
+        const u32x4 w = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(o));
+        o += kAffSpan;
+    }
+    for (; k < kend; ++k) checked(k);
+}
+
+// The final 64-bit state word of each stream (MWC: y; Philox: position) from
+// scratch into the image's array `dst`.
+__global__ __launch_bounds__(kBlock) void k_ragged_commit_u64(const RaggedItem *items, uint64_t n_items,
+                                                               const uint64_t *scratch, uint64_t *dst) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_items || !items[i].last) return;
+    dst[items[i].unit] = scratch[i];
+}
+
 template <bool L64>
 __global__ __launch_bounds__(kBlock) void k_ragged_commit_affine(const RaggedItem *items, uint64_t n_items,
                                                                   const uint64_t *scratch, uint8_t *st) {
@@ -468,8 +616,16 @@ bool ragged_affine(rngx_kind kind) {
     return kind == RNGX_LCG32 || kind == RNGX_LCG64 || kind == RNGX_LCG32_SUB || kind == RNGX_LCG64_SUB;
 }
 
-// outputs per chunk: a lane's (4096) or, for the affine kinds, a wave's
-uint64_t ragged_chunk(rngx_kind kind) { return ragged_affine(kind) ? 65536 : 4096; }
+bool ragged_wave(rngx_kind kind) {
+    return ragged_affine(kind) || kind == RNGX_MWC || kind == RNGX_MWC_DIFF || kind == RNGX_PHILOX4X32_10 ||
+           kind == RNGX_PHILOX4X32_7;
+}
+
+bool ragged_lane_table(rngx_kind kind) { return ragged_affine(kind) || kind == RNGX_MWC; }
+
+// outputs per chunk: a lane's (4096) or, for the kinds written a whole wave
+// span at a time, a wave's
+uint64_t ragged_chunk(rngx_kind kind) { return ragged_wave(kind) ? 65536 : 4096; }
 
 void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan) {
     std::vector<RaggedItem> &items = plan->items;
@@ -553,6 +709,14 @@ void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu
 }
 
 void ragged_lane_maps(const Gen *g, std::vector<uint64_t> *lane) {
+    if (g->kind == RNGX_MWC) {  // a^(i+1) mod p for i < 256, then a^256
+        std::vector<uint64_t> t64;
+        std::vector<uint32_t> t32;
+        jump_table(RNGX_MWC, 1, 257, &t64, &t32);  // a^0 .. a^256
+        lane->assign(t64.begin() + 1, t64.begin() + 257);  // entries 0..255: a^1 .. a^256
+        lane->push_back(t64[256]);                          // entry 256: the advance, a^256
+        return;
+    }
     // entry i: the (i+1)-step map (a lane whose first position is i); entry 256: the 256-step advance
     const uint64_t a = g->kind == RNGX_LCG32 ? kLcg32A : g->kind == RNGX_LCG64 ? kLcg64A : g->sub_a;
     const uint64_t c = g->kind == RNGX_LCG32 ? kLcg32C : g->kind == RNGX_LCG64 ? kLcg64C : g->sub_c;
@@ -562,7 +726,7 @@ void ragged_lane_maps(const Gen *g, std::vector<uint64_t> *lane) {
 }
 
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items) {
-    if (ragged_affine(kind)) return 8 * n_items;  // final states
+    if (ragged_wave(kind)) return 8 * n_items;  // final states
     return kind == RNGX_XS1024W ? 136 * n_items : state_bytes(kind, n_items);
 }
 
@@ -592,6 +756,21 @@ hipError_t launch_ragged(Ragged *r, uint32_t *d_out, hipStream_t st) {
             hipLaunchKernelGGL(k_ragged_commit_affine<false>, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n,
                                scr, g->d_state);
         }
+        return hipGetLastError();
+    }
+    if (ragged_wave(g->kind)) {
+        uint64_t *scr = reinterpret_cast<uint64_t *>(r->d_scratch);
+        uint64_t *dst = reinterpret_cast<uint64_t *>(g->d_state);  // MWC: y
+        switch (g->kind) {
+        case RNGX_MWC: hipLaunchKernelGGL(k_ragged_mwc<false>, dim3(blocks_for(64 * n)), dim3(kBlock), 0, st, r->d_items, n, r->d_t64, r->d_lane, g->d_state, g->S, C, scr, d_out); break;
+        case RNGX_MWC_DIFF: hipLaunchKernelGGL(k_ragged_mwc<true>, dim3(blocks_for(64 * n)), dim3(kBlock), 0, st, r->d_items, n, r->d_t64, r->d_lane, g->d_state, g->S, C, scr, d_out); break;
+        case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_ragged_philox<10>, dim3(blocks_for(64 * n)), dim3(kBlock), 0, st, r->d_items, n, g->d_state, g->S, C, scr, d_out); break;
+        case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_ragged_philox<7>, dim3(blocks_for(64 * n)), dim3(kBlock), 0, st, r->d_items, n, g->d_state, g->S, C, scr, d_out); break;
+        default: return hipErrorInvalidValue;
+        }
+        if (g->kind == RNGX_PHILOX4X32_10 || g->kind == RNGX_PHILOX4X32_7)
+            dst = reinterpret_cast<uint64_t *>(g->d_state + 8 * g->S);  // positions
+        hipLaunchKernelGGL(k_ragged_commit_u64, dim3(blocks_for(n)), dim3(kBlock), 0, st, r->d_items, n, scr, dst);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_ragged_start_small, dim3(blocks_for(n)), dim3(kBlock), 0, st, g->kind, r->d_items, n,

@@ -188,6 +188,8 @@ constexpr uint32_t kXsRowsPerCu = 128;      // 8 waves per SIMD x 4 SIMDs x 4 ro
 constexpr uint64_t kXsMinSlotSteps = 2048;  // slots are not cut finer than this
 uint64_t ragged_chunk(rngx_kind kind);
 bool ragged_affine(rngx_kind kind);  // LCG32/LCG64 and sub-stream forms: one wave per chunk
+bool ragged_wave(rngx_kind kind);    // affine kinds, MWC, MWC_DIFF, Philox: one wave per chunk, 1 KiB spans
+bool ragged_lane_table(rngx_kind kind);  // kinds whose wave kernel takes lane_maps (ragged_lane_maps)
 void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan);
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items);
 void ragged_lane_maps(const Gen *g, std::vector<uint64_t> *lane);  // affine kinds: lane start and advance maps

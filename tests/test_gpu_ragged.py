@@ -83,7 +83,7 @@ def test_ragged_graph_replay(rngx, orc, kind):
         assert np.array_equal(rngx.rng_get_state(ga), rngx.rng_get_state(gb)), rep
 
 
-@pytest.mark.parametrize("kind", ["lcg32", "lcg64", "xs1024w", "mwc"])
+@pytest.mark.parametrize("kind", ["lcg32", "lcg64", "xs1024w", "mwc", "mwc_diff", "philox4x32_10", "philox4x32_7"])
 def test_ragged_into_unaligned_view(rngx, orc, kind):
     """The output starts one word past a 16-byte boundary (a view of a larger
     buffer): values match the oracle and the words around it stay untouched."""
@@ -129,7 +129,7 @@ def _runs(seed, target):
     return [runs[i] for i in order]
 
 
-@pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "mwc", "philox4x32_10", "mwc_diff"])
 def test_ragged_bench_shape_sampled(rngx, orc, kind):
     """About 2.2e9 values in requests of 2^10 .. 2^22 values: large enough
     that the XS1024W plan uses its full row count, with cuts inside many

@@ -292,15 +292,57 @@ def _sampled_fill_check(rngx, orc, kind, S, count, seed, index):
     return g
 
 
+def _sampled_f32_check(rngx, orc, kind, S, count, seed, index):
+    """As _sampled_fill_check for FP32 output: sampled stream ranges equal the
+    oracle's (u >> 8) * 2^-24 bit for bit; the state equals a twin's after a
+    u32 fill of the same count."""
+    g = rngx.rng_create(kind, S, seed)
+    twin = rngx.rng_create(kind, S, seed)
+    rngx.rng_set_fill_config(g, index)
+    st = orc.seed(kind, S, seed)
+    out = torch.empty(S * count, dtype=torch.float32, device="cuda")
+    rngx.rng_fill_f32(g, out, count)
+    view = out.view(count, S)
+    for lo, hi in ((0, 256), (S // 2 - 128, S // 2 + 128), (S - 256, S)):
+        want = orc.generate(kind, S, st, count, lo=lo, hi=hi, mode=orc.OUT_F32)
+        got = view[:, lo:hi].contiguous().cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (kind, index, lo)
+    acc = torch.empty(S, dtype=torch.int32, device="cuda")
+    rngx.rng_consume(twin, acc, count)
+    assert np.array_equal(rngx.rng_get_state(g), rngx.rng_get_state(twin)), (kind, index)
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_every_fill_configuration(rngx, orc, kind):
     """Each autotuner candidate at 2^19 streams x 37 (large enough that the
-    paced candidates run paced) gives the same numbers."""
+    paced candidates run paced) gives the same numbers, as uint32 and as
+    FP32."""
     S, count = 1 << 19, 37
     for index in range(len(rngx.rng_fill_configs(kind))):
         print(f"case fill config {kind} #{index}", flush=True)
         _sampled_fill_check(rngx, orc, kind, S, count, 3, index)
+        _sampled_f32_check(rngx, orc, kind, S, count, 4, index)
     torch.cuda.empty_cache()
+
+
+def test_xs1024w_fill_from_unit_vector_states(rngx, orc):
+    """1024 instances, instance g holding the single set bit g of the
+    1024-bit word (the sparsest states; every word shift of the DPP step
+    reads zeros from outside the row for most lanes): a fill of 200 steps
+    equals the oracle stepping the same image, element by element."""
+    G = 1024
+    S = 32 * G
+    g = rngx.rng_create("xs1024w", S, 1)
+    img = rngx.rng_get_state(g)
+    W = img[: 4 * S].view(np.uint32)
+    W[:] = 0
+    for inst in range(G):
+        W[32 * inst + 31 - inst // 32] = np.uint32(1) << np.uint32(inst % 32)  # word 0 most significant
+    rngx.rng_set_state(g, img)
+    st = img.copy()
+    got = _fill(rngx, g, 200)
+    assert np.array_equal(got, orc.generate("xs1024w", S, st, 200))
+    assert np.array_equal(rngx.rng_get_state(g), st)
 
 
 @pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "xorwow"])

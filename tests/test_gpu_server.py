@@ -144,7 +144,8 @@ def _oracle_client_values(orc, rngx, kind, client, start, n, seed=SEED):
 @pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "lcg64", "mwc", "xorwow", "philox4x32_10", "philox4x32_7"])
 def test_served_fill_near_the_maximum_matches_the_oracle(rngx, orc, kind):
     """A served fill of 2^28 - 5 values (the largest size, every chunk
-    jump of the stream fill), then a second one that continues the stream:
+    jump of the stream fill), then a second one that continues the stream
+    (XS1024W: from the next whole instance step):
     sampled ranges -- the start, the middle, the last chunk -- equal the
     oracle's stream of the client seed; the second request starts where the
     first ended; both as uint32, the second also as FP32."""
@@ -162,7 +163,10 @@ def test_served_fill_near_the_maximum_matches_the_oracle(rngx, orc, kind):
     t = srv.submit_fill(client, kind, 3001, True)
     r = srv.wait(t, 60.0)
     got = rngx.copy_to_host(r.d_output, 4 * 3001, "float32")
-    want = _oracle_client_values(orc, rngx, kind, client, n, 3001)
+    # XS1024W requests take whole instance steps (the unused lanes of a last
+    # partial step are dropped), so the next request starts at a step
+    nxt = -(-n // _unit(kind)) * _unit(kind)
+    want = _oracle_client_values(orc, rngx, kind, client, nxt, 3001)
     assert np.array_equal(got.view(np.uint32), ((want >> 8).astype(np.float32) * np.float32(2.0 ** -24)).view(np.uint32))
     srv.release(t)
     srv.destroy()
