@@ -37,15 +37,39 @@ RAGGED_KINDS = [k for k in KINDS if not k.startswith("lfg")]  # ragged fills tak
 STATE_BYTES = {"lcg32": 4, "lcg64": 8, "mwc": 8, "xorwow": 24, "philox4x32_10": 16, "philox4x32_7": 16,
                "xs1024w": 4 + 8 / 32, "mwc_diff": 10, "lfg521": 4 * 521 / 1024, "lfg1279": 4 * 1279 / 1024}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "xs1024w_fill_u32_2p20x4096_hbm_traffic.md")
+PROFILE_ISING_VALU = os.path.join(ROOT, "profiles", "ising_valu_L4096_all_kinds.md")
 KERNEL_SOURCES = ["paper_1204_6193_amd/csrc/gen.hip", "paper_1204_6193_amd/csrc/rngx_device.h"]
+ISING_SOURCES = ["paper_1204_6193_amd/csrc/ising.hip", "paper_1204_6193_amd/csrc/rngx_device.h"]
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 instruction
+# occupies a SIMD for 4 cycles)
+VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def profile_json(path):
+    """The json block of a committed profile summary, or None."""
+    try:
+        with open(path) as f:
+            return json.loads(f.read().split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
+        return None
+
+
+def ising_valu_per_site():
+    """VALU lane-instructions per site update for each kind's L = 4096
+    kernel, from the committed counter summary, while the Ising sources are
+    the ones it was taken from."""
+    rec = profile_json(PROFILE_ISING_VALU)
+    if not rec or rec.get("kernel_hash") != kernel_hash(ISING_SOURCES):
+        return {}
+    return {k: v["valu_lane_instr_per_site"] for k, v in rec.get("kinds", {}).items()}
 
 
 def time_launches(fn, steps, warmup):
@@ -128,6 +152,10 @@ def bench_ising(rx, kind, L, sweeps, beta=0.4, hits=1):
     rec = {"sweeps": sweeps, "ms": round(ms, 3), "flips_per_ns": round(L * L * sweeps * hits / (ms * 1e6), 2),
            "strips": rx.ising_info(lat)["strips"],
            "autotune": {"plans": plans, "ms_per_20_sweeps": [round(m, 3) for m in tune_ms]}}
+    per_site = ising_valu_per_site().get(kind) if (L == 4096 and hits == 1) else None
+    if per_site:  # VALU roofline: lane-instructions issued per second over the issue peak
+        rec["valu_lane_instr_per_site"] = per_site
+        rec["valu_frac"] = round(rec["flips_per_ns"] * 1e9 * per_site / VALU_PEAK_LANE_INSTR, 4)
     if hits > 1:
         rec["hits"] = hits
         rec["ns_per_attempted_flip"] = round(ms * 1e6 / (L * L * sweeps * hits), 5)
@@ -170,8 +198,14 @@ def bench_ising_batch(rx, n=512, sweeps=10000, seed=1):
         lat.destroy()
     if bad:
         raise RuntimeError(f"Ising per-launch leg: {bad} lattices are invalid after the timed run")
+    rate = sites * sweeps / (batched_ms * 1e6)
+    per_site = ising_valu_per_site().get("batch_xs1024w")
+    extra = {}
+    if per_site:
+        extra = {"valu_lane_instr_per_site": per_site,
+                 "valu_frac": round(rate * 1e9 * per_site / VALU_PEAK_LANE_INSTR, 4)}
     return {"replicas": n, "sites": sites, "sweeps": sweeps, "batched_ms": round(batched_ms, 2),
-            "batched_flips_per_ns": round(sites * sweeps / (batched_ms * 1e6), 2),
+            "batched_flips_per_ns": round(rate, 2), **extra,
             "per_launch_sweeps": sweeps, "per_launch_ms": round(single_ms, 2),
             "per_launch_flips_per_ns": round(sites * sweeps / (single_ms * 1e6), 2)}
 
@@ -283,13 +317,8 @@ def bench_serve(rx, n_req=20000, rate=2000.0, clients=64, slots=8, inflight=32, 
 def traffic_from_profile():
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     only while the kernel sources are the ones it was taken from."""
-    try:
-        with open(PROFILE_TRAFFIC) as f:
-            text = f.read()
-        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    except (OSError, ValueError, IndexError):
-        return None
-    if rec.get("kernel_hash") != kernel_hash():
+    rec = profile_json(PROFILE_TRAFFIC)
+    if not rec or rec.get("kernel_hash") != kernel_hash():
         return None
     return rec.get("bytes_per_launch")
 

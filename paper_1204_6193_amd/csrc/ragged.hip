@@ -521,7 +521,7 @@ __device__ __forceinline__ void put(void *out, uint64_t idx, uint32_t u, int f32
 template <class G>
 __global__ __launch_bounds__(kBlock) void k_stream_fill_small(const uint8_t *st_in, uint8_t *st_out, uint64_t N,
                                                                uint64_t C, const uint64_t *t64, const uint32_t *t32,
-                                                               void *out, int f32) {
+                                                               void *out, int f32, uint32_t state_words) {
     __shared__ uint32_t tile[kBlock / 64][64][kSeg + 1];
     const uint64_t j = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t nch = (N + C - 1) / C;
@@ -550,7 +550,13 @@ __global__ __launch_bounds__(kBlock) void k_stream_fill_small(const uint8_t *st_
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (mine && j == nch - 1) g.store(st_out, 1, 0);
+    if (mine && j == nch - 1) {
+        // the whole one-stream image first: a generator's store writes only
+        // what it changes (Philox: the position, not the key)
+        for (uint32_t i = 0; i < state_words; ++i)
+            reinterpret_cast<uint32_t *>(st_out)[i] = reinterpret_cast<const uint32_t *>(st_in)[i];
+        g.store(st_out, 1, 0);
+    }
 }
 
 // XS1024W instance (state: 32 words, step counter, Weyl seed): one 16-lane
@@ -600,13 +606,14 @@ hipError_t launch_stream_fill(rngx_kind kind, const uint8_t *st_in, uint8_t *st_
         return hipGetLastError();
     }
     const unsigned blocks = blocks_for((N + C - 1) / C);
+    const uint32_t w = static_cast<uint32_t>(state_bytes(kind, 1) / 4);
     switch (kind) {
-    case RNGX_LCG32: hipLaunchKernelGGL(k_stream_fill_small<Lcg32>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
-    case RNGX_LCG64: hipLaunchKernelGGL(k_stream_fill_small<Lcg64>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
-    case RNGX_MWC: hipLaunchKernelGGL(k_stream_fill_small<Mwc>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
-    case RNGX_XORWOW: hipLaunchKernelGGL(k_stream_fill_small<Xorwow>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
-    case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_stream_fill_small<Philox>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
-    case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_stream_fill_small<Philox7>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32); break;
+    case RNGX_LCG32: hipLaunchKernelGGL(k_stream_fill_small<Lcg32>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32, w); break;
+    case RNGX_LCG64: hipLaunchKernelGGL(k_stream_fill_small<Lcg64>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32, w); break;
+    case RNGX_MWC: hipLaunchKernelGGL(k_stream_fill_small<Mwc>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32, w); break;
+    case RNGX_XORWOW: hipLaunchKernelGGL(k_stream_fill_small<Xorwow>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32, w); break;
+    case RNGX_PHILOX4X32_10: hipLaunchKernelGGL(k_stream_fill_small<Philox>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32, w); break;
+    case RNGX_PHILOX4X32_7: hipLaunchKernelGGL(k_stream_fill_small<Philox7>, dim3(blocks), dim3(kBlock), 0, st, st_in, st_out, N, C, t64, t32, out, f32, w); break;
     default: break;
     }
     return hipGetLastError();

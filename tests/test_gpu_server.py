@@ -27,7 +27,8 @@ def test_server_fills_equal_direct_fills(rngx, orc):
     srv = rngx.Server(slots=4, max_inflight=8, memory_budget=256 << 20, seed=SEED)
     reqs = [(3, "xs1024w", 1000, False), (3, "xs1024w", 300_001, True), (7, "lcg64", 9000, False),
             (3, "philox4x32_10", 77, False), (7, "lcg64", 300, True), (7, "xorwow", 20_000, False),
-            (9, "mwc", 4097, False), (9, "lcg32", 1, False)]
+            (9, "mwc", 4097, False), (9, "lcg32", 1, False), (3, "philox4x32_10", 4099, False),
+            (3, "philox4x32_7", 10, True), (3, "philox4x32_7", 70_001, False)]  # a client's later Philox requests
     tickets = [srv.submit_fill(c, k, n, f) for c, k, n, f in reqs]
     gens = {}
     for (c, k, n, f), t in zip(reqs, tickets):
