@@ -162,29 +162,51 @@ def bench_ising(rx, kind, L, sweeps, beta=0.4, hits=1):
     return rec
 
 
+def run_tuned_batch(rx, lats, betas, sweeps, tune_sweeps):
+    """Create the batch, autotune its launch shape on runs of at most
+    tune_sweeps sweeps (replicas restored afterwards), time one run, check
+    every replica's status; returns (ms, shape index, per-shape tuning ms)."""
+    batch = rx.ising_batch_create(lats, betas, sweeps)
+    tune_ms = rx.ising_batch_autotune(batch, max_sweeps=tune_sweeps, reps=1)
+    shape = rx.ising_batch_get_shape(batch)
+    durs, _ = time_launches(lambda: rx.ising_batch_run(batch), 1, 0)
+    bad = rx.ising_batch_status(batch)
+    batch.destroy()
+    if bad:
+        raise RuntimeError(f"Ising batch: {bad} replicas are invalid after the timed run")
+    return durs[0], shape, [round(m, 3) for m in tune_ms]
+
+
 def bench_ising_batch(rx, n=512, sweeps=10000, seed=1):
     """512 XS1024W replicas, L uniform over {16, 32, ..., 1024}, beta uniform in
     [0.3, 0.6], drawn with numpy default_rng(seed): one batched launch for
-    `sweeps` sweeps, then the same replicas from the same start one
-    ising_sweep call each for the same `sweeps` (the per-launch form), both
-    timed with HIP events on the stream they run on.  Every replica's status
-    is checked after each form, so an invalid lattice fails the bench."""
+    `sweeps` sweeps (launch shape autotuned first on runs of 500 sweeps),
+    then the same replicas from the same start one ising_sweep call each for
+    the same `sweeps` (the per-launch form), both timed with HIP events on
+    the stream they run on.  Every replica's status is checked after each
+    form, so an invalid lattice fails the bench.  A second batch of 2048
+    small replicas (L uniform over {16, ..., 128}, 2000 sweeps) is timed
+    batched only."""
     import numpy as np
-    import torch
     rng = np.random.default_rng(seed)
     Ls = [int(x) for x in rng.choice(np.arange(16, 1025, 16), size=n)]
     betas = [float(b) for b in rng.uniform(0.3, 0.6, size=n)]
     lats = [rx.ising_create(L, "xs1024w", 1000 + i) for i, L in enumerate(Ls)]
     sites = sum(L * L for L in Ls)
-    batch = rx.ising_batch_create(lats, betas, [sweeps] * n)
-    durs, _ = time_launches(lambda: rx.ising_batch_run(batch), 1, 0)
-    batched_ms = durs[0]
-    bad = rx.ising_batch_status(batch)
-    batch.destroy()
-    if bad:
-        raise RuntimeError(f"Ising batch: {bad} replicas are invalid after the timed run")
+    batched_ms, shape, tune_ms = run_tuned_batch(rx, lats, betas, [sweeps] * n, 500)
     for lat in lats:
         lat.destroy()
+    small_n, small_sweeps = 2048, 2000
+    sLs = [int(x) for x in rng.choice(np.arange(16, 129, 16), size=small_n)]
+    sbetas = [float(b) for b in rng.uniform(0.3, 0.6, size=small_n)]
+    slats = [rx.ising_create(L, "xs1024w", 5000 + i) for i, L in enumerate(sLs)]
+    ssites = sum(L * L for L in sLs)
+    small_ms, small_shape, small_tune = run_tuned_batch(rx, slats, sbetas, [small_sweeps] * small_n, 200)
+    for lat in slats:
+        lat.destroy()
+    small = {"replicas": small_n, "sites": ssites, "sweeps": small_sweeps, "batched_ms": round(small_ms, 2),
+             "batched_flips_per_ns": round(ssites * small_sweeps / (small_ms * 1e6), 2),
+             "shape": rx.ising_batch_shapes()[small_shape], "tune_ms": small_tune}
     lats = [rx.ising_create(L, "xs1024w", 1000 + i) for i, L in enumerate(Ls)]
 
     def per_launch():
@@ -206,8 +228,9 @@ def bench_ising_batch(rx, n=512, sweeps=10000, seed=1):
                  "valu_frac": round(rate * 1e9 * per_site / VALU_PEAK_LANE_INSTR, 4)}
     return {"replicas": n, "sites": sites, "sweeps": sweeps, "batched_ms": round(batched_ms, 2),
             "batched_flips_per_ns": round(rate, 2), **extra,
+            "shape": rx.ising_batch_shapes()[shape], "tune_ms": tune_ms,
             "per_launch_sweeps": sweeps, "per_launch_ms": round(single_ms, 2),
-            "per_launch_flips_per_ns": round(sites * sweeps / (single_ms * 1e6), 2)}
+            "per_launch_flips_per_ns": round(sites * sweeps / (single_ms * 1e6), 2), "small": small}
 
 
 def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_requests=256):
@@ -266,7 +289,8 @@ def bench_serve(rx, n_req=20000, rate=2000.0, clients=64, slots=8, inflight=32, 
     import threading
     import numpy as np
     rng = np.random.default_rng(seed)
-    kinds = [k for k in rx.KINDS if not k.endswith("_sub") and k != "mwc_diff"]  # kinds the server takes
+    # kinds the server takes (not the sub-stream, per-stream-multiplier or lagged Fibonacci ones)
+    kinds = [k for k in rx.KINDS if not k.endswith("_sub") and k != "mwc_diff" and not k.startswith("lfg")]
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
     reqs = []
     for i in range(n_req):
@@ -280,25 +304,39 @@ def bench_serve(rx, n_req=20000, rate=2000.0, clients=64, slots=8, inflight=32, 
     tickets = [None] * n_req
     ising_tickets = set()
 
+    failed = []
+
     def submitter():
         t0 = time.perf_counter()
-        for i, r in enumerate(reqs):
-            dt = arrivals[i] - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            if r[0] == "fill":
-                tickets[i] = srv.submit_fill(r[1], r[2], r[3], r[4])
-            else:
-                tickets[i] = srv.submit_ising(r[1], r[2], r[3], r[4], 100)
-                ising_tickets.add(tickets[i])
+        try:
+            for i, r in enumerate(reqs):
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                if r[0] == "fill":
+                    tickets[i] = srv.submit_fill(r[1], r[2], r[3], r[4])
+                else:
+                    tickets[i] = srv.submit_ising(r[1], r[2], r[3], r[4], 100)
+                    ising_tickets.add(tickets[i])
+        except Exception as exc:  # reported by the consuming loop
+            failed.append(exc)
 
     t0 = time.perf_counter()
     th = threading.Thread(target=submitter)
     th.start()
     lat, done = [], []
     # results are consumed in completion order, as independent clients would
-    for _ in range(n_req):
-        ticket, res = srv.wait_any()
+    while len(done) < n_req:
+        try:
+            ticket, res = srv.wait_any(timeout_s=1.0)
+        except rx.RngxError as exc:
+            if failed:
+                th.join()
+                srv.destroy()
+                raise RuntimeError(f"served trace: submission failed: {failed[0]}") from exc
+            if exc.status == -7:  # RNGX_E_BUSY: nothing finished within the second
+                continue
+            raise
         lat.append(res.latency_s)
         done.append((ticket, res.n_values))
         srv.release(ticket)

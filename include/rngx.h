@@ -395,6 +395,37 @@ rngx_status ising_batch_status(rngx_ising_batch b, uint32_t *n_invalid, void *st
  * workgroups of the persistent grid (the smaller of the two).  Any pointer
  * may be NULL. */
 rngx_status ising_batch_info(rngx_ising_batch b, uint32_t *n_items, uint32_t *resident, uint32_t *grid);
+
+/* Launch shapes of the batch kernel and their autotuner.  A shape gives the
+ * threads per workgroup, the most lattice sites one workgroup holds per
+ * thread (one random number per site and sweep: the numbers per thread) and
+ * the LDS a strip may take; together they fix how each replica is tiled into
+ * strips (one workgroup if it fits, else a gang of strips, else streamed
+ * through memory).  Every shape gives the same spins, energies and stream
+ * states.  ising_batch_shapes: the list in index order; out (n entries) may
+ * be NULL to ask for *n only.  ising_batch_set_shape: re-plan the batch with
+ * shape `index` (a new batch uses shape 0); synchronizes the device.
+ * ising_batch_autotune: times every shape on `reps` (>= 1) runs after one
+ * warm-up run, each replica's sweep count scaled by one factor so that the
+ * longest runs max_sweeps (at least one sweep each; the real counts when
+ * they are all <= max_sweeps), with no energy traces; keeps the fastest and
+ * restores every replica's spins, stream states and status as they were
+ * (saved to device memory the call allocates and frees); ms_out (may be
+ * NULL, else one entry per shape of ising_batch_shapes) receives the mean
+ * run time of each shape.  Re-planning frees the device buffers a run reads: a graph captured
+ * before ising_batch_set_shape or ising_batch_autotune must not be replayed
+ * after it.  Errors: RNGX_E_INVALID (bad index, max_sweeps or reps = 0),
+ * RNGX_E_NOMEM, RNGX_E_HIP (if re-planning fails the batch's runs return
+ * RNGX_E_HIP until a shape is set again). */
+typedef struct {
+    uint32_t threads;          /* per workgroup: 256, 512 or 1024              */
+    uint32_t sites_per_thread; /* most lattice sites per thread in a workgroup */
+    uint32_t lds_cap;          /* most LDS bytes of one strip                  */
+} rngx_batch_shape;
+rngx_status ising_batch_shapes(rngx_batch_shape *out, int32_t *n);
+rngx_status ising_batch_set_shape(rngx_ising_batch b, int32_t index);
+rngx_status ising_batch_get_shape(rngx_ising_batch b, int32_t *index);
+rngx_status ising_batch_autotune(rngx_ising_batch b, uint64_t max_sweeps, int32_t reps, float *ms_out, void *stream);
 rngx_status ising_batch_destroy(rngx_ising_batch b);
 
 /* Served form.  A server admits requests in arrival order as soon as its

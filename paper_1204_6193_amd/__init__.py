@@ -66,6 +66,10 @@ SIGNATURES = {
     "ising_batch_info": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
                                 ctypes.POINTER(ctypes.c_uint32)]),
     "ising_batch_destroy": (_i32, [_vp]),
+    "ising_batch_shapes": (_i32, [_vp, ctypes.POINTER(_i32)]),
+    "ising_batch_set_shape": (_i32, [_vp, _i32]),
+    "ising_batch_get_shape": (_i32, [_vp, ctypes.POINTER(_i32)]),
+    "ising_batch_autotune": (_i32, [_vp, _u64, _i32, _vp, _vp]),
     "srv_create": (_i32, [ctypes.c_void_p, ctypes.POINTER(_vp)]),
     "srv_submit_fill": (_i32, [_vp, ctypes.c_uint32, _i32, _u64, _i32, ctypes.POINTER(_u64)]),
     "srv_submit_ising": (_i32, [_vp, ctypes.c_uint32, _i32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32,
@@ -508,6 +512,40 @@ def ising_batch_info(batch: IsingBatch) -> dict:
     n, r, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
     _check(load().ising_batch_info(batch.handle, ctypes.byref(n), ctypes.byref(r), ctypes.byref(g)))
     return {"items": n.value, "resident": r.value, "grid": g.value}
+
+
+class BatchShape(ctypes.Structure):
+    """rngx_batch_shape: threads per workgroup, most sites per thread, most LDS bytes of a strip."""
+    _fields_ = [("threads", ctypes.c_uint32), ("sites_per_thread", ctypes.c_uint32), ("lds_cap", ctypes.c_uint32)]
+
+
+def ising_batch_shapes() -> list[tuple[int, int, int]]:
+    """The batch launch shapes in index order, as (threads, sites_per_thread, lds_cap)."""
+    n = ctypes.c_int()
+    _check(load().ising_batch_shapes(None, ctypes.byref(n)))
+    arr = (BatchShape * n.value)()
+    _check(load().ising_batch_shapes(ctypes.cast(arr, _vp), ctypes.byref(n)))
+    return [(c.threads, c.sites_per_thread, c.lds_cap) for c in arr]
+
+
+def ising_batch_set_shape(batch: IsingBatch, index: int):
+    _check(load().ising_batch_set_shape(batch.handle, int(index)))
+
+
+def ising_batch_get_shape(batch: IsingBatch) -> int:
+    v = ctypes.c_int()
+    _check(load().ising_batch_get_shape(batch.handle, ctypes.byref(v)))
+    return v.value
+
+
+def ising_batch_autotune(batch: IsingBatch, max_sweeps: int = 200, reps: int = 2, stream=None) -> list[float]:
+    """Time every batch shape (sweep counts scaled so the longest is max_sweeps), keep the fastest and
+    restore the replicas; returns the mean run time (ms) of each shape."""
+    n = len(ising_batch_shapes())
+    ms = (ctypes.c_float * n)()
+    _check(load().ising_batch_autotune(batch.handle, int(max_sweeps), int(reps), ctypes.cast(ms, _vp),
+                                       _stream(stream)))
+    return list(ms)
 
 
 def ising_batch_destroy(batch: IsingBatch):

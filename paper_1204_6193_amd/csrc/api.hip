@@ -4,6 +4,7 @@
 // device; on error it returns a negative status with a thread-local message
 // and modifies nothing.  Live handles are kept in a registry so that a
 // stale or foreign handle is reported instead of dereferenced.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -82,10 +83,7 @@ void free_ragged(Ragged *r) {
 }
 
 void free_batch(IsingBatch *b) {
-    (void)hipFree(b->d_reps);
-    (void)hipFree(b->d_items);
-    (void)hipFree(b->d_next);
-    (void)hipFree(b->d_halo);
+    batch_release(b);
     delete[] b->lats;
     b->magic = 0;
     delete b;
@@ -856,9 +854,15 @@ rngx_status ising_batch_create(const rngx_ising *lats, uint32_t n, const double 
     b->device = members[0]->device;
     b->kind = members[0]->gen->kind;
     b->n = n;
+    b->n_cu = n_cu;
+    b->shape = 0;
     b->lats = new Ising *[n];
     for (uint32_t i = 0; i < n; ++i) b->lats[i] = members[i];
-    hipError_t e = batch_prepare(b, members.data(), betas, n_sweeps, d_traces, n_cu);
+    b->betas.assign(betas, betas + n);
+    b->sweeps.assign(n_sweeps, n_sweeps + n);
+    b->traces.assign(n, nullptr);
+    if (d_traces) b->traces.assign(d_traces, d_traces + n);
+    hipError_t e = batch_prepare(b, b->sweeps.data(), true);
     if (e != hipSuccess) {
         free_batch(b);
         return hip_fail(e, "batch preparation");
@@ -905,6 +909,131 @@ rngx_status ising_batch_info(rngx_ising_batch h, uint32_t *n_items, uint32_t *re
     if (n_items) *n_items = b->n_items;
     if (resident) *resident = b->resident;
     if (grid) *grid = b->grid;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_batch_shapes(rngx_batch_shape *out, int32_t *n) {
+    if (!n) return fail(RNGX_E_INVALID, "n is NULL");
+    if (out)
+        for (int i = 0; i < kBatchShapes; ++i)
+            out[i] = rngx_batch_shape{kBatchShape[i].threads, kBatchShape[i].sites_per_thread, kBatchShape[i].lds_cap};
+    *n = kBatchShapes;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_batch_set_shape(rngx_ising_batch h, int32_t index) {
+    IsingBatch *b;
+    if (rngx_status s = check_batch(h, &b)) return s;
+    if (index < 0 || index >= kBatchShapes) return fail(RNGX_E_INVALID, "shape index out of range");
+    DeviceScope ds(b->device);
+    (void)hipDeviceSynchronize();  // no run of the old plan still reads its buffers
+    const int old = b->shape;
+    b->shape = index;
+    hipError_t e = batch_prepare(b, b->sweeps.data(), true);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b->shape = old;
+        (void)batch_prepare(b, b->sweeps.data(), true);  // if this fails too, runs fail until a shape is set
+        (void)hipGetLastError();
+        return hip_fail(e, "batch re-planning");
+    }
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_batch_get_shape(rngx_ising_batch h, int32_t *index) {
+    IsingBatch *b;
+    if (rngx_status s = check_batch(h, &b)) return s;
+    if (!index) return fail(RNGX_E_INVALID, "index is NULL");
+    *index = b->shape;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status ising_batch_autotune(rngx_ising_batch h, uint64_t max_sweeps, int32_t reps, float *ms_out, void *stream) {
+    IsingBatch *b;
+    if (rngx_status s = check_batch(h, &b)) return s;
+    if (max_sweeps == 0 || reps < 1) return fail(RNGX_E_INVALID, "max_sweeps and reps must be positive");
+    DeviceScope ds(b->device);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    // Tuning runs: every replica's sweep count scaled by one factor so that
+    // the longest runs max_sweeps (at least one sweep each), no traces.
+    uint64_t top = 1;
+    for (uint64_t v : b->sweeps) top = std::max(top, v);
+    std::vector<uint64_t> tune(b->n);
+    for (uint32_t i = 0; i < b->n; ++i)
+        tune[i] = top <= max_sweeps ? b->sweeps[i]
+                                    : std::max<uint64_t>(1, static_cast<uint64_t>(static_cast<double>(b->sweeps[i]) *
+                                                                                  max_sweeps / top + 0.5));
+    // every replica's spins, streams and status word, saved in one buffer
+    std::vector<size_t> off(b->n + 1, 0);
+    for (uint32_t i = 0; i < b->n; ++i) {
+        const Ising *l = b->lats[i];
+        off[i + 1] = off[i] + (static_cast<size_t>(l->L) * l->L + l->gen->state_bytes + 4 + 255) / 256 * 256;
+    }
+    uint8_t *saved = nullptr;
+    hipError_t e = hipMalloc(&saved, off[b->n]);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RNGX_E_NOMEM, "device memory for the saved replicas");
+    }
+    auto copy_all = [&](bool save) {
+        hipError_t r = hipSuccess;
+        for (uint32_t i = 0; i < b->n && r == hipSuccess; ++i) {
+            Ising *l = b->lats[i];
+            const size_t sb = static_cast<size_t>(l->L) * l->L, gb = l->gen->state_bytes;
+            uint8_t *p = saved + off[i];
+            void *dev[3] = {l->d_spins, l->gen->d_state, l->d_err};
+            const size_t at[3] = {0, sb, sb + gb}, len[3] = {sb, gb, 4};
+            for (int k = 0; k < 3 && r == hipSuccess; ++k)
+                r = save ? hipMemcpyAsync(p + at[k], dev[k], len[k], hipMemcpyDeviceToDevice, st)
+                         : hipMemcpyAsync(dev[k], p + at[k], len[k], hipMemcpyDeviceToDevice, st);
+        }
+        return r;
+    };
+    const int start_shape = b->shape;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = copy_all(true);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int best = -1;
+    float best_ms = 0;
+    for (int i = 0; i < kBatchShapes && e == hipSuccess; ++i) {
+        b->shape = i;
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = batch_prepare(b, tune.data(), false);
+        if (e == hipSuccess) e = copy_all(false);
+        if (e == hipSuccess) e = launch_batch(b, st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch(b, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        ms /= static_cast<float>(reps);
+        if (ms_out) ms_out[i] = ms;
+        if (e == hipSuccess && (best < 0 || ms < best_ms)) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    // the fastest shape with the real sweep counts and traces, and the
+    // replicas as they were
+    b->shape = best >= 0 ? best : start_shape;
+    const hipError_t e_run = e;
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = copy_all(false);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(saved);
+    const hipError_t e_plan = batch_prepare(b, b->sweeps.data(), true);
+    if (e_run != hipSuccess) return hip_fail(e_run, "batch tuning run");
+    if (e != hipSuccess) return hip_fail(e, "restoring the replicas");
+    if (e_plan != hipSuccess) return hip_fail(e_plan, "batch re-planning");
     clear_error();
     return RNGX_OK;
 }

@@ -985,16 +985,17 @@ __device__ void gang_start(const ReplicaDesc &d) {
 // eight-site units, i.e. L <= 256, with 1024 threads).
 template <class Unit>
 constexpr int batch_spt() { return Unit::kNB == 8 ? 8 : 16; }
-constexpr uint32_t kBatchThreads = 1024;
 
 // Work items are (replica, strip) pairs; a gang's strips are consecutive in
 // the list, which the workgroups take in order from a counter.  Every
 // workgroup of the launch is resident, so when a strip waits for a neighbour
 // that neighbour is either running or will be taken by the next workgroup to
 // finish its (independent) item; gangs are far smaller than the grid.
-template <class Unit>
-__global__ __launch_bounds__(kBatchThreads) void k_ising_batch(const ReplicaDesc *reps, const uint2 *items,
-                                                              uint32_t n_items, uint32_t *next) {
+// MAXT: the most threads per workgroup the instantiation is compiled for
+// (1024 caps a thread at 128 VGPRs, 512 at 256, so fewer spills).
+template <class Unit, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_ising_batch(const ReplicaDesc *reps, const uint2 *items, uint32_t n_items,
+                                                     uint32_t *next) {
     constexpr int NB = Unit::kNB;
     constexpr int spt = batch_spt<Unit>();
     extern __shared__ __align__(16) uint8_t lds[];
@@ -1204,26 +1205,28 @@ hipError_t run(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hi
     return run_passes<Unit, true>(lat, T4, T8, n, tr, st, hits);
 }
 
-constexpr uint32_t kBatchLdsCap = 80 * 1024;  // keeps two batch workgroups per CU
 constexpr uint32_t kMaxGang = 64;             // most strips of one batch replica
 constexpr uint64_t kGangWordBytes = 64;       // a gang's arrival counter, after its halo words
 constexpr double kGangStartSeconds = 60.0;    // longest wait of a gang member for the others to start
 
 template <class Unit>
-const void *batch_kernel() { return reinterpret_cast<const void *>(&k_ising_batch<Unit>); }
+const void *batch_kernel(uint32_t threads) {
+    if (threads > 512) return reinterpret_cast<const void *>(&k_ising_batch<Unit, 1024>);
+    return reinterpret_cast<const void *>(&k_ising_batch<Unit, 512>);
+}
 
-const void *batch_kernel_for(rngx_kind kind) {
+const void *batch_kernel_for(rngx_kind kind, uint32_t threads) {
     switch (kind) {
-    case RNGX_LCG32: return batch_kernel<SmallUnit<Lcg32>>();
-    case RNGX_LCG32_SUB: return batch_kernel<SmallUnit<Lcg32Sub>>();
-    case RNGX_LCG64: return batch_kernel<SmallUnit<Lcg64>>();
-    case RNGX_LCG64_SUB: return batch_kernel<SmallUnit<Lcg64Sub>>();
-    case RNGX_MWC: return batch_kernel<SmallUnit<Mwc>>();
-    case RNGX_MWC_DIFF: return batch_kernel<SmallUnit<MwcDiff>>();
-    case RNGX_XORWOW: return batch_kernel<SmallUnit<Xorwow>>();
-    case RNGX_PHILOX4X32_10: return batch_kernel<PhiloxUnit>();
-    case RNGX_PHILOX4X32_7: return batch_kernel<PhiloxUnit7>();
-    case RNGX_XS1024W: return batch_kernel<XsUnit>();
+    case RNGX_LCG32: return batch_kernel<SmallUnit<Lcg32>>(threads);
+    case RNGX_LCG32_SUB: return batch_kernel<SmallUnit<Lcg32Sub>>(threads);
+    case RNGX_LCG64: return batch_kernel<SmallUnit<Lcg64>>(threads);
+    case RNGX_LCG64_SUB: return batch_kernel<SmallUnit<Lcg64Sub>>(threads);
+    case RNGX_MWC: return batch_kernel<SmallUnit<Mwc>>(threads);
+    case RNGX_MWC_DIFF: return batch_kernel<SmallUnit<MwcDiff>>(threads);
+    case RNGX_XORWOW: return batch_kernel<SmallUnit<Xorwow>>(threads);
+    case RNGX_PHILOX4X32_10: return batch_kernel<PhiloxUnit>(threads);
+    case RNGX_PHILOX4X32_7: return batch_kernel<PhiloxUnit7>(threads);
+    case RNGX_XS1024W: return batch_kernel<XsUnit>(threads);
     default: break;  // lagged Fibonacci: per-pass kernels only
     }
     return nullptr;
@@ -1235,19 +1238,40 @@ uint64_t threshold(double beta, int dE) {
 
 }  // namespace
 
-hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas, const uint64_t *n_sweeps,
-                         int32_t *const *traces, int n_cu) {
+const BatchShape kBatchShape[kBatchShapes] = {
+    {1024, 64, 80 * 1024},  // the default: fewest strips, two strip workgroups' LDS per CU
+    {1024, 32, 80 * 1024},  // half the sites per workgroup: twice the strips per replica
+    {512, 64, 80 * 1024},
+    {512, 32, 40 * 1024},
+    {256, 64, 40 * 1024},   // small workgroups for many small replicas
+};
+
+void batch_release(IsingBatch *b) {
+    (void)hipFree(b->d_reps);
+    (void)hipFree(b->d_items);
+    (void)hipFree(b->d_next);
+    (void)hipFree(b->d_halo);
+    b->d_reps = b->d_items = b->d_halo = nullptr;
+    b->d_next = nullptr;
+    b->n_items = b->grid = b->resident = b->lds = 0;
+    b->gangs = false;
+}
+
+hipError_t batch_prepare(IsingBatch *b, const uint64_t *sweeps, bool with_traces) {
+    batch_release(b);
     const uint32_t n = b->n;
+    const BatchShape &sh = kBatchShape[b->shape];
     const uint32_t nb = b->kind == RNGX_XS1024W ? 8 : 4;
-    const uint64_t spt = nb == 8 ? 8 : 16, max_units = spt * kBatchThreads;
+    const uint64_t max_units = static_cast<uint64_t>(sh.sites_per_thread) * sh.threads / nb;
     std::vector<ReplicaDesc> reps(n);
     uint32_t lds = 80;
     uint64_t halo_bytes = 0;
     for (uint32_t i = 0; i < n; ++i) {
-        const Ising *l = lats[i];
+        const Ising *l = b->lats[i];
         const uint32_t L = l->L;
-        ReplicaDesc d{l->d_spins, l->gen->d_state, l->gen->S, L, kReplicaMemory, threshold(betas[i], 4),
-                      threshold(betas[i], 8), n_sweeps[i], traces ? traces[i] : nullptr, 0, 0, 0, nullptr, l->d_err};
+        int32_t *tr = with_traces ? b->traces[i] : nullptr;
+        ReplicaDesc d{l->d_spins, l->gen->d_state, l->gen->S, L, kReplicaMemory, threshold(b->betas[i], 4),
+                      threshold(b->betas[i], 8), sweeps[i], tr, 0, 0, 0, nullptr, l->d_err};
         // Fewest strips (one if possible) that fit the workgroup's LDS and
         // unit slots: strips of R rows and a last one of R_last = L - (nwg-1) R
         // rows (2 <= R_last <= R), so that L need not be a multiple of R.
@@ -1261,7 +1285,7 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
             const uint32_t R_last = L - (nwg - 1) * R;
             if (nwg > 1 && R_last < 2) continue;  // a strip's top and bottom rows are distinct
             const uint64_t units = static_cast<uint64_t>(R) * L / nb;
-            if (units > max_units || strip_lds_bytes(L, R) > kBatchLdsCap) continue;
+            if (units > max_units || strip_lds_bytes(L, R) > sh.lds_cap) continue;
             if (nb == 8 && ((static_cast<uint64_t>(R) * L) % 128 || (static_cast<uint64_t>(R_last) * L) % 128))
                 continue;
             d.mode = nwg == 1 ? kReplicaOnChip : kReplicaStrips;
@@ -1285,14 +1309,18 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
     std::vector<uint2> items;
     for (uint32_t x : order)
         for (uint32_t j = 0; j < std::max<uint32_t>(reps[x].nwg, 1); ++j) items.push_back(make_uint2(x, j));
-    const void *fn = batch_kernel_for(b->kind);
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    const void *fn = batch_kernel_for(b->kind, sh.threads);
+    // the largest strip LDS of any shape, so that batches planned with other
+    // shapes keep launching
+    uint32_t lds_top = 0;
+    for (const BatchShape &x : kBatchShape) lds_top = std::max(lds_top, x.lds_cap);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_top));
     (void)hipGetLastError();
     int occ = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBatchThreads, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, sh.threads, lds);
     if (e != hipSuccess) return e;
     if (occ < 1) return hipErrorOutOfMemory;
-    const uint32_t resident = static_cast<uint32_t>(occ * std::max(n_cu, 1));
+    const uint32_t resident = static_cast<uint32_t>(occ * std::max(b->n_cu, 1));
     if (resident < 2 * kMaxGang) {  // too few workgroups to run gangs safely: strips go to memory
         halo_bytes = 0;
         for (auto &d : reps)
@@ -1304,11 +1332,6 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
     int clock_khz = 0;  // wall_clock64() rate
     if ((e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, b->device)) != hipSuccess) return e;
     const uint64_t start_ticks = static_cast<uint64_t>(kGangStartSeconds * 1e3 * std::max(clock_khz, 1));
-    b->lds = lds;
-    b->n_items = static_cast<uint32_t>(items.size());
-    b->resident = resident;
-    b->gangs = halo_bytes != 0;
-    b->grid = std::min<uint32_t>(b->n_items, resident);
     if (halo_bytes) {
         if ((e = hipMalloc(&b->d_halo, halo_bytes)) != hipSuccess) return e;
         uint64_t off = 0;
@@ -1324,18 +1347,27 @@ hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas,
     if ((e = hipMalloc(&b->d_items, sizeof(uint2) * items.size())) != hipSuccess) return e;
     if ((e = hipMalloc(&b->d_next, 4)) != hipSuccess) return e;
     if ((e = hipMemcpy(b->d_reps, reps.data(), sizeof(ReplicaDesc) * n, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    return hipMemcpy(b->d_items, items.data(), sizeof(uint2) * items.size(), hipMemcpyHostToDevice);
+    if ((e = hipMemcpy(b->d_items, items.data(), sizeof(uint2) * items.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    b->lds = lds;
+    b->n_items = static_cast<uint32_t>(items.size());
+    b->resident = resident;
+    b->gangs = halo_bytes != 0;
+    b->grid = std::min<uint32_t>(b->n_items, resident);
+    return hipSuccess;
 }
 
 hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
     if (b->n == 0) return hipSuccess;
+    if (!b->d_reps || !b->d_items || !b->d_next) return hipErrorNotReady;  // a failed re-plan left no plan
     const auto *reps = static_cast<const ReplicaDesc *>(b->d_reps);
     const auto *items = static_cast<const uint2 *>(b->d_items);
     hipLaunchKernelGGL(k_batch_prologue, dim3(b->n), dim3(kBlock), 0, st, reps, b->d_next);
-    const void *fn = batch_kernel_for(b->kind);
+    const void *fn = batch_kernel_for(b->kind, kBatchShape[b->shape].threads);
     if (!fn) return hipErrorInvalidValue;
     uint32_t n_items = b->n_items;
     uint32_t *next = b->d_next;
+    const uint32_t threads = kBatchShape[b->shape].threads;
     void *args[] = {&reps, &items, &n_items, &next};
     // With gangs, and outside graph capture, the launch is cooperative, which
     // makes the whole grid resident together whatever else runs on the
@@ -1347,8 +1379,8 @@ hipError_t launch_batch(IsingBatch *b, hipStream_t st) {
     hipError_t e = hipStreamIsCapturing(st, &cap);
     if (e != hipSuccess) return e;
     if (b->gangs && cap == hipStreamCaptureStatusNone)
-        return hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(kBatchThreads), args, b->lds, st);
-    return hipLaunchKernel(fn, dim3(b->grid), dim3(kBatchThreads), args, b->lds, st);
+        return hipLaunchCooperativeKernel(fn, dim3(b->grid), dim3(threads), args, b->lds, st);
+    return hipLaunchKernel(fn, dim3(b->grid), dim3(threads), args, b->lds, st);
 }
 
 namespace {

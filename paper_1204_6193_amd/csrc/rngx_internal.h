@@ -91,6 +91,17 @@ struct Ising {
     uint32_t batches;    // batches that hold this lattice
 };
 
+// A launch shape of the batch kernel: threads per workgroup, most lattice
+// sites per workgroup and thread (one random draw per site and sweep, so the
+// numbers per thread), and the LDS a strip may take (which bounds the strip
+// height, i.e. the sub-lattice tiling).  The autotuner picks one of a fixed
+// list.
+struct BatchShape {
+    uint32_t threads, sites_per_thread, lds_cap;
+};
+constexpr int kBatchShapes = 5;
+extern const BatchShape kBatchShape[kBatchShapes];
+
 // A fixed list of lattices swept together in one launch.
 struct IsingBatch {
     uint64_t magic;
@@ -105,7 +116,12 @@ struct IsingBatch {
     uint32_t lds, grid;  // launch shape
     uint32_t resident;   // workgroups of the batch kernel that fit at once
     bool gangs;          // some replica runs as a gang of strips
+    int shape;           // index into kBatchShape
+    int n_cu;
     Ising **lats;        // host copy of the members
+    std::vector<double> betas;        // the run's arguments, kept to re-plan
+    std::vector<uint64_t> sweeps;     //   under another shape
+    std::vector<int32_t *> traces;
 };
 
 struct Server;  // request server (server.hip)
@@ -171,8 +187,11 @@ hipError_t launch_ising(Ising *lat, double beta, uint64_t n_sweeps, int32_t *d_t
 hipError_t launch_zero(uint32_t *p, uint64_t n, hipStream_t st);
 bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out);
 int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int max);  // strip candidates
-hipError_t batch_prepare(IsingBatch *b, Ising *const *lats, const double *betas, const uint64_t *n_sweeps,
-                         int32_t *const *traces, int n_cu);
+// Plans b (shape b->shape) from b->lats, b->betas, b->traces and `sweeps`
+// (b->sweeps for real runs; scaled-down counts and no traces while tuning),
+// replacing any earlier plan's device buffers.
+hipError_t batch_prepare(IsingBatch *b, const uint64_t *sweeps, bool with_traces);
+void batch_release(IsingBatch *b);  // the plan's device buffers
 hipError_t launch_batch(IsingBatch *b, hipStream_t st);
 // Work items of a ragged fill.  Small-state kinds: chunks of ragged_chunk
 // outputs, one per lane.  XS1024W: the steps of all instances, concatenated,

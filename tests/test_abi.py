@@ -106,6 +106,23 @@ def test_fill_configuration_lists(rngx):
     assert lib.rng_autotune_fill(bogus, ctypes.c_void_p(0x1000), 4, 1, None, None) == -1
 
 
+def test_batch_shape_list(rngx):
+    """The batch launch shapes: the default first (1024 threads, 64 sites per
+    thread), every entry within a workgroup's limits."""
+    lib = rngx.load()
+    shapes = rngx.ising_batch_shapes()
+    assert len(shapes) == 5 and shapes[0] == (1024, 64, 80 * 1024)
+    for threads, sites, lds in shapes:
+        assert threads in (256, 512, 1024) and 1 <= sites <= 64 and 0 < lds <= 160 * 1024
+    assert len(set(shapes)) == len(shapes)
+    assert lib.ising_batch_shapes(None, None) == -1
+    bogus = ctypes.c_void_p(0x1234560)
+    assert lib.ising_batch_set_shape(bogus, 0) == -1
+    v = ctypes.c_int()
+    assert lib.ising_batch_get_shape(bogus, ctypes.byref(v)) == -1
+    assert lib.ising_batch_autotune(bogus, 10, 1, None, None) == -1
+
+
 def test_last_error_is_per_thread(rngx):
     import threading
     lib = rngx.load()

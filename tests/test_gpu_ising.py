@@ -334,6 +334,65 @@ def test_batch_gang_behind_long_replicas(rngx, orc):
     assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[-1])), st)
 
 
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "philox4x32_10", "xorwow"])
+def test_batch_every_shape_matches_oracle(rngx, orc, kind):
+    """Every batch launch shape (threads per workgroup, sites per thread,
+    strip LDS) tiles the replicas differently -- one workgroup, gangs of
+    strips or streaming through memory -- and every one gives the oracle's
+    spins, energies and stream states.  The runs follow each other, the
+    oracle advanced in step."""
+    Ls = [16, 48, 128, 256, 400, 1008, 2048, 64]
+    betas = [0.3, 0.41, 0.44, 0.5, 0.38, 0.45, 0.42, 0.6]
+    sweeps = [3, 2, 2, 3, 2, 2, 2, 4]
+    lats = [rngx.ising_create(L, kind, 800 + i) for i, L in enumerate(Ls)]
+    refs = [orc.ising_create(L, kind, 800 + i) for i, L in enumerate(Ls)]
+    traces = [torch.full((s,), 7, dtype=torch.int32, device="cuda") for s in sweeps]
+    batch = rngx.ising_batch_create(lats, betas, sweeps, traces)
+    for shape in range(len(rngx.ising_batch_shapes())):
+        print(f"case batch shape {kind} {shape}", flush=True)
+        rngx.ising_batch_set_shape(batch, shape)
+        assert rngx.ising_batch_get_shape(batch) == shape
+        rngx.ising_batch_run(batch)
+        assert rngx.ising_batch_status(batch) == 0
+        for i, (sp, st) in enumerate(refs):
+            want = orc.ising_sweeps(Ls[i], kind, betas[i], st, sp, sweeps[i])
+            assert np.array_equal(traces[i].cpu().numpy(), want), (shape, i, Ls[i])
+            assert np.array_equal(rngx.ising_get_spins(lats[i]).ravel(), sp), (shape, i, Ls[i])
+            assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[i])), st), (shape, i, Ls[i])
+
+
+def test_batch_autotune_restores_replicas(rngx):
+    """The batch autotuner times every shape, keeps one, and leaves every
+    replica's spins and streams as they were; runs afterwards still equal
+    ising_sweep on each lattice alone."""
+    kind = "xs1024w"
+    Ls, betas, sweeps = _batch_case(rngx, kind, 21, n=16, max_L=512, big=(1024,))
+    sweeps = [s * 40 for s in sweeps]  # tuned at most 50 sweeps: scaled down
+    lats = [rngx.ising_create(L, kind, 900 + i) for i, L in enumerate(Ls)]
+    twins = [rngx.ising_create(L, kind, 900 + i) for i, L in enumerate(Ls)]
+    traces = [torch.full((s,), 7, dtype=torch.int32, device="cuda") for s in sweeps]
+    batch = rngx.ising_batch_create(lats, betas, sweeps, traces)
+    spins0 = [rngx.ising_get_spins(x) for x in lats]
+    states0 = [rngx.rng_get_state(rngx.ising_rng(x)) for x in lats]
+    ms = rngx.ising_batch_autotune(batch, max_sweeps=50, reps=1)
+    print(f"case batch autotune ms={ms}", flush=True)
+    assert len(ms) == len(rngx.ising_batch_shapes()) and all(m > 0 for m in ms)
+    assert ms[rngx.ising_batch_get_shape(batch)] == min(ms)
+    for i, x in enumerate(lats):
+        assert np.array_equal(rngx.ising_get_spins(x), spins0[i]), i
+        assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(x)), states0[i]), i
+        assert int(traces[i][0]) == 7  # tuning runs write no trace
+    assert rngx.ising_batch_status(batch) == 0
+    rngx.ising_batch_run(batch)
+    for i, tw in enumerate(twins):
+        tt = torch.zeros(sweeps[i], dtype=torch.int32, device="cuda")
+        rngx.ising_sweep(tw, betas[i], sweeps[i], tt)
+        assert torch.equal(traces[i], tt), (i, Ls[i])
+        assert np.array_equal(rngx.ising_get_spins(lats[i]), rngx.ising_get_spins(tw)), (i, Ls[i])
+        assert np.array_equal(rngx.rng_get_state(rngx.ising_rng(lats[i])),
+                              rngx.rng_get_state(rngx.ising_rng(tw))), i
+
+
 def test_batch_small_replicas_match_oracle(rngx, orc):
     kind = "xs1024w"
     Ls, betas, sweeps = [16, 48, 96], [0.31, 0.44, 0.58], [3, 5, 2]
