@@ -447,8 +447,8 @@ def main():
                     help="for rocprofv3: `steps` Ising calls of 200 sweeps each at L=4096, beta=0.4 "
                          "(energy trace on) of --profile-kind (default xs1024w); prints no JSON")
     ap.add_argument("--profile-fill", action="store_true",
-                    help="for rocprofv3: `steps` u32 fills of 2^20 x 4096 of --profile-kind, then `steps` "
-                         "consume calls of the same size; prints no JSON")
+                    help="for rocprofv3: the fill autotuner, then `steps` u32 fills of 2^20 x 4096 of "
+                         "--profile-kind, then `steps` consume calls of the same size; prints no JSON")
     ap.add_argument("--profile-kind", default="xs1024w")
     ap.add_argument("--profile-batch", action="store_true",
                     help="for rocprofv3: `steps` runs of the 512-replica XS1024W batch (L in 16..1024, "
@@ -470,6 +470,7 @@ def main():
         kind = args.profile_kind
         g = rx.rng_create(kind, S_FULL, 1)
         out = torch.empty(S_FULL * COUNT_FULL, dtype=torch.int32, device="cuda")
+        rx.rng_autotune_fill(g, out, COUNT_FULL, reps=1)  # the configuration the bench times
         for _ in range(args.steps):
             rx.rng_fill_u32(g, out, COUNT_FULL)
         acc = torch.empty(S_FULL, dtype=torch.int32, device="cuda")
