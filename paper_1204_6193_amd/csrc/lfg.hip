@@ -12,8 +12,13 @@
 //
 // Fill / consume: one wave per instance (workgroups of four waves, four
 // instances), runs of 64 V values (V per lane), wave-synchronous with no
-// barrier.  Seeding and jump-ahead are plain per-instance kernels.  The
-// Ising consumer is in ising.hip.
+// barrier.  At 2^20 streams there are only 1024 instances, one wave per SIMD,
+// so nothing hides a run's LDS latency and the run's instruction count sets
+// the rate: the fill keeps every value twice, at q mod B and q mod B + B, so
+// that a run's reads [x, x + 64 V) never wrap and every LDS address of a run
+// is one base (uniform plus the lane) and an immediate offset.  Seeding and
+// jump-ahead are plain per-instance kernels.  The Ising consumer is in
+// ising.hip.
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -36,13 +41,14 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Ring geometry of the fill kernel: runs of 64 V values, V per lane.
+// Ring geometry of the fill kernel: runs of 64 V values, V per lane; B a
+// power of two >= r + P (and a multiple of P, so a run's writes never wrap).
 template <int R, int SL>
 struct LfgFill {
     static constexpr int V = SL >= 512 ? 8 : 4;  // 64 V <= s
     static constexpr int P = 64 * V;             // values per run (divides 1024)
     static constexpr int B = (R + P) <= 1024 ? 1024 : (R + P) <= 2048 ? 2048 : 4096;
-    static_assert(P <= SL && 1024 % P == 0, "run longer than the short lag");
+    static_assert(P <= SL && 1024 % P == 0 && B % P == 0, "run longer than the short lag");
 };
 
 // `count` rows (1024 values) of every instance; MODE as the other fills.
@@ -53,7 +59,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_fill_lfg(uint8_t *st, uint64_t 
                                                          uint32_t *ring) {
     using F = LfgFill<R, SL>;
     constexpr int V = F::V, P = F::P, B = F::B, RUNS = 1024 / P;
-    __shared__ uint32_t rings[kWaves][B];
+    __shared__ uint32_t rings[kWaves][2 * B];  // value q at [q mod B] and [q mod B + B]
     __shared__ uint32_t s_free;
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * kWaves + w;
@@ -63,7 +69,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_fill_lfg(uint8_t *st, uint64_t 
     uint32_t *rg = rings[w];
     uint32_t *X = reinterpret_cast<uint32_t *>(st) + (live ? g : 0) * R;
     if (live)
-        for (int j = lane; j < R; j += 64) rg[B - R + j] = X[j];  // x_{j-r} at (j - r) mod B
+        for (int j = lane; j < R; j += 64) {  // x_{j-r} at (j - r) mod B, twice
+            const uint32_t x = X[j];
+            rg[B - R + j] = x;
+            rg[2 * B - R + j] = x;
+        }
     wave_lds_sync();
     uint32_t acc[RUNS * V];
 #pragma unroll
@@ -76,14 +86,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_fill_lfg(uint8_t *st, uint64_t 
         for (uint64_t k = k0; k < k1; ++k) {
 #pragma unroll
             for (int f = 0; f < RUNS; ++f) {
+                // q is a multiple of P and B of P: the run writes [q mod B,
+                // q mod B + P) < B, and reads from bases below B that the
+                // second copy extends past B
+                const uint32_t *lag_r = rg + ((q - R) & (B - 1)) + lane;
+                const uint32_t *lag_s = rg + ((q - SL) & (B - 1)) + lane;
+                uint32_t *dst = rg + (q & (B - 1)) + lane;
                 uint32_t v[V];
 #pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    const uint32_t qq = q + 64 * j + lane;
-                    v[j] = rg[(qq - R) & (B - 1)] + rg[(qq - SL) & (B - 1)];
-                }
+                for (int j = 0; j < V; ++j) v[j] = lag_r[64 * j] + lag_s[64 * j];
 #pragma unroll
-                for (int j = 0; j < V; ++j) rg[(q + 64 * j + lane) & (B - 1)] = v[j];
+                for (int j = 0; j < V; ++j) {
+                    dst[64 * j] = v[j];
+                    dst[64 * j + B] = v[j];
+                }
                 if constexpr (MODE == kOutXor) {
 #pragma unroll
                     for (int j = 0; j < V; ++j) acc[f * V + j] ^= v[j];
