@@ -412,11 +412,12 @@ rngx_status ising_batch_info(rngx_ising_batch b, uint32_t *n_items, uint32_t *re
  * restores every replica's spins, stream states and status as they were
  * (saved to device memory the call allocates and frees); ms_out (may be
  * NULL, else one entry per shape of ising_batch_shapes) receives the mean
- * run time of each shape.  Re-planning frees the device buffers a run reads: a graph captured
- * before ising_batch_set_shape or ising_batch_autotune must not be replayed
- * after it.  Errors: RNGX_E_INVALID (bad index, max_sweeps or reps = 0),
- * RNGX_E_NOMEM, RNGX_E_HIP (if re-planning fails the batch's runs return
- * RNGX_E_HIP until a shape is set again). */
+ * run time of each shape; synchronizes the device.  Re-planning frees the
+ * device buffers a run reads: a graph captured before ising_batch_set_shape
+ * or ising_batch_autotune must not be replayed after it.  Errors:
+ * RNGX_E_INVALID (bad index, max_sweeps or reps = 0), RNGX_E_NOMEM,
+ * RNGX_E_HIP (if re-planning fails the batch's runs return RNGX_E_HIP
+ * until a shape is set again). */
 typedef struct {
     uint32_t threads;          /* per workgroup: 256, 512 or 1024              */
     uint32_t sites_per_thread; /* most lattice sites per thread in a workgroup */

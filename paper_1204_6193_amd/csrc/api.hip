@@ -995,7 +995,7 @@ rngx_status ising_batch_autotune(rngx_ising_batch h, uint64_t max_sweeps, int32_
     };
     const int start_shape = b->shape;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    e = hipStreamSynchronize(st);
+    e = hipDeviceSynchronize();  // no earlier run, on any stream, still reads the plan it replaces
     if (e == hipSuccess) e = copy_all(true);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
