@@ -407,8 +407,11 @@ def test_batch_small_replicas_match_oracle(rngx, orc):
         assert np.array_equal(rngx.ising_get_spins(lats[i]).ravel(), sp)
 
 
-def test_batch_graph_replay(rngx):
-    """The batch run captured in a HIP graph: every replay equals an eager run."""
+@pytest.mark.parametrize("shape", [0, 4])
+def test_batch_graph_replay(rngx, shape):
+    """The batch run captured in a HIP graph (under the default launch shape
+    and the 256-thread one): every replay equals an eager run of a batch
+    left at the default shape."""
     kind = "xs1024w"
     Ls, betas, sweeps = _batch_case(rngx, kind, 9, n=10, max_L=256, big=(320,))
     a = [rngx.ising_create(L, kind, 50 + i) for i, L in enumerate(Ls)]
@@ -417,6 +420,7 @@ def test_batch_graph_replay(rngx):
     tb = [torch.zeros(s, dtype=torch.int32, device="cuda") for s in sweeps]
     ba = rngx.ising_batch_create(a, betas, sweeps, ta)
     bb = rngx.ising_batch_create(b, betas, sweeps, tb)
+    rngx.ising_batch_set_shape(ba, shape)
     s = torch.cuda.Stream()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=s):
