@@ -904,6 +904,74 @@ __global__ __launch_bounds__(1024) void k_ising_pass_lfg(PassArgs a) {
     }
 }
 
+// Single-hit passes with T < 1024 threads per instance, U = 1024 / T units
+// per thread (unit j of the instance on thread j mod T): every workgroup is a
+// chain of dependent steps (window and spin loads, a barrier per run of new
+// values, stores) whose latency one 1024-thread workgroup per SIMD pair
+// cannot hide; smaller workgroups put several instances on each CU.  The
+// units' spin words are loaded before the window so that both loads are in
+// flight together, and each row is made in runs of at most s values as in
+// LfgPassUnit.  Same draws, spins and energies as k_ising_pass_lfg.
+template <int R, int SL, int T>
+__global__ __launch_bounds__(T) void k_ising_pass_lfg_n(PassArgs a) {
+    constexpr int U = 1024 / T;
+    constexpr uint32_t B = LfgPassUnit<R, SL>::B;
+    __shared__ uint32_t ring[B];
+    __shared__ int red[T / 64];
+    const uint32_t t = threadIdx.x, L = a.L, upr = L / 4;
+    uint8_t *sp = reinterpret_cast<uint8_t *>(a.spins);
+    uint64_t w[U], m[U], at[U];
+    int p[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint64_t k = static_cast<uint64_t>(blockIdx.x) * 1024 + t + i * T;
+        const uint64_t y = k / upr;
+        const uint32_t x0 = static_cast<uint32_t>(k % upr) * 4;
+        const uint64_t row = y * L, up_row = (y == 0 ? L - 1 : y - 1) * static_cast<uint64_t>(L);
+        const uint64_t dn_row = (y == L - 1 ? 0 : y + 1) * static_cast<uint64_t>(L);
+        w[i] = lds_run<4>(sp + row + x0);
+        const uint64_t upw = lds_run<4>(sp + up_row + x0), dnw = lds_run<4>(sp + dn_row + x0);
+        const uint32_t lb = sp[row + (x0 == 0 ? L - 1 : x0 - 1)];
+        const uint32_t rb = sp[row + (x0 + 4 == L ? 0 : x0 + 4)];
+        m[i] = mismatches<4>(w[i], upw, dnw, lb, rb);
+        p[i] = static_cast<int>((a.c + y) & 1);
+        at[i] = row + x0;
+    }
+    uint32_t *X = reinterpret_cast<uint32_t *>(a.st) + static_cast<uint64_t>(blockIdx.x) * R;
+    for (uint32_t j = t; j < R; j += T) ring[B - R + j] = X[j];
+    __syncthreads();
+    // the pass's two rows: value j of row d is draw d of unit j
+    uint32_t r[U][2];
+    uint32_t q = 0;
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        for (uint32_t b = 0; b < 1024; b += SL) {
+            const uint32_t len = min(static_cast<uint32_t>(SL), 1024 - b);
+            for (uint32_t j = t; j < len; j += T) {
+                const uint32_t qq = q + b + j;
+                ring[qq & (B - 1)] = ring[(qq - R) & (B - 1)] + ring[(qq - SL) & (B - 1)];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) r[i][d] = ring[(q + t + i * T) & (B - 1)];
+        q += 1024;
+    }
+    int sh = 0;
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        sh += metropolis(w[i], m[i], p[i], r[i][0], a.T4, a.T8);
+        sh += metropolis(w[i], m[i], p[i] + 2, r[i][1], a.T4, a.T8);
+        lds_put<4>(sp + at[i], w[i]);
+    }
+    // the second row's barrier has passed and no thread writes the ring again
+    for (uint32_t j = t; j < R; j += T) X[j] = ring[(q - R + j) & (B - 1)];
+    if (a.partial) {
+        const int tot = block_sum(sh, red);
+        if (t == 0) a.partial[blockIdx.x] = tot;
+    }
+}
+
 // L = 64: the lattice is one instance, so one workgroup runs every sweep of
 // the call in one launch, the window staying in LDS throughout; the spins
 // stay in memory and a barrier separates the passes.
@@ -1435,6 +1503,8 @@ bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
 }
 
 namespace {
+constexpr int kLfgPassThreads = 256;  // single-hit LFG passes: four units per thread
+
 template <int R, int SL, bool MH>
 hipError_t run_passes_lfg(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st,
                           uint32_t hits) {
@@ -1444,7 +1514,11 @@ hipError_t run_passes_lfg(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int3
         for (int c = 0; c < 2; ++c) {
             pa.c = c;
             pa.partial = (c == 1 && tr) ? lat->d_partial : nullptr;
-            hipLaunchKernelGGL((k_ising_pass_lfg<R, SL, MH>), dim3(static_cast<unsigned>(G)), dim3(1024), 0, st, pa);
+            if constexpr (MH)
+                hipLaunchKernelGGL((k_ising_pass_lfg<R, SL, true>), dim3(static_cast<unsigned>(G)), dim3(1024), 0, st, pa);
+            else
+                hipLaunchKernelGGL((k_ising_pass_lfg_n<R, SL, kLfgPassThreads>), dim3(static_cast<unsigned>(G)),
+                                   dim3(kLfgPassThreads), 0, st, pa);
         }
         if (tr) hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(1024), 0, st, lat->d_partial, G, tr + t);
     }
