@@ -779,11 +779,12 @@ template <class Unit, bool MH>
 __device__ __forceinline__ int unit_in_memory_with(Unit &u, uint8_t *sp, uint8_t *st, uint64_t S, uint32_t L,
                                                    uint64_t k, int c, uint64_t T4, uint64_t T8, uint32_t hits) {
     constexpr int NB = Unit::kNB;
-    const uint32_t upr = L / NB;
-    const uint64_t y = k / upr;
-    const uint32_t x0 = static_cast<uint32_t>(k % upr) * NB;
-    const uint64_t row = y * L, up_row = (y == 0 ? L - 1 : y - 1) * static_cast<uint64_t>(L);
-    const uint64_t dn_row = (y == L - 1 ? 0 : y + 1) * static_cast<uint64_t>(L);
+    // L <= 16384: unit indices and site offsets fit 32 bits (no 64-bit division)
+    const uint32_t upr = L / NB, k32 = static_cast<uint32_t>(k);
+    const uint32_t y = k32 / upr;
+    const uint32_t x0 = (k32 - y * upr) * NB;
+    const uint32_t row = y * L, up_row = (y == 0 ? L - 1 : y - 1) * L;
+    const uint32_t dn_row = (y == L - 1 ? 0 : y + 1) * L;
     uint64_t w = lds_run<NB>(sp + row + x0);
     const uint64_t upw = lds_run<NB>(sp + up_row + x0), dnw = lds_run<NB>(sp + dn_row + x0);
     const uint32_t lb = sp[row + (x0 == 0 ? L - 1 : x0 - 1)];
@@ -920,15 +921,17 @@ __global__ __launch_bounds__(T) void k_ising_pass_lfg_n(PassArgs a) {
     __shared__ int red[T / 64];
     const uint32_t t = threadIdx.x, L = a.L, upr = L / 4;
     uint8_t *sp = reinterpret_cast<uint8_t *>(a.spins);
-    uint64_t w[U], m[U], at[U];
+    uint64_t w[U], m[U];
+    uint32_t at[U];
     int p[U];
 #pragma unroll
     for (int i = 0; i < U; ++i) {
-        const uint64_t k = static_cast<uint64_t>(blockIdx.x) * 1024 + t + i * T;
-        const uint64_t y = k / upr;
-        const uint32_t x0 = static_cast<uint32_t>(k % upr) * 4;
-        const uint64_t row = y * L, up_row = (y == 0 ? L - 1 : y - 1) * static_cast<uint64_t>(L);
-        const uint64_t dn_row = (y == L - 1 ? 0 : y + 1) * static_cast<uint64_t>(L);
+        // L <= 16384: unit indices and site offsets fit 32 bits
+        const uint32_t k = blockIdx.x * 1024 + t + i * T;
+        const uint32_t y = k / upr;
+        const uint32_t x0 = (k - y * upr) * 4;
+        const uint32_t row = y * L, up_row = (y == 0 ? L - 1 : y - 1) * L;
+        const uint32_t dn_row = (y == L - 1 ? 0 : y + 1) * L;
         w[i] = lds_run<4>(sp + row + x0);
         const uint64_t upw = lds_run<4>(sp + up_row + x0), dnw = lds_run<4>(sp + dn_row + x0);
         const uint32_t lb = sp[row + (x0 == 0 ? L - 1 : x0 - 1)];
