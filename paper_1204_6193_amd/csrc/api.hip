@@ -582,7 +582,8 @@ rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *
         e = hipMalloc(&lat->d_halo, static_cast<size_t>(8) * lat->plan.nwg * L);
         lat->halo_nwg = lat->plan.nwg;
     }
-    if (e == hipSuccess && !lat->plan.strips) e = hipMalloc(&lat->d_partial, 4 * ising_partials(L));
+    // partials of the per-pass path (lagged Fibonacci multi-hit sweeps take it under any plan)
+    if (e == hipSuccess && (!lat->plan.strips || is_lfg(kind))) e = hipMalloc(&lat->d_partial, 4 * ising_partials(L));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         free_ising(lat);
@@ -647,7 +648,8 @@ hipError_t apply_plan(Ising *lat, const IsingPlan &p) {
         e = hipMalloc(&lat->d_halo, 8ull * p.nwg * L);
         if (e == hipSuccess) lat->halo_nwg = p.nwg;
     }
-    if (e == hipSuccess && !p.strips && !lat->d_partial) e = hipMalloc(&lat->d_partial, 4 * ising_partials(lat->L));
+    if (e == hipSuccess && (!p.strips || is_lfg(lat->gen->kind)) && !lat->d_partial)
+        e = hipMalloc(&lat->d_partial, 4 * ising_partials(lat->L));
     if (e == hipSuccess && lat->d_halo)
         e = launch_zero(reinterpret_cast<uint32_t *>(lat->d_halo), 2ull * lat->halo_nwg * L, nullptr);
     if (e == hipSuccess) e = launch_zero(lat->d_err, 1, nullptr);

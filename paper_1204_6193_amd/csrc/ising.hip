@@ -185,6 +185,36 @@ template <int ROUNDS> struct SweepCounter<PhiloxSweepUnitR<ROUNDS>> : std::true_
 template <class Unit> struct PhiloxSweepOf { using type = void; };  // the sweep form of a Philox unit
 template <int ROUNDS> struct PhiloxSweepOf<PhiloxUnitR<ROUNDS>> { using type = PhiloxSweepUnitR<ROUNDS>; };
 
+// Lagged Fibonacci units in strips (single-hit).  A strip holds whole
+// instances (1024 units each) and runs 1024 threads, so slot i of thread t is
+// stream t of the strip's instance i.  Before each colour pass the workgroup
+// makes that pass's two rows of every instance of the strip in LDS rings of B
+// words (value v at v mod B; runs of at most kRun values, a barrier each,
+// whose reads and writes never share a ring word) and each thread takes
+// value t of both rows for every slot; the unit only hands them out, in the
+// order of the per-pass path (row 1 to the first colour-c site, row 2 to the
+// second).
+template <int LR, int LS>
+struct LfgStripUnit {
+    static constexpr int kNB = 4;
+    static constexpr uint32_t kR = LR, kS = LS;
+    static constexpr uint32_t B = LR < 1024 ? 1024 : 2048;
+    static constexpr uint32_t kRun = (B - LR) < static_cast<uint32_t>(LS) ? B - LR : LS;
+    static_assert(B >= LR + 1 && kRun >= 1, "ring too small");
+    uint32_t d0, d1;
+    __device__ void load(const uint8_t *, uint64_t, uint64_t) {}
+    __device__ void store(uint8_t *, uint64_t, uint64_t, uint64_t) const {}
+    __device__ void draw(uint32_t (&r)[2]) { r[0] = d0; r[1] = d1; }
+};
+template <class Unit> struct IsLfgStrip : std::false_type {};
+template <int LR, int LS> struct IsLfgStrip<LfgStripUnit<LR, LS>> : std::true_type {};
+// LDS of the rings of a strip's instances (after the strip's own bytes).
+template <class Unit>
+__host__ __device__ constexpr uint64_t lfg_ring_bytes(uint32_t units) {
+    if constexpr (IsLfgStrip<Unit>::value) return 4ull * Unit::B * (units / 1024) + 16;
+    else return 0;
+}
+
 // XS1024W lane pair u: lane u%16 of instance u/16 of the handle (words 2u,
 // 2u+1 = streams 2u and 2u+1).  Two instance steps per pass; the draws are
 // ordered stream 2u first, stream 2u+1 second, each in step order.
@@ -538,7 +568,9 @@ __device__ __forceinline__ void edge_ghosts(uint8_t *run, uint32_t pl, uint32_t 
 // otherwise spill.  The batch kernel keeps them in registers (its LDS budget
 // is tighter).
 template <class Unit, int SPT>
-__host__ __device__ constexpr bool place_in_lds() { return SPT * (sizeof(Unit) / 4 + 1) >= 40; }
+__host__ __device__ constexpr bool place_in_lds() {
+    return !IsLfgStrip<Unit>::value && SPT * (sizeof(Unit) / 4 + 1) >= 40;
+}
 
 template <class Unit, int SPT, bool EARLY, bool PLDS, bool MH = false>
 __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8_t *lds) {
@@ -579,6 +611,20 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
         }
     }
     const Accept A = make_accept(a.T4, a.T8);
+
+    // lagged Fibonacci: the windows of the strip's instances into their rings
+    // (ordered before use by the barrier that starts every pass)
+    uint32_t *rings = reinterpret_cast<uint32_t *>(lds + ((strip_lds_bytes(L, R) + 15) & ~15ull));
+    uint32_t lq = 0;  // index of the next value of every instance of the strip
+    if constexpr (IsLfgStrip<Unit>::value) {
+        constexpr uint32_t LR = Unit::kR, RB = Unit::B;
+        const uint32_t n_inst = a.units / 1024;
+        const uint32_t *X = reinterpret_cast<const uint32_t *>(a.st) + (ubase / 1024) * LR;
+        for (uint32_t idx = t; idx < n_inst * LR; idx += nt) {
+            const uint32_t i = idx / LR, j = idx - i * LR;
+            rings[i * RB + RB - LR + j] = X[idx];
+        }
+    }
 
     const uint32_t up_wg = (r + nwg - 1) % nwg, dn_wg = (r + 1) % nwg;
     // EARLY: top row entirely in slot 0 and bottom row entirely in slot
@@ -621,6 +667,35 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
             if (t < 2 * W) pre0 = __hip_atomic_load(src_word(t), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (t + nt < 2 * W) pre1 = __hip_atomic_load(src_word(t + nt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         };
+        if constexpr (IsLfgStrip<Unit>::value) {
+            constexpr uint32_t LR = Unit::kR, LS = Unit::kS, RB = Unit::B, RUN = Unit::kRun;
+            constexpr uint32_t NR = (1024 + RUN - 1) / RUN;
+            const uint32_t n_inst = a.units / 1024;
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+#pragma unroll
+                for (uint32_t rr = 0; rr < NR; ++rr) {
+                    constexpr uint32_t kLast = 1024 - (NR - 1) * RUN;
+                    const uint32_t len = rr + 1 < NR ? RUN : kLast;
+                    const uint32_t v0 = lq + rr * RUN;
+                    for (uint32_t idx = t; idx < n_inst * len; idx += nt) {
+                        const uint32_t i = idx / len, v = v0 + (idx - i * len);
+                        uint32_t *rg = rings + i * RB;
+                        rg[v & (RB - 1)] = rg[(v - LR) & (RB - 1)] + rg[(v - LS) & (RB - 1)];
+                    }
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int i = 0; i < SPT; ++i)  // slot i: instance i, stream t (1024 threads)
+                    if (t + i * nt < a.units) {
+                        const uint32_t val = rings[i * RB + ((lq + t) & (RB - 1))];
+                        if (d == 0) u[i].d0 = val;
+                        else u[i].d1 = val;
+                    }
+                if (RB < 2048 && d == 0) __syncthreads();  // row 1 read before row 2 overwrites it
+                lq += 1024;
+            }
+        }
         uint32_t esum = 0;
         const uint32_t zero = *zero_word;
 #pragma unroll
@@ -696,6 +771,15 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
 
     // write back spins and state
     copy_strip<false>(lds + P + kPad, a.spins + row0 * L, L, R, t, nt);
+    if constexpr (IsLfgStrip<Unit>::value) {  // the last r values of every instance
+        constexpr uint32_t LR = Unit::kR, RB = Unit::B;
+        const uint32_t n_inst = a.units / 1024;
+        uint32_t *X = reinterpret_cast<uint32_t *>(a.st) + (ubase / 1024) * LR;
+        for (uint32_t idx = t; idx < n_inst * LR; idx += nt) {
+            const uint32_t i = idx / LR, j = idx - i * LR;
+            X[idx] = rings[i * RB + ((lq - LR + j) & (RB - 1))];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < SPT; ++i) {
         const uint32_t k = t + i * nt;
@@ -1232,6 +1316,10 @@ bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out)
     if (spt > max_spt) return false;
     uint32_t threads = (units + spt - 1) / spt;
     threads = (threads + 63) / 64 * 64;
+    if constexpr (IsLfgStrip<Unit>::value) {  // whole instances, slot i = instance i on 1024 threads
+        if (units % 1024 || threads != 1024 || static_cast<uint32_t>(spt) * 1024 != units) return false;
+        lds = (lds + 15) / 16 * 16 + lfg_ring_bytes<Unit>(units);
+    }
     const bool early = plan_early(spt, L / NB, units, threads);
     if (place_lds_for<Unit>(spt)) lds += 4ull * spt * threads;
     if (lds > kLdsMax) return false;
@@ -1483,7 +1571,9 @@ int ising_plan_list(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out, int ma
     case RNGX_PHILOX4X32_10: return list_plans<PhiloxUnit>(L, 16, n_cu, out, max);
     case RNGX_PHILOX4X32_7: return list_plans<PhiloxUnit7>(L, 16, n_cu, out, max);
     case RNGX_XS1024W: return list_plans<XsUnit>(L, 16, n_cu, out, max);
-    default: break;  // lagged Fibonacci: per-pass kernels only
+    case RNGX_LFG521: return list_plans<LfgStripUnit<521, 353>>(L, 16, n_cu, out, max);
+    case RNGX_LFG1279: return list_plans<LfgStripUnit<1279, 861>>(L, 16, n_cu, out, max);
+    default: break;
     }
     return 0;
 }
@@ -1500,7 +1590,9 @@ bool ising_plan(uint32_t L, rngx_kind kind, int n_cu, IsingPlan *out) {
     case RNGX_PHILOX4X32_10: return plan_strips<PhiloxUnit>(L, 16, n_cu, out);
     case RNGX_PHILOX4X32_7: return plan_strips<PhiloxUnit7>(L, 16, n_cu, out);
     case RNGX_XS1024W: return plan_strips<XsUnit>(L, 16, n_cu, out);
-    default: break;  // lagged Fibonacci: per-pass kernels only
+    case RNGX_LFG521: return plan_strips<LfgStripUnit<521, 353>>(L, 16, n_cu, out);
+    case RNGX_LFG1279: return plan_strips<LfgStripUnit<1279, 861>>(L, 16, n_cu, out);
+    default: break;
     }
     return false;
 }
@@ -1538,6 +1630,8 @@ hipError_t run_one_lfg(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t
 template <int R, int SL>
 hipError_t run_lfg(Ising *lat, uint64_t T4, uint64_t T8, uint64_t n, int32_t *tr, hipStream_t st, uint32_t hits) {
     if (n == 0) return hipSuccess;
+    // single-hit sweeps on chip when a strip plan holds whole instances
+    if (hits == 1 && lat->plan.strips) return run_strips<LfgStripUnit<R, SL>, false>(lat, T4, T8, n, tr, st, 1);
     if (lat->gen->S == kLfgLanes) {
         if (hits == 1) return run_one_lfg<R, SL, false>(lat, T4, T8, n, tr, st, 1);
         return run_one_lfg<R, SL, true>(lat, T4, T8, n, tr, st, hits);

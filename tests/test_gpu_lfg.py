@@ -127,9 +127,14 @@ def test_full_size_sampled_parity(rngx, orc, kind):
     torch.cuda.empty_cache()
 
 
-def _run_both(rx, orc, L, kind, beta, chunks, hits=1, seed=1):
+def _run_both(rx, orc, L, kind, beta, chunks, hits=1, seed=1, plan=None, strips=None):
+    """plan: None keeps the planner's choice, 0 forces one launch per colour
+    pass; strips: the strip count the lattice must then have."""
     lat = rx.ising_create(L, kind, seed)
-    assert rx.ising_info(lat)["strips"] == 0  # one launch per colour pass
+    if plan is not None:
+        rx.ising_set_plan(lat, plan)
+    if strips is not None:
+        assert rx.ising_info(lat)["strips"] == strips, rx.ising_info(lat)
     sp, st = orc.ising_create(L, kind, seed)
     for n in chunks:
         tr = torch.zeros(n, dtype=torch.int32, device="cuda")
@@ -140,15 +145,36 @@ def _run_both(rx, orc, L, kind, beta, chunks, hits=1, seed=1):
         assert np.array_equal(rx.rng_get_state(rx.ising_rng(lat)), st), (L, kind, beta, hits)
 
 
+# strips the planner gives both kinds: whole instances per strip on 1024
+# threads (L = 1024: 256 strips of one instance), or none (L = 192: 9
+# instances of 48 units per row have no such split)
+PLANNED = {64: 1, 128: 1, 192: 0, 1024: 256}
+
+
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("L", [64, 128, 192, 1024])
 def test_ising_parity(rngx, orc, kind, L):
-    """Spins, energies and instance windows bit-exact: one instance (L = 64,
-    an instance spans 64 rows), several, an odd number of instances per row
-    band (192: 9 instances), and L = 1024 (256 instances of 4 rows)."""
+    """Spins, energies and instance windows bit-exact under the planner's
+    choice and one launch per colour pass: one instance (L = 64, an instance
+    spans 64 rows), several, an odd number of instances per row band (192:
+    9 instances, no strip plan), and L = 1024 (256 strips of one instance)."""
     print(f"case lfg ising {kind} L={L}", flush=True)
     for beta in (0.4, ex.BETA_C):
-        _run_both(rngx, orc, L, kind, beta, (5, 1, 4) if L < 1024 else (2, 1))
+        chunks = (5, 1, 4) if L < 1024 else (2, 1)
+        _run_both(rngx, orc, L, kind, beta, chunks, strips=PLANNED[L])
+        if PLANNED[L]:
+            _run_both(rngx, orc, L, kind, beta, chunks, plan=0, strips=0)
+
+
+@pytest.mark.parametrize("kind,L,strips", [("lfg521", 4096, 256), ("lfg1279", 2048, 256), ("lfg1279", 4096, 0)])
+def test_ising_strips_large(rngx, orc, kind, L, strips):
+    """The bench size: L = 4096 r = 521 runs as 256 strips of 16 instances,
+    each strip making its instances' rows in LDS rings; r = 1279 at L = 2048
+    (strips of 4 instances), and at L = 4096 where 16 rings of 8 KiB do not fit
+    beside a strip, one launch per colour pass.  Two sweeps then one against
+    the oracle."""
+    print(f"case lfg ising strips {kind} L={L}", flush=True)
+    _run_both(rngx, orc, L, kind, 0.4, (2, 1), strips=strips)
 
 
 @pytest.mark.parametrize("kind", KINDS)
@@ -168,7 +194,7 @@ def test_ising_rejections(rngx):
         rngx.ising_create(96, "lfg521", 1)
     assert e.value.status == -2
     lat = rngx.ising_create(64, "lfg521", 1)
-    assert rngx.ising_plans(lat) == [0]
+    assert rngx.ising_plans(lat) == [1, 0]  # the one instance on chip, or per pass
     with pytest.raises(rngx.RngxError):
         rngx.ising_batch_create([lat], [0.4], [1])
     g = rngx.rng_create("lfg1279", 1024, 1)
