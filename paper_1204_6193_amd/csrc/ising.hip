@@ -1386,7 +1386,7 @@ const void *batch_kernel_for(rngx_kind kind, uint32_t threads) {
     case RNGX_PHILOX4X32_10: return batch_kernel<PhiloxUnit>(threads);
     case RNGX_PHILOX4X32_7: return batch_kernel<PhiloxUnit7>(threads);
     case RNGX_XS1024W: return batch_kernel<XsUnit>(threads);
-    default: break;  // lagged Fibonacci: per-pass kernels only
+    default: break;  // lagged Fibonacci lattices are not batched
     }
     return nullptr;
 }
