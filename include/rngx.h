@@ -304,9 +304,12 @@ rngx_status rng_set_state(rngx_gen g, const void *host_buf, size_t bytes, void *
  * Synchronous.  Errors: RNGX_E_ALIGN unless L % 16 == 0 and L >= 16 (LFG
  * kinds: L % 64 == 0, whole 1024-stream instances), RNGX_E_OVERFLOW when
  * the kind cannot hold L*L/4 streams (MWC_DIFF: L > 2896).  LFG lattices
- * are swept one launch per colour pass, a workgroup per instance: it loads
- * the instance's window into LDS, generates the pass's values there row by
- * row and writes the window back. */
+ * run on chip when strips of whole instances fit (every strip keeps its
+ * instances' windows in LDS for the call and makes each pass's values there
+ * row by row; e.g. r = 521 up to L = 4096, r = 1279 up to L = 2048), else
+ * one launch per colour pass with a workgroup per instance; multi-hit
+ * sweeps of LFG lattices always take the per-pass form.  Either gives the
+ * same spins, energies and windows. */
 rngx_status ising_create(uint32_t L, rngx_kind kind, uint64_t seed, rngx_ising *out);
 
 /* Run n_sweeps checkerboard Metropolis sweeps at inverse temperature beta
