@@ -671,17 +671,25 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
             constexpr uint32_t LR = Unit::kR, LS = Unit::kS, RB = Unit::B, RUN = Unit::kRun;
             constexpr uint32_t NR = (1024 + RUN - 1) / RUN;
             const uint32_t n_inst = a.units / 1024;
+            const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63, n_waves = nt >> 6;
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
 #pragma unroll
                 for (uint32_t rr = 0; rr < NR; ++rr) {
                     constexpr uint32_t kLast = 1024 - (NR - 1) * RUN;
                     const uint32_t len = rr + 1 < NR ? RUN : kLast;
+                    const uint32_t nblk = (len + 63) / 64;  // 64-value blocks of the run per instance
                     const uint32_t v0 = lq + rr * RUN;
-                    for (uint32_t idx = t; idx < n_inst * len; idx += nt) {
-                        const uint32_t i = idx / len, v = v0 + (idx - i * len);
-                        uint32_t *rg = rings + i * RB;
-                        rg[v & (RB - 1)] = rg[(v - LR) & (RB - 1)] + rg[(v - LS) & (RB - 1)];
+                    // block b = (instance i, block m) goes to wave b mod (waves):
+                    // i and m are wave-uniform, lane l makes value 64 m + l
+                    for (uint32_t b = wave; b < n_inst * nblk; b += n_waves) {
+                        const uint32_t i = b / nblk, m = b - i * nblk;
+                        const uint32_t j = 64 * m + lane;
+                        if (j < len) {
+                            uint32_t *rg = rings + i * RB;
+                            const uint32_t v = v0 + j;
+                            rg[v & (RB - 1)] = rg[(v - LR) & (RB - 1)] + rg[(v - LS) & (RB - 1)];
+                        }
                     }
                     __syncthreads();
                 }
