@@ -413,7 +413,9 @@ __global__ __launch_bounds__(kBlock) void k_ragged_xs(const RaggedItem *items, u
                                                        const uint32_t *slots, uint32_t n_slots, const uint8_t *st,
                                                        uint64_t S, const uint32_t *t32, uint64_t chunk,
                                                        uint8_t *scratch, uint32_t *out) {
-    __shared__ uint32_t ring[kBlock / 16][64];
+    // 64-word ring per row, kept twice (word p at p and p + 64) so that a
+    // lane's pair never wraps
+    __shared__ uint32_t ring[kBlock / 16][128];
     const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t r = t >> 4;
     const uint32_t lane = static_cast<uint32_t>(t & 15), rl = threadIdx.x >> 4;
@@ -428,6 +430,10 @@ __global__ __launch_bounds__(kBlock) void k_ragged_xs(const RaggedItem *items, u
     uint32_t q = slots[r];
     RaggedItem it;
     uint32_t a, b, y, mis, len, kf, k;
+    // ring positions of the lane's pair: written (step k's words 2 lane, 2
+    // lane + 1 at 32 k mod 64) and read (line k at 32 k + 2 lane - mis mod 64),
+    // for the current parity of k; xor with *_flip moves to the other parity
+    uint32_t wcur, rcur, wflip, rflip;
     uint64_t n;
     int64_t nvals;
     uint32_t *o;
@@ -450,6 +456,10 @@ __global__ __launch_bounds__(kBlock) void k_ragged_xs(const RaggedItem *items, u
         const int64_t kf_ = (nvals + mis - 32) / 32;
         kf = kf_ <= 0 ? 0 : static_cast<uint32_t>(min(kf_, static_cast<int64_t>(len) - 1));
         k = 0;
+        wcur = 2 * lane;
+        wflip = 32;
+        rcur = (2 * lane - mis) & 63;
+        rflip = rcur ^ ((32 + 2 * lane - mis) & 63);
         // Loads complete here: stores share the memory counter, so a wait
         // left to the step loop would also wait for the stores.
         __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -458,8 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_ragged_xs(const RaggedItem *items, u
     while (true) {
         if (k == len) {
             {  // line len: the last mis words of step len-1
-                const uint32_t x = 32 * len + 2 * lane - mis;
-                const uint32_t f0 = rg[x & 63], f1 = rg[(x + 1) & 63];
+                const uint32_t f0 = rg[rcur], f1 = rg[rcur + 1];
                 __builtin_amdgcn_wave_barrier();
                 const int64_t v0 = 32 * static_cast<int64_t>(len) + 2 * lane - mis;
                 if (v0 < nvals) o[0] = f0;
@@ -476,11 +485,14 @@ __global__ __launch_bounds__(kBlock) void k_ragged_xs(const RaggedItem *items, u
         xs1024_step(a, b);
         y += kWeylC;
         const uint32_t m = weyl_mix(y);
-        *reinterpret_cast<uint2 *>(rg + ((32 * k + 2 * lane) & 63)) = make_uint2(a + m, b + m);
+        const uint2 pv = make_uint2(a + m, b + m);
+        *reinterpret_cast<uint2 *>(rg + wcur) = pv;
+        *reinterpret_cast<uint2 *>(rg + wcur + 64) = pv;
         __builtin_amdgcn_wave_barrier();
-        const uint32_t x = 32 * k + 2 * lane - mis;
-        const uint32_t w0 = rg[x & 63], w1 = rg[(x + 1) & 63];
+        const uint32_t w0 = rg[rcur], w1 = rg[rcur + 1];
         __builtin_amdgcn_wave_barrier();
+        wcur ^= wflip;
+        rcur ^= rflip;
         if (k - 1 < kf) {  // 1 <= k <= kf: a whole line
             __builtin_nontemporal_store(w0 | static_cast<uint64_t>(w1) << 32, reinterpret_cast<uint64_t *>(o));
         } else {
