@@ -481,6 +481,26 @@ __global__ __launch_bounds__(kBlock) void k_ragged_xs(const RaggedItem *items, u
             if (++q == q_end) break;
             begin();
         }
+        if (k >= 1 && k + 3 <= kf) {  // lines k .. k+3 whole: four steps with no tests
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                xs1024_step(a, b);
+                y += kWeylC;
+                const uint32_t m = weyl_mix(y);
+                const uint2 pv = make_uint2(a + m, b + m);
+                *reinterpret_cast<uint2 *>(rg + wcur) = pv;
+                *reinterpret_cast<uint2 *>(rg + wcur + 64) = pv;
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t w0 = rg[rcur], w1 = rg[rcur + 1];
+                __builtin_amdgcn_wave_barrier();
+                wcur ^= wflip;
+                rcur ^= rflip;
+                __builtin_nontemporal_store(w0 | static_cast<uint64_t>(w1) << 32, reinterpret_cast<uint64_t *>(o + 32 * j));
+            }
+            o += 128;
+            k += 4;
+            continue;  // k <= kf + 1 <= len: the chunk may end here
+        }
         // step k into the ring, then the lane's pair of line k
         xs1024_step(a, b);
         y += kWeylC;
