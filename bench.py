@@ -236,7 +236,8 @@ def bench_ising_batch(rx, n=512, sweeps=10000, seed=1):
 def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_requests=256):
     """10^4 requests with lengths log-uniform in [2^10, 2^22] (numpy
     default_rng(seed)); XS1024W requests are per instance.  One ragged call
-    (3 timed after 1 warm-up) vs the plain form, one launch per request: a
+    (3 timed after 1 warm-up, the plan's shape autotuned first) vs the plain
+    form, one launch per request: a
     generator of one stream (XS1024W: one instance) per request, created
     before the timed region, fills its request at its offset.  The plain form
     is timed over `baseline_requests` requests drawn at random without
@@ -250,6 +251,8 @@ def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_requests=256):
     g = rx.rng_create(kind, S, 1)
     plan = rx.rng_ragged_create(g, off)
     out = torch.empty(int(off[-1]) + 32, dtype=torch.int32, device="cuda")
+    tune_ms = rx.rng_ragged_autotune(plan, out, reps=1)
+    shape = rx.rng_ragged_shapes(kind)[rx.rng_ragged_get_shape(plan)]
     durs, _ = time_launches(lambda: rx.rng_fill_ragged_u32(plan, out), 3, 1)
     ms = sum(durs) / len(durs)
     total = int(off[-1])
@@ -277,6 +280,7 @@ def bench_ragged(rx, kind="xs1024w", n=10000, seed=1, baseline_requests=256):
     return {"kind": kind, "requests": n, "values": total, "ms": round(ms, 3),
             "gsamples_s": round(total / ms / 1e6, 2), "gbs": round(total * 4 / ms / 1e6, 1),
             "hbm_frac": round(total * 4 / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "shape": shape, "tune_ms": [round(m, 3) for m in tune_ms],
             "per_launch_requests": len(pick), "per_launch_values": sub, "per_launch_ms": round(durs[0], 2),
             "per_launch_gsamples_s": round(sub / durs[0] / 1e6, 3)}
 

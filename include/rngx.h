@@ -268,6 +268,29 @@ rngx_status rng_ragged_create(rngx_gen g, const uint64_t *offsets, uint64_t n_of
 rngx_status rng_fill_ragged_u32(rngx_ragged r, uint32_t *d_out, void *stream);
 rngx_status rng_ragged_destroy(rngx_ragged r);
 
+/* Shapes of a ragged plan and their autotuner.  The value of a shape is, for
+ * XS1024W, the generating rows per compute unit (fewer rows: fewer jumps at
+ * row starts, less parallelism), else the outputs per chunk (a lane's or a
+ * wave's; smaller chunks: more jumps, better balance).  Every shape writes
+ * the same values and leaves the same stream states.
+ * rng_ragged_shapes: the values for `kind` in index order (shape 0, the
+ * default, first); values (n entries) may be NULL to ask for *n only.
+ * rng_ragged_set_shape: re-plan with shape `index`; synchronizes the device.
+ * rng_ragged_autotune: times every shape on `reps` (>= 1) fills into d_out
+ * (overwritten; as for rng_fill_ragged_u32) after one warm-up fill, keeps the
+ * fastest and restores the streams to their state before the call (saved to
+ * device memory the call allocates and frees); ms_out (may be NULL, else one
+ * entry per shape) receives the mean fill time of each shape; synchronizes
+ * the device.  Re-planning frees the device buffers a fill reads: a graph
+ * captured before either call must not be replayed after it.  Errors:
+ * RNGX_E_INVALID (kind without ragged fills, bad index, reps < 1, NULL),
+ * RNGX_E_NOMEM, RNGX_E_HIP (if re-planning fails, fills return RNGX_E_HIP
+ * until a shape is set again). */
+rngx_status rng_ragged_shapes(rngx_kind kind, uint64_t *values, int32_t *n);
+rngx_status rng_ragged_set_shape(rngx_ragged r, int32_t index);
+rngx_status rng_ragged_get_shape(rngx_ragged r, int32_t *index);
+rngx_status rng_ragged_autotune(rngx_ragged r, uint32_t *d_out, int32_t reps, float *ms_out, void *stream);
+
 /* For callers that cannot allocate device memory (code that must not call
  * hipMalloc: tight serving loops, harnesses that forbid it): the same fill
  * as rng_ragged_create(g, offsets, n_offsets) followed by

@@ -46,6 +46,10 @@ SIGNATURES = {
     "rng_ragged_create": (_i32, [_vp, _vp, _u64, ctypes.POINTER(_vp)]),
     "rng_fill_ragged_u32": (_i32, [_vp, _vp, _vp]),
     "rng_ragged_destroy": (_i32, [_vp]),
+    "rng_ragged_shapes": (_i32, [_i32, ctypes.POINTER(_u64), ctypes.POINTER(_i32)]),
+    "rng_ragged_set_shape": (_i32, [_vp, _i32]),
+    "rng_ragged_get_shape": (_i32, [_vp, ctypes.POINTER(_i32)]),
+    "rng_ragged_autotune": (_i32, [_vp, _vp, _i32, _vp, _vp]),
     "rng_fill_ragged_u32_noalloc": (_i32, [_vp, _vp, _u64, _vp, _vp]),
     "rng_get_state": (_i32, [_vp, _vp, ctypes.POINTER(_sz), _vp]),
     "rng_set_state": (_i32, [_vp, _vp, _sz, _vp]),
@@ -294,6 +298,35 @@ def rng_fill_ragged_u32(r: Ragged, out, stream=None):
 
 def rng_ragged_destroy(r: Ragged):
     r.destroy()
+
+
+def rng_ragged_shapes(kind) -> list[int]:
+    """The ragged shape values of `kind` in index order (XS1024W: rows per CU; else outputs per chunk)."""
+    n = ctypes.c_int()
+    _check(load().rng_ragged_shapes(_kind(kind), None, ctypes.byref(n)))
+    arr = (_u64 * n.value)()
+    _check(load().rng_ragged_shapes(_kind(kind), arr, ctypes.byref(n)))
+    return [int(v) for v in arr]
+
+
+def rng_ragged_set_shape(r: Ragged, index: int):
+    _check(load().rng_ragged_set_shape(r.handle, int(index)))
+
+
+def rng_ragged_get_shape(r: Ragged) -> int:
+    v = ctypes.c_int()
+    _check(load().rng_ragged_get_shape(r.handle, ctypes.byref(v)))
+    return v.value
+
+
+def rng_ragged_autotune(r: Ragged, out, reps: int = 2, stream=None) -> list[float]:
+    """Time every ragged shape on fills into `out` (overwritten), keep the fastest and restore the
+    streams; returns the mean fill time (ms) of each shape."""
+    n = len(rng_ragged_shapes(r.gen.kind))
+    ms = (ctypes.c_float * n)()
+    _check(load().rng_ragged_autotune(r.handle, _dptr(out, r.total, 4), int(reps), ctypes.cast(ms, _vp),
+                                      _stream(stream)))
+    return list(ms)
 
 
 def rng_fill_ragged_u32_noalloc(g: Gen, offsets, out, stream=None):

@@ -71,15 +71,71 @@ rngx_status check_ragged(rngx_ragged h, Ragged **r) {
     return RNGX_OK;
 }
 
-void free_ragged(Ragged *r) {
+// The plan's device buffers.
+void ragged_release(Ragged *r) {
     (void)hipFree(r->d_items);
     (void)hipFree(r->d_scratch);
     (void)hipFree(r->d_t64);
     (void)hipFree(r->d_t32);
     (void)hipFree(r->d_slots);
     (void)hipFree(r->d_lane);
+    r->d_items = nullptr;
+    r->d_scratch = nullptr;
+    r->d_t64 = r->d_lane = nullptr;
+    r->d_t32 = r->d_slots = nullptr;
+    r->n_items = 0;
+    r->n_slots = 0;
+}
+
+void free_ragged(Ragged *r) {
+    ragged_release(r);
     r->magic = 0;
     delete r;
+}
+
+// (Re)builds r's plan from r->offsets under r->shape: work items, jump
+// tables, lane maps, row slots and chunk-state scratch on the device.
+rngx_status ragged_build(Ragged *r) {
+    Gen *g = r->gen;
+    ragged_release(r);
+    const uint64_t units = r->offsets.size() - 1;
+    RaggedPlan plan;
+    ragged_plan(g->kind, r->offsets.data(), units, g->n_cu, &plan, r->shape);
+    const std::vector<RaggedItem> &items = plan.items;
+    if (items.size() > 0xFFFFFFFFull) return fail(RNGX_E_OVERFLOW, "too many chunks in one ragged plan");
+    std::vector<uint64_t> t64;
+    std::vector<uint32_t> t32;
+    jump_table_gen(g, plan.step, plan.max_j + 1, &t64, &t32);
+    r->total = r->offsets[units];
+    r->step = plan.step;
+    r->n_slots = plan.slots.empty() ? 0 : static_cast<uint32_t>(plan.slots.size() - 1);
+    hipError_t e = hipSuccess;
+    if (!items.empty()) {
+        e = hipMalloc(&r->d_items, sizeof(RaggedItem) * items.size());
+        if (e == hipSuccess && ragged_lane_table(g->kind)) {
+            std::vector<uint64_t> lane;
+            ragged_lane_maps(g, &lane);
+            e = hipMalloc(&r->d_lane, 8 * lane.size());
+            if (e == hipSuccess) e = hipMemcpy(r->d_lane, lane.data(), 8 * lane.size(), hipMemcpyHostToDevice);
+        }
+        if (e == hipSuccess && !plan.slots.empty()) e = hipMalloc(&r->d_slots, 4 * plan.slots.size());
+        if (e == hipSuccess && !plan.slots.empty())
+            e = hipMemcpy(r->d_slots, plan.slots.data(), 4 * plan.slots.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&r->d_scratch, ragged_scratch_bytes(g->kind, items.size()));
+        if (e == hipSuccess && !t64.empty()) e = hipMalloc(&r->d_t64, 8 * t64.size());
+        if (e == hipSuccess && !t32.empty()) e = hipMalloc(&r->d_t32, 4 * t32.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(r->d_items, items.data(), sizeof(RaggedItem) * items.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !t64.empty()) e = hipMemcpy(r->d_t64, t64.data(), 8 * t64.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !t32.empty()) e = hipMemcpy(r->d_t32, t32.data(), 4 * t32.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        ragged_release(r);
+        (void)hipGetLastError();
+        return fail(RNGX_E_NOMEM, std::string("ragged plan allocation failed: ") + hipGetErrorString(e));
+    }
+    r->n_items = items.size();
+    return RNGX_OK;
 }
 
 void free_batch(IsingBatch *b) {
@@ -409,45 +465,16 @@ rngx_status rng_ragged_create(rngx_gen h, const uint64_t *offsets, uint64_t n_of
         if (offsets[u + 1] < offsets[u]) return fail(RNGX_E_INVALID, "offsets decrease at " + std::to_string(u));
     uint64_t bytes;
     if (mul_overflows(offsets[units], 4, &bytes)) return fail(RNGX_E_OVERFLOW, "output size overflows");
-    RaggedPlan plan;
-    ragged_plan(g->kind, offsets, units, g->n_cu, &plan);
-    const std::vector<RaggedItem> &items = plan.items;
-    if (items.size() > 0xFFFFFFFFull) return fail(RNGX_E_OVERFLOW, "too many chunks in one ragged plan");
-    std::vector<uint64_t> t64;
-    std::vector<uint32_t> t32;
-    jump_table_gen(g, plan.step, plan.max_j + 1, &t64, &t32);
     DeviceScope ds(g->device);
     Ragged *r = new Ragged{};
     r->magic = kRaggedMagic;
     r->gen = g;
-    r->n_items = items.size();
-    r->total = offsets[units];
-    r->step = plan.step;
-    r->n_slots = plan.slots.empty() ? 0 : static_cast<uint32_t>(plan.slots.size() - 1);
-    hipError_t e = hipSuccess;
-    if (!items.empty()) {
-        e = hipMalloc(&r->d_items, sizeof(RaggedItem) * items.size());
-        if (e == hipSuccess && ragged_lane_table(g->kind)) {
-            std::vector<uint64_t> lane;
-            ragged_lane_maps(g, &lane);
-            e = hipMalloc(&r->d_lane, 8 * lane.size());
-            if (e == hipSuccess) e = hipMemcpy(r->d_lane, lane.data(), 8 * lane.size(), hipMemcpyHostToDevice);
-        }
-        if (e == hipSuccess && !plan.slots.empty()) e = hipMalloc(&r->d_slots, 4 * plan.slots.size());
-        if (e == hipSuccess && !plan.slots.empty())
-            e = hipMemcpy(r->d_slots, plan.slots.data(), 4 * plan.slots.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMalloc(&r->d_scratch, ragged_scratch_bytes(g->kind, items.size()));
-        if (e == hipSuccess && !t64.empty()) e = hipMalloc(&r->d_t64, 8 * t64.size());
-        if (e == hipSuccess && !t32.empty()) e = hipMalloc(&r->d_t32, 4 * t32.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(r->d_items, items.data(), sizeof(RaggedItem) * items.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess && !t64.empty()) e = hipMemcpy(r->d_t64, t64.data(), 8 * t64.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess && !t32.empty()) e = hipMemcpy(r->d_t32, t32.data(), 4 * t32.size(), hipMemcpyHostToDevice);
-    }
-    if (e != hipSuccess) {
+    r->shape = 0;
+    r->offsets.assign(offsets, offsets + units + 1);
+    if (rngx_status st = ragged_build(r)) {
+        const std::string msg = g_error;
         free_ragged(r);
-        (void)hipGetLastError();
-        return fail(RNGX_E_NOMEM, std::string("ragged plan allocation failed: ") + hipGetErrorString(e));
+        return fail(st, msg);
     }
     ++g->plans;
     reg(r);
@@ -482,9 +509,109 @@ rngx_status rng_fill_ragged_u32(rngx_ragged h, uint32_t *d_out, void *stream) {
     if (rngx_status s = check_ragged(h, &r)) return s;
     if (!d_out && r->total) return fail(RNGX_E_INVALID, "output pointer is NULL");
     if (reinterpret_cast<uintptr_t>(d_out) % 4) return fail(RNGX_E_ALIGN, "output must be 4-byte aligned");
+    if (r->total && !r->d_items) return fail(RNGX_E_HIP, "the plan was lost by a failed re-plan; set a shape again");
     DeviceScope ds(r->gen->device);
     hipError_t e = launch_ragged(r, d_out, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "ragged fill launch");
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_ragged_shapes(rngx_kind kind, uint64_t *values, int32_t *n) {
+    if (!n) return fail(RNGX_E_INVALID, "n is NULL");
+    if (!kind_valid(kind) || is_lfg(kind)) return fail(RNGX_E_INVALID, "no ragged fills for this kind");
+    if (values)
+        for (int i = 0; i < kRaggedShapes; ++i) values[i] = ragged_shape_value(kind, i);
+    *n = kRaggedShapes;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_ragged_set_shape(rngx_ragged h, int32_t index) {
+    Ragged *r;
+    if (rngx_status s = check_ragged(h, &r)) return s;
+    if (index < 0 || index >= kRaggedShapes) return fail(RNGX_E_INVALID, "shape index out of range");
+    DeviceScope ds(r->gen->device);
+    (void)hipDeviceSynchronize();  // no fill still reads the plan it replaces
+    const int old = r->shape;
+    r->shape = index;
+    if (rngx_status st = ragged_build(r)) {
+        const std::string msg = g_error;
+        r->shape = old;
+        (void)ragged_build(r);  // if this fails too, fills fail until a shape is set
+        return fail(st, msg);
+    }
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_ragged_get_shape(rngx_ragged h, int32_t *index) {
+    Ragged *r;
+    if (rngx_status s = check_ragged(h, &r)) return s;
+    if (!index) return fail(RNGX_E_INVALID, "index is NULL");
+    *index = r->shape;
+    clear_error();
+    return RNGX_OK;
+}
+
+rngx_status rng_ragged_autotune(rngx_ragged h, uint32_t *d_out, int32_t reps, float *ms_out, void *stream) {
+    Ragged *r;
+    if (rngx_status s = check_ragged(h, &r)) return s;
+    if (reps < 1) return fail(RNGX_E_INVALID, "reps must be positive");
+    if (!d_out && r->total) return fail(RNGX_E_INVALID, "output pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(d_out) % 4) return fail(RNGX_E_ALIGN, "output must be 4-byte aligned");
+    Gen *g = r->gen;
+    DeviceScope ds(g->device);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    void *saved = nullptr;
+    hipError_t e = hipMalloc(&saved, g->state_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RNGX_E_NOMEM, "device memory for the saved stream states");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipDeviceSynchronize();  // no earlier fill, on any stream, still reads the plan
+    if (e == hipSuccess) e = hipMemcpy(saved, g->d_state, g->state_bytes, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int start_shape = r->shape;
+    int best = -1;
+    float best_ms = 0;
+    rngx_status built = RNGX_OK;
+    for (int i = 0; i < kRaggedShapes && e == hipSuccess && built == RNGX_OK; ++i) {
+        r->shape = i;
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+        if ((built = ragged_build(r)) != RNGX_OK) break;
+        e = hipMemcpyAsync(g->d_state, saved, g->state_bytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = launch_ragged(r, d_out, st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int k = 0; k < reps && e == hipSuccess; ++k) e = launch_ragged(r, d_out, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        ms /= static_cast<float>(reps);
+        if (ms_out) ms_out[i] = ms;
+        if (e == hipSuccess && (best < 0 || ms < best_ms)) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    const std::string build_msg = built != RNGX_OK ? g_error : std::string();
+    // the fastest shape, and the streams as they were
+    r->shape = best >= 0 ? best : start_shape;
+    const hipError_t e_run = e;
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(g->d_state, saved, g->state_bytes, hipMemcpyDeviceToDevice);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(saved);
+    const rngx_status rebuilt = ragged_build(r);
+    if (built != RNGX_OK) return fail(built, build_msg);
+    if (e_run != hipSuccess) return hip_fail(e_run, "ragged tuning run");
+    if (e != hipSuccess) return hip_fail(e, "restoring the stream states");
+    if (rebuilt != RNGX_OK) return rebuilt;
     clear_error();
     return RNGX_OK;
 }

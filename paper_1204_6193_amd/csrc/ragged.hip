@@ -662,17 +662,28 @@ bool ragged_wave(rngx_kind kind) {
 
 bool ragged_lane_table(rngx_kind kind) { return ragged_affine(kind) || kind == RNGX_MWC; }
 
-// outputs per chunk: a lane's (4096) or, for the kinds written a whole wave
-// span at a time, a wave's
-uint64_t ragged_chunk(rngx_kind kind) { return ragged_wave(kind) ? 65536 : 4096; }
+// The tuned value of each shape: XS1024W rows per CU (the default fills every
+// wave slot), else outputs per chunk, a lane's (4096) or, for the kinds
+// written a whole wave span at a time, a wave's (65536).  Smaller chunks or
+// fewer rows trade jumps for balance.
+uint64_t ragged_shape_value(rngx_kind kind, int shape) {
+    static constexpr uint64_t kXsRows[kRaggedShapes] = {kXsRowsPerCu, kXsRowsPerCu / 2, kXsRowsPerCu / 4};
+    static constexpr uint64_t kWave[kRaggedShapes] = {65536, 16384, 262144};
+    static constexpr uint64_t kLane[kRaggedShapes] = {4096, 1024, 16384};
+    const int i = shape >= 0 && shape < kRaggedShapes ? shape : 0;
+    if (kind == RNGX_XS1024W) return kXsRows[i];
+    return ragged_wave(kind) ? kWave[i] : kLane[i];
+}
 
-void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan) {
+uint64_t ragged_chunk(rngx_kind kind, int shape) { return ragged_shape_value(kind, shape); }
+
+void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan, int shape) {
     std::vector<RaggedItem> &items = plan->items;
     items.clear();
     plan->slots.clear();
     plan->max_j = 0;
     if (kind != RNGX_XS1024W) {
-        const uint64_t C = ragged_chunk(kind);
+        const uint64_t C = ragged_chunk(kind, shape);
         plan->step = C;
         for (uint64_t u = 0; u < n_units; ++u) {
             const uint64_t total = off[u + 1] - off[u];
@@ -705,7 +716,7 @@ void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu
     plan->step = J;
     if (T == 0) return;
     const uint64_t R = std::max<uint64_t>(
-        1, std::min<uint64_t>(static_cast<uint64_t>(kXsRowsPerCu) * std::max(n_cu, 1), (T + kXsMinSlotSteps - 1) / kXsMinSlotSteps));
+        1, std::min<uint64_t>(ragged_shape_value(kind, shape) * std::max(n_cu, 1), (T + kXsMinSlotSteps - 1) / kXsMinSlotSteps));
     const uint64_t Q = (T + R - 1) / R;
     // Slot r should end at (r + 1) Q placed steps; G (steps placed) stays
     // below the open slot's target between pieces.

@@ -61,6 +61,8 @@ struct Ragged {
     uint32_t n_slots;    // XS1024W: rows of the generation kernel
     uint32_t *d_slots;   // XS1024W: first item of each row, n_slots + 1 entries
     uint64_t *d_lane;    // affine kinds: (i+1)-step maps for lanes i = 0..63, then the 64-step map
+    int shape;                       // index into the kind's ragged shapes (ragged_shape_value)
+    std::vector<uint64_t> offsets;   // the request list, kept to re-plan under another shape
 };
 
 // How a lattice is swept: as strips held on chip by co-resident
@@ -203,13 +205,17 @@ struct RaggedPlan {
     std::vector<uint32_t> slots;  // XS1024W only
     uint64_t step = 1, max_j = 0;
 };
-constexpr uint32_t kXsRowsPerCu = 128;      // 8 waves per SIMD x 4 SIMDs x 4 rows
+constexpr uint32_t kXsRowsPerCu = 128;      // most rows per CU of any shape: 8 waves per SIMD x 4 SIMDs x 4 rows
 constexpr uint64_t kXsMinSlotSteps = 2048;  // slots are not cut finer than this
-uint64_t ragged_chunk(rngx_kind kind);
+// Shapes of a ragged plan, tuned per plan: XS1024W generating rows per CU,
+// other kinds outputs per chunk.  Shape 0 is the default.
+constexpr int kRaggedShapes = 3;
+uint64_t ragged_shape_value(rngx_kind kind, int shape);
+uint64_t ragged_chunk(rngx_kind kind, int shape = 0);
 bool ragged_affine(rngx_kind kind);  // LCG32/LCG64 and sub-stream forms: one wave per chunk
 bool ragged_wave(rngx_kind kind);    // affine kinds, MWC, MWC_DIFF, Philox: one wave per chunk, 1 KiB spans
 bool ragged_lane_table(rngx_kind kind);  // kinds whose wave kernel takes lane_maps (ragged_lane_maps)
-void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan);
+void ragged_plan(rngx_kind kind, const uint64_t *off, uint64_t n_units, int n_cu, RaggedPlan *plan, int shape = 0);
 size_t ragged_scratch_bytes(rngx_kind kind, uint64_t n_items);
 void ragged_lane_maps(const Gen *g, std::vector<uint64_t> *lane);  // affine kinds: lane start and advance maps
 // The one-call ragged fill of rng_fill_ragged_u32_noalloc (noalloc.hip):

@@ -123,6 +123,25 @@ def test_batch_shape_list(rngx):
     assert lib.ising_batch_autotune(bogus, 10, 1, None, None) == -1
 
 
+def test_ragged_shape_lists(rngx):
+    """Ragged shapes: XS1024W rows per CU, wave kinds and per-lane kinds
+    outputs per chunk, the default first; none for the lagged Fibonacci kinds."""
+    lib = rngx.load()
+    assert rngx.rng_ragged_shapes("xs1024w") == [128, 64, 32]
+    for kind in ("lcg32", "lcg64", "lcg32_sub", "lcg64_sub", "mwc", "mwc_diff", "philox4x32_10", "philox4x32_7"):
+        assert rngx.rng_ragged_shapes(kind) == [65536, 16384, 262144], kind
+    assert rngx.rng_ragged_shapes("xorwow") == [4096, 1024, 16384]
+    for kind in ("lfg521", "lfg1279"):
+        with pytest.raises(rngx.RngxError):
+            rngx.rng_ragged_shapes(kind)
+    assert lib.rng_ragged_shapes(1, None, None) == -1
+    bogus = ctypes.c_void_p(0x1234560)
+    assert lib.rng_ragged_set_shape(bogus, 0) == -1
+    v = ctypes.c_int()
+    assert lib.rng_ragged_get_shape(bogus, ctypes.byref(v)) == -1
+    assert lib.rng_ragged_autotune(bogus, ctypes.c_void_p(0x1000), 1, None, None) == -1
+
+
 def test_last_error_is_per_thread(rngx):
     import threading
     lib = rngx.load()

@@ -59,6 +59,55 @@ def test_ragged_parity(rngx, orc, kind):
     assert np.array_equal(u.cpu().numpy().view(np.uint32).reshape(5, S), orc.generate(kind, S, st, 5))
 
 
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "lcg64_sub", "mwc", "mwc_diff", "xorwow", "philox4x32_10"])
+def test_ragged_every_shape_matches_oracle(rngx, orc, kind):
+    """Every ragged shape (XS1024W: 128, 64, 32 generating rows per CU; the
+    others: other chunk lengths, hence other jumps and cuts) writes the
+    oracle's values and leaves the oracle's states; the fills follow each
+    other from the same plan, the oracle advanced in step."""
+    S = 320 if kind == "xs1024w" else 37
+    n_units = S // 32 if kind == "xs1024w" else S
+    lens = _lengths(kind, n_units, 5)
+    lens[-2] = 900_000 if kind == "xs1024w" else 300_000  # more chunks at every chunk length
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    g = rngx.rng_create(kind, S, 13)
+    plan = rngx.rng_ragged_create(g, off)
+    st = orc.seed(kind, S, 13)
+    for shape in range(len(rngx.rng_ragged_shapes(kind))):
+        print(f"case ragged shape {kind} {shape}", flush=True)
+        rngx.rng_ragged_set_shape(plan, shape)
+        assert rngx.rng_ragged_get_shape(plan) == shape
+        out = torch.full((int(off[-1]) + 8,), -1, dtype=torch.int32, device="cuda")
+        rngx.rng_fill_ragged_u32(plan, out)
+        got = out.cpu().numpy().view(np.uint32)
+        want = _oracle_ragged(orc, kind, S, st, lens)
+        assert np.array_equal(got[: int(off[-1])], want), (kind, shape)
+        assert np.all(got[int(off[-1]):] == 0xFFFFFFFF), (kind, shape)
+        assert np.array_equal(rngx.rng_get_state(g), st), (kind, shape)
+
+
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "xorwow"])
+def test_ragged_autotune_restores_streams(rngx, orc, kind):
+    """The ragged autotuner times every shape, keeps the fastest and leaves
+    the streams as they were: the next fill equals the oracle's first."""
+    S = 320 if kind == "xs1024w" else 37
+    n_units = S // 32 if kind == "xs1024w" else S
+    lens = _lengths(kind, n_units, 6)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    g = rngx.rng_create(kind, S, 17)
+    plan = rngx.rng_ragged_create(g, off)
+    st = orc.seed(kind, S, 17)
+    out = torch.empty(int(off[-1]), dtype=torch.int32, device="cuda")
+    ms = rngx.rng_ragged_autotune(plan, out, reps=1)
+    print(f"case ragged autotune {kind} ms={ms}", flush=True)
+    assert len(ms) == len(rngx.rng_ragged_shapes(kind)) and all(m > 0 for m in ms)
+    assert ms[rngx.rng_ragged_get_shape(plan)] == min(ms)
+    assert np.array_equal(rngx.rng_get_state(g), st)
+    rngx.rng_fill_ragged_u32(plan, out)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), _oracle_ragged(orc, kind, S, st, lens))
+    assert np.array_equal(rngx.rng_get_state(g), st)
+
+
 @pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
 def test_ragged_graph_replay(rngx, orc, kind):
     print(f"case ragged graph {kind}", flush=True)
@@ -129,14 +178,15 @@ def _runs(seed, target):
     return [runs[i] for i in order]
 
 
-@pytest.mark.parametrize("kind", ["xs1024w", "lcg32", "mwc", "philox4x32_10", "mwc_diff"])
-def test_ragged_bench_shape_sampled(rngx, orc, kind):
+@pytest.mark.parametrize("kind,shape", [("xs1024w", 0), ("xs1024w", 1), ("xs1024w", 2), ("lcg32", 0), ("lcg32", 1),
+                                        ("lcg32", 2), ("mwc", 0), ("mwc", 2), ("philox4x32_10", 0), ("mwc_diff", 0)])
+def test_ragged_bench_shape_sampled(rngx, orc, kind, shape):
     """About 2.2e9 values in requests of 2^10 .. 2^22 values: large enough
-    that the XS1024W plan uses its full row count, with cuts inside many
-    instances.  Sampled requests are compared with the oracle value by value,
-    every stream's final state with the oracle's jump-ahead, and one word past
-    the end stays untouched."""
-    print(f"case ragged bench shape {kind}", flush=True)
+    that the XS1024W plan uses every shape's full row count (128, 64 or 32
+    per CU), with cuts inside many instances.  Sampled requests are compared
+    with the oracle value by value, every stream's final state with the
+    oracle's jump-ahead, and one word past the end stays untouched."""
+    print(f"case ragged bench shape {kind} shape {shape}", flush=True)
     runs = _runs(5, 2.2e9)
     lens = np.concatenate([np.full(m, ln, dtype=np.int64) for m, ln in runs])
     n = len(lens)
@@ -146,6 +196,7 @@ def test_ragged_bench_shape_sampled(rngx, orc, kind):
     S = width * n
     g = rngx.rng_create(kind, S, 21)
     plan = rngx.rng_ragged_create(g, off)
+    rngx.rng_ragged_set_shape(plan, shape)
     out = torch.empty(total + 1, dtype=torch.int32, device="cuda")
     out[total] = -1
     rngx.rng_fill_ragged_u32(plan, out)
