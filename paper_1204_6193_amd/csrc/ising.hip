@@ -395,9 +395,9 @@ template <bool E>
 __device__ __forceinline__ uint32_t decide(uint32_t m2, uint32_t sh, uint32_t f, uint32_t r, const Accept &A,
                                            uint32_t &esum) {
     const uint32_t d = __builtin_amdgcn_ubfe(m2, sh, 8);
-    // three compares combined as lane masks (no select of the threshold)
-    const bool two = d == 2;
-    const bool acc = (d >= A.lo) | (two & (r < A.t4)) | (!two & (r < A.t8));
+    // compares combined as lane masks (no select of the threshold): since
+    // t8 <= t4, r < t8 accepts at d = 2 too, so it needs no d != 2 term
+    const bool acc = (d >= A.lo) | (r < A.t8) | ((d == 2) & (r < A.t4));
     if constexpr (E) esum += acc ? 8 - d : d;
     return acc ? f : 0u;
 }
@@ -405,8 +405,7 @@ __device__ __forceinline__ uint32_t decide(uint32_t m2, uint32_t sh, uint32_t f,
 // One update of a multi-hit site with doubled count d and draw r; a taken
 // flip turns d into 8 - d and toggles `flip`.
 __device__ __forceinline__ void hit_lds(uint32_t &d, uint32_t &flip, uint32_t r, const Accept &A) {
-    const bool two = d == 2;
-    const bool acc = (d >= A.lo) | (two & (r < A.t4)) | (!two & (r < A.t8));
+    const bool acc = (d >= A.lo) | (r < A.t8) | ((d == 2) & (r < A.t4));  // as in decide
     d = acc ? 8 - d : d;
     flip ^= acc ? 1u : 0u;
 }
