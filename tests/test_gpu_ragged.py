@@ -108,14 +108,17 @@ def test_ragged_autotune_restores_streams(rngx, orc, kind):
     assert np.array_equal(rngx.rng_get_state(g), st)
 
 
-@pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
-def test_ragged_graph_replay(rngx, orc, kind):
-    print(f"case ragged graph {kind}", flush=True)
+@pytest.mark.parametrize("kind,shape", [("xs1024w", 0), ("lcg32", 0), ("lcg32", 1), ("xorwow", 1)])
+def test_ragged_graph_replay(rngx, orc, kind, shape):
+    """A ragged fill captured in a HIP graph (plan at `shape`): every replay
+    equals an eager fill from a plan left at the default shape."""
+    print(f"case ragged graph {kind} shape {shape}", flush=True)
     S = 256 if kind == "xs1024w" else 37
     lens = _lengths(kind, S // 32 if kind == "xs1024w" else S, 8)
     off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
     ga, gb = rngx.rng_create(kind, S, 2), rngx.rng_create(kind, S, 2)
     pa, pb = rngx.rng_ragged_create(ga, off), rngx.rng_ragged_create(gb, off)
+    rngx.rng_ragged_set_shape(pa, shape)
     oa = torch.zeros(int(off[-1]), dtype=torch.int32, device="cuda")
     ob = torch.zeros(int(off[-1]), dtype=torch.int32, device="cuda")
     s = torch.cuda.Stream()
