@@ -1321,27 +1321,35 @@ bool try_strips(uint32_t L, uint32_t nwg, int max_spt, int n_cu, IsingPlan *out)
     int spt = 1;
     while (spt <= max_spt && (units + spt - 1) / spt > kMaxThreads) spt *= 2;
     if (spt > max_spt) return false;
-    uint32_t threads = (units + spt - 1) / spt;
-    threads = (threads + 63) / 64 * 64;
-    if constexpr (IsLfgStrip<Unit>::value) {  // whole instances, slot i = instance i on 1024 threads
-        if (units % 1024 || threads != 1024 || static_cast<uint32_t>(spt) * 1024 != units) return false;
-        lds = (lds + 15) / 16 * 16 + lfg_ring_bytes<Unit>(units);
-    }
-    const bool early = plan_early(spt, L / NB, units, threads);
-    if (place_lds_for<Unit>(spt)) lds += 4ull * spt * threads;
-    if (lds > kLdsMax) return false;
-    const void *fn = strip_kernel_for<Unit>(spt, early);
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    (void)hipGetLastError();
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, static_cast<int>(threads), lds) != hipSuccess ||
-        occ < 1) {
+    // The fewest units per thread that fit; if the strips are then not all
+    // resident (more strips than CUs), more units per thread and fewer
+    // threads per strip put several strips on each CU.
+    for (; spt <= max_spt; spt *= 2) {
+        uint32_t threads = (units + spt - 1) / spt;
+        threads = (threads + 63) / 64 * 64;
+        uint64_t b = lds;
+        if constexpr (IsLfgStrip<Unit>::value) {  // whole instances, slot i = instance i on 1024 threads
+            if (units % 1024 || threads != 1024 || static_cast<uint32_t>(spt) * 1024 != units) return false;
+            b = (b + 15) / 16 * 16 + lfg_ring_bytes<Unit>(units);
+        }
+        const bool early = plan_early(spt, L / NB, units, threads);
+        if (place_lds_for<Unit>(spt)) b += 4ull * spt * threads;
+        if (b > kLdsMax) return false;
+        const void *fn = strip_kernel_for<Unit>(spt, early);
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(b));
         (void)hipGetLastError();
-        return false;
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, static_cast<int>(threads), b) != hipSuccess ||
+            occ < 1) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (static_cast<uint64_t>(occ) * n_cu >= nwg) {
+            *out = IsingPlan{true, R, nwg, units, static_cast<uint32_t>(spt), threads, static_cast<uint32_t>(b), early};
+            return true;
+        }
     }
-    if (static_cast<uint64_t>(occ) * n_cu < nwg) return false;
-    *out = IsingPlan{true, R, nwg, units, static_cast<uint32_t>(spt), threads, static_cast<uint32_t>(lds), early};
-    return true;
+    return false;
 }
 
 // Lattices up to 256 x 256 run in one workgroup (barriers stay inside the
@@ -1555,7 +1563,8 @@ namespace {
 template <class Unit>
 int list_plans(uint32_t L, int max_spt, int n_cu, IsingPlan *out, int max) {
     int n = 0;
-    const uint32_t top = std::min<uint32_t>(L, static_cast<uint32_t>(std::max(n_cu, 1)));
+    // up to two strips per CU (smaller workgroups, several per CU)
+    const uint32_t top = std::min<uint32_t>(L, 2 * static_cast<uint32_t>(std::max(n_cu, 1)));
     for (uint32_t nwg = top; nwg >= 1 && n < max; --nwg) {
         if (L % nwg) continue;
         if (nwg > 1 && static_cast<uint64_t>(L / nwg) * L < 2048) continue;

@@ -139,6 +139,21 @@ def test_every_plan_gives_the_same_lattice(rngx, orc, kind, L):
         _run_both(rngx, orc, L, kind, 0.4, 3, chunks=(2, 1), plan=strips)
 
 
+@pytest.mark.parametrize("kind", ["xs1024w", "lcg32"])
+def test_plans_with_several_strips_per_cu(rngx, orc, kind):
+    """At L = 4096 the tuner's candidates include more strips than CUs (8
+    rows each), made resident by more units and fewer threads per strip (for
+    the kinds whose strips then fit two to a CU's LDS); they give the
+    oracle's lattice too."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    plans = rngx.ising_plans(rngx.ising_create(4096, kind, 1))
+    many = [p for p in plans if p > n_cu]
+    assert many, plans
+    for strips in many:
+        print(f"case ising plan {kind} L=4096 strips={strips}", flush=True)
+        _run_both(rngx, orc, 4096, kind, 0.4, 2, chunks=(2,), plan=strips)
+
+
 def test_autotune_restores_the_lattice(rngx, orc):
     L, kind = 1024, "xs1024w"
     print("case ising autotune", flush=True)
