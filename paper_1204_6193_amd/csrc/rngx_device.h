@@ -32,6 +32,13 @@ constexpr uint32_t kPollLimit = 4096; // polls before a workgroup stops waiting
 
 enum { kOutU32 = 0, kOutF32 = 1, kOutXor = 2 };
 
+// a ^ b ^ c as one gfx950 three-input bit operation (truth table 0x96 is
+// the three-way xor); the compiler does not fuse chained xors by itself.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+
 // Pacing of a fill's workgroups in bands of kBand rows (see k_fill_xs).
 // before(b): wait (bounded) until every workgroup has finished band
 // b - kSlack; after(b): count this workgroup's band b.  A workgroup whose wait
@@ -226,7 +233,7 @@ struct Xorwow {
     __device__ uint32_t next() {
         uint32_t t = x ^ (x >> 2);
         x = y; y = z; z = w; w = v;
-        v = (v ^ (v << 4)) ^ (t ^ (t << 1));
+        v = xor3(v, v << 4, t ^ (t << 1));
         d += kWeylC;
         return d + v;
     }
@@ -242,8 +249,8 @@ __device__ inline void philox_block(uint32_t k0, uint32_t k1, uint64_t blk, uint
     for (int r = 0; r < ROUNDS; ++r) {
         const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * x0;
         const uint64_t p1 = static_cast<uint64_t>(kPhiloxM1) * x2;
-        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ x1 ^ k0;
-        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ x3 ^ k1;
+        const uint32_t n0 = xor3(static_cast<uint32_t>(p1 >> 32), x1, k0);
+        const uint32_t n2 = xor3(static_cast<uint32_t>(p0 >> 32), x3, k1);
         x1 = static_cast<uint32_t>(p1);
         x3 = static_cast<uint32_t>(p0);
         x0 = n0; x2 = n2;
@@ -333,7 +340,7 @@ __device__ __forceinline__ void xorwow_apply_poly(const uint32_t *c, uint32_t (&
     for (int i = 159; i >= 0; --i) {
         const uint32_t t = acc[0] ^ (acc[0] >> 2);
         acc[0] = acc[1]; acc[1] = acc[2]; acc[2] = acc[3]; acc[3] = acc[4];
-        acc[4] = (acc[4] ^ (acc[4] << 4)) ^ (t ^ (t << 1));
+        acc[4] = xor3(acc[4], acc[4] << 4, t ^ (t << 1));
         if ((c[i >> 5] >> (i & 31)) & 1u)
             for (int q = 0; q < 5; ++q) acc[q] ^= s[q];
     }
