@@ -126,16 +126,34 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
     uint32_t acc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = 0;
-    for (uint64_t k = 0; k < count; ++k) {
-        uint32_t u[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) u[v] = g[v].next();
+    auto emit = [&](uint64_t k, const uint32_t (&u)[V]) {
         if constexpr (MODE == kOutXor) {
 #pragma unroll
             for (int v = 0; v < V; ++v) acc[v] ^= u[v];
         } else {
             store_out<MODE, V>(out, k * S + s0, u);
         }
+    };
+    uint64_t k = 0;
+    if constexpr (HasNext8<G>::value) {  // 8 outputs of each stream at a time
+        for (; k + 8 <= count; k += 8) {
+            uint32_t d[V][8];
+#pragma unroll
+            for (int v = 0; v < V; ++v) g[v].next8(d[v]);
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                uint32_t u[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) u[v] = d[v][kk];
+                emit(k + kk, u);
+            }
+        }
+    }
+    for (; k < count; ++k) {
+        uint32_t u[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) u[v] = g[v].next();
+        emit(k, u);
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) g[v].store(st, S, s0 + v);
@@ -170,8 +188,22 @@ __global__ __launch_bounds__(BLK) void k_fill_paced(uint8_t *st, uint64_t S, uin
         };
         const uint64_t k1 = k0 + kBand < count ? k0 + kBand : count;
         if (k1 - k0 == kBand) {
+            if constexpr (HasNext8<G>::value) {  // a band is 8 outputs of each stream
+                static_assert(kBand == 8, "next8 covers one band");
+                uint32_t d[V][8];
 #pragma unroll
-            for (uint32_t kk = 0; kk < kBand; ++kk) row(k0 + kk);
+                for (int v = 0; v < V; ++v) g[v].next8(d[v]);
+#pragma unroll
+                for (uint32_t kk = 0; kk < kBand; ++kk) {
+                    uint32_t u[V];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) u[v] = d[v][kk];
+                    if (live) store_out<MODE, V>(out, (k0 + kk) * S + s0, u);
+                }
+            } else {
+#pragma unroll
+                for (uint32_t kk = 0; kk < kBand; ++kk) row(k0 + kk);
+            }
         } else {
             for (uint64_t k = k0; k < k1; ++k) row(k);
         }

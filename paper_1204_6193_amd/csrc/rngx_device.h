@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace rngx {
 
@@ -239,6 +240,18 @@ struct Xorwow {
     }
 };
 
+// One Philox4x32 round on (x0, x1, x2, x3) with round key (k0, k1).
+__device__ __forceinline__ void philox_round(uint32_t &x0, uint32_t &x1, uint32_t &x2, uint32_t &x3, uint32_t k0,
+                                             uint32_t k1) {
+    const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * x0;
+    const uint64_t p1 = static_cast<uint64_t>(kPhiloxM1) * x2;
+    const uint32_t n0 = xor3(static_cast<uint32_t>(p1 >> 32), x1, k0);
+    const uint32_t n2 = xor3(static_cast<uint32_t>(p0 >> 32), x3, k1);
+    x1 = static_cast<uint32_t>(p1);
+    x3 = static_cast<uint32_t>(p0);
+    x0 = n0; x2 = n2;
+}
+
 // Philox4x32-R block function on counter (lo, hi, 0, 0) with key (k0, k1);
 // R = 10, or 7 for the faster variant of the counter-based section.
 template <int ROUNDS = 10>
@@ -247,16 +260,27 @@ __device__ inline void philox_block(uint32_t k0, uint32_t k1, uint64_t blk, uint
     uint32_t x0 = static_cast<uint32_t>(blk), x1 = static_cast<uint32_t>(blk >> 32), x2 = 0, x3 = 0;
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
-        const uint64_t p0 = static_cast<uint64_t>(kPhiloxM0) * x0;
-        const uint64_t p1 = static_cast<uint64_t>(kPhiloxM1) * x2;
-        const uint32_t n0 = xor3(static_cast<uint32_t>(p1 >> 32), x1, k0);
-        const uint32_t n2 = xor3(static_cast<uint32_t>(p0 >> 32), x3, k1);
-        x1 = static_cast<uint32_t>(p1);
-        x3 = static_cast<uint32_t>(p0);
-        x0 = n0; x2 = n2;
+        philox_round(x0, x1, x2, x3, k0, k1);
         k0 += kPhiloxW0; k1 += kPhiloxW1;
     }
     o0 = x0; o1 = x1; o2 = x2; o3 = x3;
+}
+
+// Blocks blk and blk + 1 of one key side by side, sharing the key schedule:
+// o[0..3] and o[4..7] are the two blocks' words.
+template <int ROUNDS = 10>
+__device__ inline void philox_block2(uint32_t k0, uint32_t k1, uint64_t blk, uint32_t (&o)[8]) {
+    const uint64_t nb = blk + 1;
+    uint32_t x0 = static_cast<uint32_t>(blk), x1 = static_cast<uint32_t>(blk >> 32), x2 = 0, x3 = 0;
+    uint32_t y0 = static_cast<uint32_t>(nb), y1 = static_cast<uint32_t>(nb >> 32), y2 = 0, y3 = 0;
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        philox_round(x0, x1, x2, x3, k0, k1);
+        philox_round(y0, y1, y2, y3, k0, k1);
+        k0 += kPhiloxW0; k1 += kPhiloxW1;
+    }
+    o[0] = x0; o[1] = x1; o[2] = x2; o[3] = x3;
+    o[4] = y0; o[5] = y1; o[6] = y2; o[7] = y3;
 }
 
 template <int ROUNDS>
@@ -278,7 +302,21 @@ struct PhiloxR {
         ++pos;
         return j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3;
     }
+    // The next 8 outputs.  From a block boundary these are two whole blocks,
+    // made together; elsewhere they are 8 calls of next().
+    __device__ void next8(uint32_t (&u)[8]) {
+        if ((pos & 3) == 0) {
+            philox_block2<ROUNDS>(k0, k1, pos >> 2, u);
+            pos += 8;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) u[j] = next();
+        }
+    }
 };
+// Generators with next8() (outputs made 8 at a time).
+template <class G> struct HasNext8 : std::false_type {};
+template <int ROUNDS> struct HasNext8<PhiloxR<ROUNDS>> : std::true_type {};
 using Philox = PhiloxR<10>;
 using Philox7 = PhiloxR<7>;
 
