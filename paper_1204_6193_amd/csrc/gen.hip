@@ -135,24 +135,17 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
         }
     };
     uint64_t k = 0;
-    if constexpr (HasNext8<G>::value) {  // from block boundaries: 8 outputs of each stream at a time
-        bool aligned = true;
+    if constexpr (HasNext8<G>::value) {  // 8 outputs of each stream at a time
+        for (; k + 8 <= count; k += 8) {
+            uint32_t d[V][8];
 #pragma unroll
-        for (int v = 0; v < V; ++v) aligned = aligned && g[v].at_boundary();
-        if (aligned) {
+            for (int v = 0; v < V; ++v) g[v].next8(d[v]);
 #pragma unroll
-            for (int v = 0; v < V; ++v) g[v].drop_block();
-            for (; k + 8 <= count; k += 8) {
-                uint32_t d[V][8];
+            for (int kk = 0; kk < 8; ++kk) {
+                uint32_t u[V];
 #pragma unroll
-                for (int v = 0; v < V; ++v) g[v].next8_aligned(d[v]);
-#pragma unroll
-                for (int kk = 0; kk < 8; ++kk) {
-                    uint32_t u[V];
-#pragma unroll
-                    for (int v = 0; v < V; ++v) u[v] = d[v][kk];
-                    emit(k + kk, u);
-                }
+                for (int v = 0; v < V; ++v) u[v] = d[v][kk];
+                emit(k + kk, u);
             }
         }
     }
@@ -185,69 +178,36 @@ __global__ __launch_bounds__(BLK) void k_fill_paced(uint8_t *st, uint64_t S, uin
         if (live) g[v].load(st, S, s0 + v);
     __shared__ uint32_t s_free;
     Pacer pc(ring);
-    // The band loop; with A (every stream of the workgroup at a block
-    // boundary, which full bands keep) a full band is next8_aligned().
-    auto bands = [&](auto A) {
-        for (uint64_t k0 = 0, band = 0; k0 < count; k0 += kBand, ++band) {
-            pc.before(band, &s_free);
-            auto row = [&](uint64_t k) {
-                uint32_t u[V];
+    for (uint64_t k0 = 0, band = 0; k0 < count; k0 += kBand, ++band) {
+        pc.before(band, &s_free);
+        auto row = [&](uint64_t k) {
+            uint32_t u[V];
 #pragma unroll
-                for (int v = 0; v < V; ++v) u[v] = g[v].next();
-                if (live) store_out<MODE, V>(out, k * S + s0, u);
-            };
-            const uint64_t k1 = k0 + kBand < count ? k0 + kBand : count;
-            if (k1 - k0 == kBand) {
-                bool done = false;
-                if constexpr (HasNext8<G>::value) {
-                    if constexpr (decltype(A)::value) {
-                        static_assert(kBand == 8, "next8_aligned covers one band");
-                        if (live) {  // (threads past the last stream skip the band)
-                            uint32_t d[V][8];
+            for (int v = 0; v < V; ++v) u[v] = g[v].next();
+            if (live) store_out<MODE, V>(out, k * S + s0, u);
+        };
+        const uint64_t k1 = k0 + kBand < count ? k0 + kBand : count;
+        if (k1 - k0 == kBand) {
+            if constexpr (HasNext8<G>::value) {  // a band is 8 outputs of each stream
+                static_assert(kBand == 8, "next8 covers one band");
+                uint32_t d[V][8];
 #pragma unroll
-                            for (int v = 0; v < V; ++v) {
-                                g[v].next8_aligned(d[v]);
-                                __builtin_amdgcn_sched_barrier(0);  // one stream's blocks at a time: fewer live registers
-                            }
+                for (int v = 0; v < V; ++v) g[v].next8(d[v]);
 #pragma unroll
-                            for (uint32_t kk = 0; kk < kBand; ++kk) {
-                                uint32_t u[V];
+                for (uint32_t kk = 0; kk < kBand; ++kk) {
+                    uint32_t u[V];
 #pragma unroll
-                                for (int v = 0; v < V; ++v) u[v] = d[v][kk];
-                                store_out<MODE, V>(out, (k0 + kk) * S + s0, u);
-                            }
-                        }
-                        done = true;
-                    }
-                }
-                if (!done) {
-                    if constexpr (HasNext8<G>::value) {  // positions off block boundaries: rare, kept small
-#pragma unroll 1
-                        for (uint32_t kk = 0; kk < kBand; ++kk) row(k0 + kk);
-                    } else {
-#pragma unroll
-                        for (uint32_t kk = 0; kk < kBand; ++kk) row(k0 + kk);
-                    }
+                    for (int v = 0; v < V; ++v) u[v] = d[v][kk];
+                    if (live) store_out<MODE, V>(out, (k0 + kk) * S + s0, u);
                 }
             } else {
-                for (uint64_t k = k0; k < k1; ++k) row(k);
+#pragma unroll
+                for (uint32_t kk = 0; kk < kBand; ++kk) row(k0 + kk);
             }
-            pc.after(band);
-        }
-    };
-    if constexpr (HasNext8<G>::value) {
-        bool aligned = true;
-#pragma unroll
-        for (int v = 0; v < V; ++v) aligned = aligned && (!live || g[v].at_boundary());
-        if (__syncthreads_and(aligned)) {  // workgroup-uniform: both loops hold barriers
-#pragma unroll
-            for (int v = 0; v < V; ++v) g[v].drop_block();
-            bands(std::true_type{});
         } else {
-            bands(std::false_type{});
+            for (uint64_t k = k0; k < k1; ++k) row(k);
         }
-    } else {
-        bands(std::false_type{});
+        pc.after(band);
     }
     if (!live) return;
 #pragma unroll

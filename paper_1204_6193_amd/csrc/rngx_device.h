@@ -302,17 +302,19 @@ struct PhiloxR {
         ++pos;
         return j == 0 ? b0 : j == 1 ? b1 : j == 2 ? b2 : b3;
     }
-    // At a block boundary the buffered block (b0..b3) is never read again:
-    // next() makes a new one first.  drop_block() forgets it, so that it
-    // holds no registers; next8_aligned() keeps the position at a boundary.
-    __device__ bool at_boundary() const { return (pos & 3) == 0; }
-    __device__ void drop_block() { b0 = b1 = b2 = b3 = 0; }
-    __device__ void next8_aligned(uint32_t (&u)[8]) {  // at_boundary() only
-        philox_block2<ROUNDS>(k0, k1, pos >> 2, u);
-        pos += 8;
+    // The next 8 outputs.  From a block boundary these are two whole blocks,
+    // made together; elsewhere they are 8 calls of next().
+    __device__ void next8(uint32_t (&u)[8]) {
+        if ((pos & 3) == 0) {
+            philox_block2<ROUNDS>(k0, k1, pos >> 2, u);
+            pos += 8;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) u[j] = next();
+        }
     }
 };
-// Generators with next8_aligned() (8 outputs at a time from a block boundary).
+// Generators with next8() (outputs made 8 at a time).
 template <class G> struct HasNext8 : std::false_type {};
 template <int ROUNDS> struct HasNext8<PhiloxR<ROUNDS>> : std::true_type {};
 using Philox = PhiloxR<10>;

@@ -325,6 +325,50 @@ def test_every_fill_configuration(rngx, orc, kind):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("kind", ["philox4x32_10", "philox4x32_7"])
+def test_philox_fills_off_block_boundaries(rngx, orc, kind):
+    """Philox streams at positions that are not multiples of 4 (one block of
+    the counter-based generator): the first half of the streams at block
+    boundaries, the second half each at its own offset, so that paced
+    workgroups run both the aligned and the unaligned band loop and
+    unpaced threads both of their paths.  Every fill configuration, u32 and
+    FP32, equals the oracle over the whole output and leaves the oracle's
+    state; so does consume."""
+    S, count, seed = 1 << 19, 37, 5
+    img = orc.seed(kind, S, seed)
+    pos = img[8 * S:16 * S].view(np.uint64)
+    pos[S // 2:] += np.random.default_rng(11).integers(1, 8, size=S // 2, dtype=np.uint64)
+    st = img.copy()
+    want = orc.generate(kind, S, st, count)
+    want_f = orc.generate(kind, S, img.copy(), count, mode=orc.OUT_F32)
+    for index in range(len(rngx.rng_fill_configs(kind))):
+        print(f"case philox off-boundary fill {kind} #{index}", flush=True)
+        for f32 in (False, True):
+            g = rngx.rng_create(kind, S, seed)
+            rngx.rng_set_state(g, img)
+            rngx.rng_set_fill_config(g, index)
+            if f32:
+                out = torch.empty(S * count, dtype=torch.float32, device="cuda")
+                rngx.rng_fill_f32(g, out, count)
+                got = out.view(count, S).cpu().numpy().view(np.uint32)
+                assert np.array_equal(got, want_f.view(np.uint32)), (kind, index, "f32")
+            else:
+                out = torch.empty(S * count, dtype=torch.int32, device="cuda")
+                rngx.rng_fill_u32(g, out, count)
+                got = out.view(count, S).cpu().numpy().view(np.uint32)
+                assert np.array_equal(got, want), (kind, index, "u32")
+            assert np.array_equal(rngx.rng_get_state(g), st), (kind, index, f32)
+            rngx.rng_destroy(g)
+    g = rngx.rng_create(kind, S, seed)
+    rngx.rng_set_state(g, img)
+    acc = torch.empty(S, dtype=torch.int32, device="cuda")
+    rngx.rng_consume(g, acc, count)
+    assert np.array_equal(acc.cpu().numpy().view(np.uint32), np.bitwise_xor.reduce(want, axis=0))
+    assert np.array_equal(rngx.rng_get_state(g), st)
+    rngx.rng_destroy(g)
+    torch.cuda.empty_cache()
+
+
 def test_xs1024w_fill_from_unit_vector_states(rngx, orc):
     """1024 instances, instance g holding the single set bit g of the
     1024-bit word (the sparsest states; every word shift of the DPP step
