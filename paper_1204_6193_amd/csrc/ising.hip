@@ -168,22 +168,22 @@ struct PhiloxSweepUnitR {
         k0 = p[u]; k1 = p[S + u];
         c2 = c3 = 0;
     }
-    __device__ void store_at(uint8_t *st, uint64_t S, uint64_t u, uint64_t pos) const {
-        reinterpret_cast<uint64_t *>(st + 8 * S)[u] = pos;
+    template <class Args>
+    __device__ void store_at(uint8_t *st, uint64_t S, uint64_t u, const Args &g) const {
+        reinterpret_cast<uint64_t *>(st + 8 * S)[u] = 4 * (g.blk0 + g.n_sweeps);
     }
-    __device__ void draw_at(uint32_t (&r)[2], uint64_t blk, int c) {
+    template <class Args>
+    __device__ void draw_at(uint32_t (&r)[2], const Args &g, uint64_t sweep, int c) {
         if (c == 0) {
-            philox_block<ROUNDS>(k0, k1, blk, r[0], r[1], c2, c3);
+            philox_block<ROUNDS>(k0, k1, g.blk0 + sweep, r[0], r[1], c2, c3);
         } else {
             r[0] = c2;
             r[1] = c3;
         }
     }
 };
-template <class Unit> struct SweepCounter : std::false_type {};  // units that take the block index per pass
+template <class Unit> struct SweepCounter : std::false_type {};  // units that derive their pass from the call's start
 template <int ROUNDS> struct SweepCounter<PhiloxSweepUnitR<ROUNDS>> : std::true_type {};
-template <class Unit> struct PhiloxSweepOf { using type = void; };  // the sweep form of a Philox unit
-template <int ROUNDS> struct PhiloxSweepOf<PhiloxUnitR<ROUNDS>> { using type = PhiloxSweepUnitR<ROUNDS>; };
 
 // Lagged Fibonacci units in strips (single-hit).  A strip holds whole
 // instances (1024 units each) and runs 1024 threads, so slot i of thread t is
@@ -251,6 +251,40 @@ struct XsUnit {
     }
 };
 
+// XS1024W in a strip whose instances have all taken the same number of
+// steps at the start of a call (the usual case: every call advances every
+// instance alike).  The Weyl word of a pass is then the same for every unit:
+// it follows from the call's start (step count blk0, Weyl word y_start) and
+// the sweep, instead of being held and stepped per unit.
+struct XsSweepUnit {
+    static constexpr int kNB = 8;
+    uint32_t a, b;
+    __device__ void load(const uint8_t *st, uint64_t, uint64_t u) {
+        const uint2 w = reinterpret_cast<const uint2 *>(st)[u];
+        a = w.x; b = w.y;
+    }
+    template <class Args>
+    __device__ void store_at(uint8_t *st, uint64_t S, uint64_t u, const Args &g) const {
+        reinterpret_cast<uint2 *>(st)[u] = make_uint2(a, b);
+        if ((u & 15) == 0) reinterpret_cast<uint64_t *>(st + 4 * S)[u >> 4] = g.blk0 + 4 * g.n_sweeps;
+    }
+    // as XsUnit::draw for the pass (sweep, c): 4 sweep + 2 c steps after the start
+    template <class Args>
+    __device__ void draw_at(uint32_t (&r)[4], const Args &g, uint64_t sweep, int c) {
+        const uint32_t y = g.y_start + static_cast<uint32_t>(4 * sweep + 2 * c) * kWeylC;
+        xs1024_step(a, b);
+        uint32_t m = weyl_mix(y + kWeylC);
+        r[0] = a + m; r[2] = b + m;
+        xs1024_step(a, b);
+        m = weyl_mix(y + 2 * kWeylC);
+        r[1] = a + m; r[3] = b + m;
+    }
+};
+template <> struct SweepCounter<XsSweepUnit> : std::true_type {};
+template <class Unit> struct SweepOf { using type = void; };  // the sweep form of a unit, if it has one
+template <int ROUNDS> struct SweepOf<PhiloxUnitR<ROUNDS>> { using type = PhiloxSweepUnitR<ROUNDS>; };
+template <> struct SweepOf<XsUnit> { using type = XsSweepUnit; };
+
 template <int NB>
 __device__ __forceinline__ uint64_t lds_run(const uint8_t *p) {
     if constexpr (NB == 8) return *reinterpret_cast<const uint64_t *>(p);
@@ -295,7 +329,8 @@ struct StripArgs {
     uint32_t *err;
     uint32_t hits;              // Metropolis updates per visited site (multi-hit kernels)
     uint32_t R0;                // rows of every strip but the last: strip r starts at row r*R0
-    uint64_t blk0;              // sweep-form Philox units: the common block index at the start
+    uint64_t blk0;              // sweep forms, at the start: Philox the common block index, XS1024W the step count
+    uint32_t y_start;           // sweep-form XS1024W: the common Weyl word at the start
 };
 
 constexpr uint32_t kSpinLimit = 1u << 20;
@@ -438,7 +473,7 @@ __device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint32_t 
 template <class Unit, bool E, bool MH>
 __device__ __forceinline__ uint64_t update_unit(uint8_t *lds, uint32_t pl, uint32_t P, uint32_t up_add, uint32_t dn_add,
                                                 int c, Unit &u, const Accept &A, uint32_t &esum, uint32_t hits,
-                                                uint64_t blk = 0) {
+                                                const StripArgs &g, uint64_t sweep) {
     constexpr int NB = Unit::kNB;
     const uint32_t off = pl & kOffMask;
     const uint32_t sh0 = ((pl >> 31) ^ static_cast<uint32_t>(c)) << 3;  // bit offset of the first colour-c byte
@@ -484,7 +519,7 @@ __device__ __forceinline__ uint64_t update_unit(uint8_t *lds, uint32_t pl, uint3
         }
     }
     uint32_t rr[NB / 2];
-    if constexpr (SweepCounter<Unit>::value) u.draw_at(rr, blk, c);
+    if constexpr (SweepCounter<Unit>::value) u.draw_at(rr, g, sweep, c);
     else u.draw(rr);
     if constexpr (NB == 4) {
         const uint32_t w = l32[0];
@@ -719,7 +754,7 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
                 else pl = place[i] + zero;
                 const bool top = bslot && ((pl >> 27) & 1), bot = bslot && ((pl >> 28) & 1);
                 const uint64_t nw = update_unit<Unit, E, MH>(lds, pl, P, top ? up_add : 0u, bot ? dn_add : 0u, c, u[i], A, esum,
-                                                                   a.hits, a.blk0 + sweep);
+                                                                   a.hits, a, sweep);
                 const uint32_t off = pl & kOffMask;
                 const uint32_t yrow = top ? 1 : bot ? R : 0;   // only used for boundary units
                 const uint32_t x0 = off - kPad - yrow * P;
@@ -791,7 +826,7 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
     for (int i = 0; i < SPT; ++i) {
         const uint32_t k = t + i * nt;
         if (k < a.units) {
-            if constexpr (SweepCounter<Unit>::value) u[i].store_at(a.st, a.S, ubase + k, 4 * (a.blk0 + a.n_sweeps));
+            if constexpr (SweepCounter<Unit>::value) u[i].store_at(a.st, a.S, ubase + k, a);
             else u[i].store(a.st, a.S, ubase + k, 4 * a.n_sweeps * (MH ? a.hits : 1));
         }
     }
@@ -806,6 +841,20 @@ __device__ inline bool strip_positions_aligned(const StripArgs &a, uint32_t r, u
     int ok = (p0 & 3) == 0;
     for (uint32_t k = threadIdx.x; k < a.units; k += blockDim.x) ok &= pos[k] == p0;
     *blk0 = p0 >> 2;
+    return __syncthreads_and(ok) != 0;
+}
+
+// Whether every XS1024W instance with a unit in strip r has taken the same
+// number of steps: then *n0 is that count and *y_start the common Weyl word.
+__device__ inline bool strip_steps_uniform(const StripArgs &a, uint32_t r, uint64_t *n0, uint32_t *y_start) {
+    const uint64_t ubase = static_cast<uint64_t>(r) * a.R0 * (a.L / 8);
+    const uint64_t *N = reinterpret_cast<const uint64_t *>(a.st + 4 * a.S);
+    const uint64_t g0 = ubase >> 4, g1 = (ubase + a.units - 1) >> 4;
+    const uint64_t n = N[g0];
+    int ok = 1;
+    for (uint64_t g = g0 + threadIdx.x; g <= g1; g += blockDim.x) ok &= N[g] == n;
+    *n0 = n;
+    *y_start = *reinterpret_cast<const uint32_t *>(a.st + 4 * a.S + 8 * (a.S / 32)) + static_cast<uint32_t>(n) * kWeylC;
     return __syncthreads_and(ok) != 0;
 }
 
@@ -826,11 +875,14 @@ __global__ __launch_bounds__(1024) void k_ising_strip(StripArgs a) {
         if (threadIdx.x == 0) __hip_atomic_fetch_or(a.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
     }
-    using Sweep = typename PhiloxSweepOf<Unit>::type;
+    using Sweep = typename SweepOf<Unit>::type;
     if constexpr (!std::is_void<Sweep>::value && !MH) {
         static_assert(place_in_lds<Sweep, SPT>() == place_in_lds<Unit, SPT>(), "the two forms share the LDS plan");
         StripArgs b2 = a;
-        if (strip_positions_aligned(a, r, &b2.blk0)) {
+        bool uniform;
+        if constexpr (std::is_same<Unit, XsUnit>::value) uniform = strip_steps_uniform(a, r, &b2.blk0, &b2.y_start);
+        else uniform = strip_positions_aligned(a, r, &b2.blk0);
+        if (uniform) {
             strip_body<Sweep, SPT, EARLY, place_in_lds<Sweep, SPT>(), false>(b2, r, lds);
             return;
         }
