@@ -482,26 +482,21 @@ __global__ __launch_bounds__(kBlock) void k_ragged_xs(const RaggedItem *items, u
             begin();
         }
         if (k >= 1 && k + 3 <= kf) {  // lines k .. k+3 whole: four steps with no tests
-            // Each line is stored after the next step's arithmetic, so the
-            // ring read it waits for completes behind that work.  The four
-            // parities alternate, so wcur and rcur are where they started.
-            uint64_t line = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 xs1024_step(a, b);
                 y += kWeylC;
                 const uint32_t m = weyl_mix(y);
                 const uint2 pv = make_uint2(a + m, b + m);
-                if (j > 0) __builtin_nontemporal_store(line, reinterpret_cast<uint64_t *>(o + 32 * (j - 1)));
-                const uint32_t wp = (j & 1) ? wcur ^ wflip : wcur, rp = (j & 1) ? rcur ^ rflip : rcur;
-                *reinterpret_cast<uint2 *>(rg + wp) = pv;
-                *reinterpret_cast<uint2 *>(rg + wp + 64) = pv;
+                *reinterpret_cast<uint2 *>(rg + wcur) = pv;
+                *reinterpret_cast<uint2 *>(rg + wcur + 64) = pv;
                 __builtin_amdgcn_wave_barrier();
-                const uint32_t w0 = rg[rp], w1 = rg[rp + 1];
+                const uint32_t w0 = rg[rcur], w1 = rg[rcur + 1];
                 __builtin_amdgcn_wave_barrier();
-                line = w0 | static_cast<uint64_t>(w1) << 32;
+                wcur ^= wflip;
+                rcur ^= rflip;
+                __builtin_nontemporal_store(w0 | static_cast<uint64_t>(w1) << 32, reinterpret_cast<uint64_t *>(o + 32 * j));
             }
-            __builtin_nontemporal_store(line, reinterpret_cast<uint64_t *>(o + 96));
             o += 128;
             k += 4;
             continue;  // k <= kf + 1 <= len: the chunk may end here
