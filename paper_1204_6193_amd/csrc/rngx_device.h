@@ -341,19 +341,25 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
 }
 
 // X ^= X << 329; X ^= X >> 347; X ^= X << 344  on the row-distributed state.
+// Each term a lane xors in is a funnel of two words of one other lane (5 to
+// the right or left), so that lane's own funnel is made first and moved by a
+// row shift: the shift then rides on the xor (a DPP operand of v_xor_b32)
+// instead of being a separate move of each input word.
 __device__ __forceinline__ void xs1024_step(uint32_t &a, uint32_t &b) {
     // << 329 = 10 words + 9 bits: W[i] ^= W[i+10] << 9 | W[i+11] >> 23
-    uint32_t p5a = from_lane_plus<5>(a), p5b = from_lane_plus<5>(b), p6a = from_lane_plus<6>(a);
-    a ^= funnel(p5a, p5b, 23);
-    b ^= funnel(p5b, p6a, 23);
+    uint32_t ta = funnel(a, b, 23), tb = funnel(b, from_lane_plus<1>(a), 23);
+    a ^= from_lane_plus<5>(ta);
+    b ^= from_lane_plus<5>(tb);
     // >> 347 = 10 words + 27 bits: W[i] ^= W[i-11] << 5 | W[i-10] >> 27
-    uint32_t m6b = from_lane_minus<6>(b), m5a = from_lane_minus<5>(a), m5b = from_lane_minus<5>(b);
-    a ^= funnel(m6b, m5a, 27);
-    b ^= funnel(m5a, m5b, 27);
+    ta = funnel(from_lane_minus<1>(b), a, 27);
+    tb = funnel(a, b, 27);
+    a ^= from_lane_minus<5>(ta);
+    b ^= from_lane_minus<5>(tb);
     // << 344 = 10 words + 24 bits: W[i] ^= W[i+10] << 24 | W[i+11] >> 8
-    p5a = from_lane_plus<5>(a); p5b = from_lane_plus<5>(b); p6a = from_lane_plus<6>(a);
-    a ^= funnel(p5a, p5b, 8);
-    b ^= funnel(p5b, p6a, 8);
+    ta = funnel(a, b, 8);
+    tb = funnel(b, from_lane_plus<1>(a), 8);
+    a ^= from_lane_plus<5>(ta);
+    b ^= from_lane_plus<5>(tb);
 }
 
 // Weyl output term y (I + R^16) with y = y0 + n c.
