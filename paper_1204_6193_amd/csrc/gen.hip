@@ -168,8 +168,8 @@ __global__ __launch_bounds__(kBlock) void k_fill_small(uint8_t *st, uint64_t S, 
 // per workgroup (S % V == 0; threads past the last stream stay in the loop
 // with their stores masked, since they take part in the barriers).
 template <class G, int MODE, int V, int BLK>
-__global__ __launch_bounds__(BLK, (HasNext8<G>::value && V == 2 && BLK == 1024) ? 8 : 1) void k_fill_paced(
-    uint8_t *st, uint64_t S, uint64_t count, void *out, uint32_t *ring) {
+__global__ __launch_bounds__(BLK) void k_fill_paced(uint8_t *st, uint64_t S, uint64_t count, void *out,
+                                                    uint32_t *ring) {
     const uint64_t s0 = (static_cast<uint64_t>(blockIdx.x) * BLK + threadIdx.x) * V;
     const bool live = s0 < S;
     G g[V];
