@@ -463,67 +463,6 @@ __device__ __forceinline__ uint32_t unit_place(uint32_t k, uint32_t L, uint32_t 
     return off;
 }
 
-// The LDS words a single-hit unit update reads: its run w, the runs above
-// and below, and the words left and right of it.
-template <int NB> struct UnitWords;
-template <> struct UnitWords<4> { uint32_t w, l, r, up, dn; };
-template <> struct UnitWords<8> { uint2 w, up, dn; uint32_t l, r; };
-
-template <int NB>
-__device__ __forceinline__ UnitWords<NB> read_words(const uint8_t *lds, uint32_t off, uint32_t P, uint32_t up_add,
-                                                    uint32_t dn_add) {
-    const uint32_t *l32 = reinterpret_cast<const uint32_t *>(lds + off);
-    UnitWords<NB> v;
-    if constexpr (NB == 4) {
-        v.w = l32[0];
-        v.l = l32[-1];
-        v.r = l32[1];
-        v.up = *reinterpret_cast<const uint32_t *>(lds + off - P + up_add);
-        v.dn = *reinterpret_cast<const uint32_t *>(lds + off + P + dn_add);
-    } else {
-        v.w = *reinterpret_cast<const uint2 *>(lds + off);
-        v.up = *reinterpret_cast<const uint2 *>(lds + off - P + up_add);
-        v.dn = *reinterpret_cast<const uint2 *>(lds + off + P + dn_add);
-        v.l = l32[-1];
-        v.r = l32[2];
-    }
-    return v;
-}
-
-// Single-hit colour-c update of the unit at `pl` from its words v (read by
-// read_words, possibly before the thread's previous unit was written back:
-// see the unit loop); stores and returns its new spins.
-template <class Unit, bool E>
-__device__ __forceinline__ uint64_t update_words(uint8_t *lds, uint32_t pl, int c, Unit &u, const Accept &A,
-                                                 uint32_t &esum, const StripArgs &g, uint64_t sweep,
-                                                 const UnitWords<Unit::kNB> &v) {
-    constexpr int NB = Unit::kNB;
-    const uint32_t off = pl & kOffMask;
-    const uint32_t sh0 = ((pl >> 31) ^ static_cast<uint32_t>(c)) << 3;  // bit offset of the first colour-c byte
-    const uint32_t f0 = 0xFEu << sh0, f1 = f0 << 16;                     // flip masks (+1 <-> -1)
-    uint32_t rr[NB / 2];
-    if constexpr (SweepCounter<Unit>::value) u.draw_at(rr, g, sweep, c);
-    else u.draw(rr);
-    if constexpr (NB == 4) {
-        const uint32_t m2 = mismatch2(v.w, v.l, v.r, v.up, v.dn);
-        const uint32_t g0 = decide<E>(m2, sh0, f0, rr[0], A, esum);
-        const uint32_t g1 = decide<E>(m2, sh0 + 16, f1, rr[1], A, esum);
-        const uint32_t nw = v.w ^ (g0 | g1);
-        *reinterpret_cast<uint32_t *>(lds + off) = nw;
-        return nw;
-    } else {
-        const uint32_t m2a = mismatch2(v.w.x, v.l, v.w.y, v.up.x, v.dn.x);
-        const uint32_t m2b = mismatch2(v.w.y, v.w.x, v.r, v.up.y, v.dn.y);
-        const uint32_t g0 = decide<E>(m2a, sh0, f0, rr[0], A, esum);
-        const uint32_t g1 = decide<E>(m2a, sh0 + 16, f1, rr[1], A, esum);
-        const uint32_t g2 = decide<E>(m2b, sh0, f0, rr[2], A, esum);
-        const uint32_t g3 = decide<E>(m2b, sh0 + 16, f1, rr[3], A, esum);
-        const uint2 nw = make_uint2(v.w.x ^ (g0 | g1), v.w.y ^ (g2 | g3));
-        *reinterpret_cast<uint2 *>(lds + off) = nw;
-        return (static_cast<uint64_t>(nw.y) << 32) | nw.x;
-    }
-}
-
 // Colour-c update of the unit at `pl` (place word, made opaque per pass);
 // returns its new spins.  The rows above and below are read at off - P +
 // up_add and off + P + dn_add (non-zero only to reach halo buffer 1).  The
@@ -579,7 +518,32 @@ __device__ __forceinline__ uint64_t update_unit(uint8_t *lds, uint32_t pl, uint3
             return (static_cast<uint64_t>(nw.y) << 32) | nw.x;
         }
     }
-    return update_words<Unit, E>(lds, pl, c, u, A, esum, g, sweep, read_words<NB>(lds, off, P, up_add, dn_add));
+    uint32_t rr[NB / 2];
+    if constexpr (SweepCounter<Unit>::value) u.draw_at(rr, g, sweep, c);
+    else u.draw(rr);
+    if constexpr (NB == 4) {
+        const uint32_t w = l32[0];
+        const uint32_t m2 = mismatch2(w, l32[-1], l32[1], *reinterpret_cast<const uint32_t *>(lds + off - P + up_add),
+                                      *reinterpret_cast<const uint32_t *>(lds + off + P + dn_add));
+        const uint32_t g0 = decide<E>(m2, sh0, f0, rr[0], A, esum);
+        const uint32_t g1 = decide<E>(m2, sh0 + 16, f1, rr[1], A, esum);
+        const uint32_t nw = w ^ (g0 | g1);
+        *reinterpret_cast<uint32_t *>(lds + off) = nw;
+        return nw;
+    } else {
+        const uint2 w = *reinterpret_cast<const uint2 *>(lds + off);
+        const uint2 up = *reinterpret_cast<const uint2 *>(lds + off - P + up_add);
+        const uint2 dn = *reinterpret_cast<const uint2 *>(lds + off + P + dn_add);
+        const uint32_t m2a = mismatch2(w.x, l32[-1], w.y, up.x, dn.x);
+        const uint32_t m2b = mismatch2(w.y, w.x, l32[2], up.y, dn.y);
+        const uint32_t g0 = decide<E>(m2a, sh0, f0, rr[0], A, esum);
+        const uint32_t g1 = decide<E>(m2a, sh0 + 16, f1, rr[1], A, esum);
+        const uint32_t g2 = decide<E>(m2b, sh0, f0, rr[2], A, esum);
+        const uint32_t g3 = decide<E>(m2b, sh0 + 16, f1, rr[3], A, esum);
+        const uint2 nw = make_uint2(w.x ^ (g0 | g1), w.y ^ (g2 | g3));
+        *reinterpret_cast<uint2 *>(lds + off) = nw;
+        return (static_cast<uint64_t>(nw.y) << 32) | nw.x;
+    }
 }
 
 // Ghost words of LDS rows [y0, y1) from the same rows' spins.
@@ -776,50 +740,21 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
         }
         uint32_t esum = 0;
         const uint32_t zero = *zero_word;
-        auto slot = [](int j) { return j == 0 ? SPT - 1 : j - 1; };  // bottom-row slot, top-row slot, then the rest
-        // `zero` is reloaded from LDS every pass, so the addresses derived
-        // from a place word cannot be hoisted out of the sweep loop and held
-        // per unit in registers.
-        auto place_of = [&](int i) -> uint32_t {
-            if constexpr (PLDS) return place_lds[i * nt + t];
-            else return place[i] + zero;
-        };
-        // Single-hit: the next unit's words are read before this unit is
-        // updated, so their LDS latency passes during this unit's work.  A
-        // word this update writes can be among them (the next unit's row is
-        // often the next row), but the update changes only bytes of colour c,
-        // and no colour-c site has a colour-c neighbour: the next unit's
-        // decisions read none of those bytes.
-        UnitWords<NB> nwords{};
-        uint32_t npl = 0;
-        auto fetch = [&](int j) {
-            const int i = slot(j);
-            if (t + i * nt < a.units) {
-                const bool bslot = !early || j <= 1;
-                npl = place_of(i);
-                const bool top = bslot && ((npl >> 27) & 1), bot = bslot && ((npl >> 28) & 1);
-                nwords = read_words<NB>(lds, npl & kOffMask, P, top ? up_add : 0u, bot ? dn_add : 0u);
-            }
-        };
-        if constexpr (!MH) fetch(0);
 #pragma unroll
         for (int j = 0; j < SPT; ++j) {
-            const int i = slot(j);
+            const int i = j == 0 ? SPT - 1 : j - 1;  // bottom-row slot, top-row slot, then the rest
             const uint32_t k = t + i * nt;
             const bool bslot = !early || j <= 1;      // may hold top- or bottom-row units
-            const UnitWords<NB> words = nwords;
-            const uint32_t wpl = npl;
-            if constexpr (!MH)
-                if (j + 1 < SPT) fetch(j + 1);
             if (k < a.units) {
-                const uint32_t pl = MH ? place_of(i) : wpl;
+                // `zero` is reloaded from LDS every pass, so the addresses
+                // derived from `pl` cannot be hoisted out of the sweep loop
+                // and held per unit in registers.
+                uint32_t pl;
+                if constexpr (PLDS) pl = place_lds[i * nt + t];
+                else pl = place[i] + zero;
                 const bool top = bslot && ((pl >> 27) & 1), bot = bslot && ((pl >> 28) & 1);
-                uint64_t nw;
-                if constexpr (MH)
-                    nw = update_unit<Unit, E, MH>(lds, pl, P, top ? up_add : 0u, bot ? dn_add : 0u, c, u[i], A, esum,
-                                                  a.hits, a, sweep);
-                else
-                    nw = update_words<Unit, E>(lds, pl, c, u[i], A, esum, a, sweep, words);
+                const uint64_t nw = update_unit<Unit, E, MH>(lds, pl, P, top ? up_add : 0u, bot ? dn_add : 0u, c, u[i], A, esum,
+                                                                   a.hits, a, sweep);
                 const uint32_t off = pl & kOffMask;
                 const uint32_t yrow = top ? 1 : bot ? R : 0;   // only used for boundary units
                 const uint32_t x0 = off - kPad - yrow * P;
