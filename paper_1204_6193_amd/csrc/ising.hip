@@ -706,26 +706,48 @@ __device__ __forceinline__ void strip_body(const StripArgs &a, uint32_t r, uint8
             constexpr uint32_t NR = (1024 + RUN - 1) / RUN;
             const uint32_t n_inst = a.units / 1024;
             const uint32_t wave = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63, n_waves = nt >> 6;
+            constexpr uint32_t kLast = 1024 - (NR - 1) * RUN;
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
+                if (n_inst >= n_waves) {
+                    // as many instances as waves or more: wave w makes the
+                    // runs of instances w, w + waves, ... in turn; a run
+                    // reads only earlier runs of its own instance, written
+                    // by the same wave, whose LDS accesses complete in order
+                    for (uint32_t i = wave; i < n_inst; i += n_waves) {
+                        uint32_t *rg = rings + i * RB;
 #pragma unroll
-                for (uint32_t rr = 0; rr < NR; ++rr) {
-                    constexpr uint32_t kLast = 1024 - (NR - 1) * RUN;
-                    const uint32_t len = rr + 1 < NR ? RUN : kLast;
-                    const uint32_t nblk = (len + 63) / 64;  // 64-value blocks of the run per instance
-                    const uint32_t v0 = lq + rr * RUN;
-                    // block b = (instance i, block m) goes to wave b mod (waves):
-                    // i and m are wave-uniform, lane l makes value 64 m + l
-                    for (uint32_t b = wave; b < n_inst * nblk; b += n_waves) {
-                        const uint32_t i = b / nblk, m = b - i * nblk;
-                        const uint32_t j = 64 * m + lane;
-                        if (j < len) {
-                            uint32_t *rg = rings + i * RB;
-                            const uint32_t v = v0 + j;
-                            rg[v & (RB - 1)] = rg[(v - LR) & (RB - 1)] + rg[(v - LS) & (RB - 1)];
+                        for (uint32_t rr = 0; rr < NR; ++rr) {
+                            const uint32_t len = rr + 1 < NR ? RUN : kLast;
+                            const uint32_t v0 = lq + rr * RUN;
+                            for (uint32_t j = lane; j < len; j += 64) {
+                                const uint32_t v = v0 + j;
+                                rg[v & (RB - 1)] = rg[(v - LR) & (RB - 1)] + rg[(v - LS) & (RB - 1)];
+                            }
+                            __builtin_amdgcn_wave_barrier();
                         }
                     }
                     __syncthreads();
+                } else {
+#pragma unroll
+                    for (uint32_t rr = 0; rr < NR; ++rr) {
+                        const uint32_t len = rr + 1 < NR ? RUN : kLast;
+                        const uint32_t nblk = (len + 63) / 64;  // 64-value blocks of the run per instance
+                        const uint32_t v0 = lq + rr * RUN;
+                        // block b = (instance i, block m) goes to wave b mod
+                        // (waves): i and m are wave-uniform, lane l makes
+                        // value 64 m + l
+                        for (uint32_t b = wave; b < n_inst * nblk; b += n_waves) {
+                            const uint32_t i = b / nblk, m = b - i * nblk;
+                            const uint32_t j = 64 * m + lane;
+                            if (j < len) {
+                                uint32_t *rg = rings + i * RB;
+                                const uint32_t v = v0 + j;
+                                rg[v & (RB - 1)] = rg[(v - LR) & (RB - 1)] + rg[(v - LS) & (RB - 1)];
+                            }
+                        }
+                        __syncthreads();
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < SPT; ++i)  // slot i: instance i, stream t (1024 threads)
