@@ -546,35 +546,42 @@ def test_substream_lcg32_fails_the_ising_test(rngx):
     assert abs(z["lcg32"][0]) < 4 and abs(z["lcg32"][1]) < 4
 
 
-def test_xs1024w_strips_with_uneven_step_counts(rngx, orc):
+@pytest.mark.parametrize("L", [512, 1008])
+def test_xs1024w_strips_with_uneven_step_counts(rngx, orc, L):
     """The strip kernel derives the XS1024W Weyl word of a pass from the
     call's start when every instance of a strip has taken the same number of
     steps, and holds and steps it per unit otherwise: step counts that
     differ in the lower half of the lattice only (its strips take the
     per-unit form, the others the shared one), then all equal again at a
-    count past 2^32 -- bit-exact with the oracle every time."""
-    L = 512
-    print("case xs1024w step counts", flush=True)
-    lat = rngx.ising_create(L, "xs1024w", 4)
-    assert rngx.ising_info(lat)["strips"] > 1
-    g = rngx.ising_rng(lat)
-    sp, st = orc.ising_create(L, "xs1024w", 4)
-    S = L * L // 4
-    G = S // 32
-    n = st[4 * S:4 * S + 8 * G].view(np.uint64)
-    for rep in range(3):
-        if rep == 1:  # uneven in the lower half
-            n[G // 2:] += np.arange(G - G // 2, dtype=np.uint64) % np.uint64(5)
-            rngx.rng_set_state(g, st)
-        if rep == 2:
-            n[:] = np.uint64((1 << 32) + 12345)  # equal again
-            rngx.rng_set_state(g, st)
-        tr = torch.zeros(3, dtype=torch.int32, device="cuda")
-        rngx.ising_sweep(lat, 0.42, 3, tr)
-        want = orc.ising_sweeps(L, "xs1024w", 0.42, st, sp, 3)
-        assert np.array_equal(tr.cpu().numpy(), want), rep
-        assert np.array_equal(rngx.ising_get_spins(lat).ravel(), sp), rep
-        assert np.array_equal(rngx.rng_get_state(g), st), rep
+    count past 2^32 -- bit-exact with the oracle every time.  At L = 1008
+    (126 units of 8 sites per row, every strip plan in turn) instances
+    straddle rows and, for strips whose height is not a multiple of 8, strips."""
+    print(f"case xs1024w step counts L={L}", flush=True)
+    probe = rngx.ising_create(L, "xs1024w", 4)
+    plans = [p for p in rngx.ising_plans(probe) if p > 1] if L == 1008 else [rngx.ising_info(probe)["strips"]]
+    assert plans and plans[0] > 1
+    for strips in plans:
+        print(f"case xs1024w step counts L={L} strips={strips}", flush=True)
+        lat = rngx.ising_create(L, "xs1024w", 4)
+        rngx.ising_set_plan(lat, strips)
+        g = rngx.ising_rng(lat)
+        sp, st = orc.ising_create(L, "xs1024w", 4)
+        S = L * L // 4
+        G = S // 32
+        n = st[4 * S:4 * S + 8 * G].view(np.uint64)
+        for rep in range(3):
+            if rep == 1:  # uneven in the lower half
+                n[G // 2:] += np.arange(G - G // 2, dtype=np.uint64) % np.uint64(5)
+                rngx.rng_set_state(g, st)
+            if rep == 2:
+                n[:] = np.uint64((1 << 32) + 12345)  # equal again
+                rngx.rng_set_state(g, st)
+            tr = torch.zeros(3, dtype=torch.int32, device="cuda")
+            rngx.ising_sweep(lat, 0.42, 3, tr)
+            want = orc.ising_sweeps(L, "xs1024w", 0.42, st, sp, 3)
+            assert np.array_equal(tr.cpu().numpy(), want), (strips, rep)
+            assert np.array_equal(rngx.ising_get_spins(lat).ravel(), sp), (strips, rep)
+            assert np.array_equal(rngx.rng_get_state(g), st), (strips, rep)
 
 
 @pytest.mark.parametrize("kind", ["philox4x32_10", "philox4x32_7"])
